@@ -1,0 +1,485 @@
+/*
+ * CPU ORACLE — test infrastructure only.
+ *
+ * Plain, slow, single-threaded C that states what the GPU merge sort must
+ * compute.  Only the test suite, the smoke check and the CPU-baseline leg of
+ * the benchmark load this library; the product path never does.  Nothing in
+ * here is shared with the HIP sources: the networks are generated from their
+ * textbook definition at run time, comparisons use the plain dtype order, and
+ * every sort is the paper's recursive algorithm written out.
+ *
+ * Paper: Aly, Jensen, ElAarag, "Improving Merge Sort and Quick Sort
+ * Performance by Utilizing AlphaDev's Sorting Networks as Base Cases",
+ * ACMSE 2025 (arXiv 2503.05934).
+ *
+ *   - orc_sort(ORC_MS, ...)      Algorithm 1 (OptimizedMergeSort); with an
+ *                                empty network set it is the classical merge
+ *                                sort the paper measures against (Sec. 3,
+ *                                Eq. 1).
+ *   - orc_sort(ORC_QS, ...)      Algorithm 2 (OptimizedQuickSort) with
+ *                                median-of-three pivots and Hoare partitioning
+ *                                (Sec. 3); empty set = classical quick sort.
+ *   - orc_config_mask            the network sets of Table 3.
+ *   - orc_network                the fixed sorting networks for sizes 2..8
+ *                                (the role AlphaDev's networks play, Sec. 1/3),
+ *                                built here from Batcher's odd-even merge sort.
+ *   - orc_segmented_sort         the above per CSR segment.
+ *   - orc_gather_backward        gradient of a sort: grad_in[perm[i]] =
+ *                                grad_out[i] (not in the paper; definition).
+ *
+ * Readings of the paper taken here (the paper is silent on them):
+ *   - key types: uint32, int32, float32; ascending order.
+ *   - float32 order: IEEE "<", so -0 and +0 tie; every NaN sorts after +inf
+ *     and all NaNs tie with each other.
+ *   - Merge takes from the left run on ties (stable).
+ *   - "stable" sorts compare (key, original position) so that a network, which
+ *     is not stable on keys alone, still yields the stable order.
+ *   - MedianOfThree orders a[low], a[mid], a[high] in place and returns mid;
+ *     HoarePartition is Hoare's 1962 scheme with the pivot value taken there.
+ *   - VarSortK (Table 3) handles every size up to K, so its set is {2..K}.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_U32 0
+#define ORC_I32 1
+#define ORC_F32 2
+
+#define ORC_MS 0 /* Algorithm 1 (merge sort) */
+#define ORC_QS 1 /* Algorithm 2 (quick sort) */
+
+#define ORC_MAX_NET 8
+#define ORC_MAX_CMP 32
+
+/* One element being sorted: the key bits, its payload, and its original
+ * position (used only to break ties when a stable order is asked for). */
+typedef struct {
+    uint32_t key;
+    uint32_t val;
+    uint32_t pos;
+} rec_t;
+
+typedef struct {
+    int dtype;
+    int stable;
+} order_t;
+
+/* ---------------------------------------------------------------- order --- */
+
+static float bits_to_f32(uint32_t b) {
+    float f;
+    memcpy(&f, &b, sizeof f);
+    return f;
+}
+
+/* a < b in the plain order of the dtype. */
+static int key_less(int dtype, uint32_t a, uint32_t b) {
+    if (dtype == ORC_U32) return a < b;
+    if (dtype == ORC_I32) return (int32_t)a < (int32_t)b;
+    {
+        float fa = bits_to_f32(a), fb = bits_to_f32(b);
+        if (isnan(fa)) return 0;         /* NaN is never below anything */
+        if (isnan(fb)) return 1;         /* every number is below NaN    */
+        return fa < fb;                  /* IEEE: -0 < +0 is false       */
+    }
+}
+
+static int rec_less(const order_t* o, const rec_t* a, const rec_t* b) {
+    if (key_less(o->dtype, a->key, b->key)) return 1;
+    if (key_less(o->dtype, b->key, a->key)) return 0;
+    return o->stable && a->pos < b->pos;
+}
+
+/* ------------------------------------------------------------- networks --- */
+/*
+ * Batcher's odd-even merge sort for 8 wires, from its recursive definition
+ * (Batcher 1968; Knuth, TAOCP vol. 3, Sec. 5.3.4).  The network for n < 8
+ * wires keeps the comparators whose wires are both below n (the others would
+ * only ever see +infinity on their upper wire), and then drops any comparator
+ * that never exchanges for any of the 2^n zero-one inputs.
+ */
+static int g_net_ready = 0;
+static int g_net_len[ORC_MAX_NET + 1];
+static int g_net[ORC_MAX_NET + 1][ORC_MAX_CMP][2];
+
+static int g_full_len;
+static int g_full[ORC_MAX_CMP][2];
+
+static void batcher_add(int i, int j) {
+    g_full[g_full_len][0] = i;
+    g_full[g_full_len][1] = j;
+    g_full_len++;
+}
+
+/* merge the two sorted halves of wires lo, lo+r, lo+2r, ... (n wires) */
+static void batcher_merge(int lo, int n, int r) {
+    int step = r * 2;
+    if (step < n) {
+        batcher_merge(lo, n, step);       /* even subsequence */
+        batcher_merge(lo + r, n, step);   /* odd subsequence  */
+        for (int i = lo + r; i + r < lo + n; i += step) batcher_add(i, i + r);
+    } else {
+        batcher_add(lo, lo + r);
+    }
+}
+
+static void batcher_sort(int lo, int n) {
+    if (n > 1) {
+        int m = n / 2;
+        batcher_sort(lo, m);
+        batcher_sort(lo + m, m);
+        batcher_merge(lo, n, 1);
+    }
+}
+
+static void build_networks(void) {
+    if (g_net_ready) return;
+    g_full_len = 0;
+    batcher_sort(0, ORC_MAX_NET);
+    for (int n = 0; n <= ORC_MAX_NET; n++) {
+        int kept[ORC_MAX_CMP][2], nk = 0;
+        for (int c = 0; c < g_full_len; c++)
+            if (g_full[c][1] < n) {
+                kept[nk][0] = g_full[c][0];
+                kept[nk][1] = g_full[c][1];
+                nk++;
+            }
+        /* a comparator is useful if it exchanges for some 0-1 input */
+        int useful[ORC_MAX_CMP] = {0};
+        for (uint32_t in = 0; in < (1u << n); in++) {
+            int w[ORC_MAX_NET];
+            for (int b = 0; b < n; b++) w[b] = (in >> b) & 1;
+            for (int c = 0; c < nk; c++) {
+                int i = kept[c][0], j = kept[c][1];
+                if (w[j] < w[i]) {
+                    int t = w[i];
+                    w[i] = w[j];
+                    w[j] = t;
+                    useful[c] = 1;
+                }
+            }
+        }
+        g_net_len[n] = 0;
+        for (int c = 0; c < nk; c++)
+            if (useful[c]) {
+                g_net[n][g_net_len[n]][0] = kept[c][0];
+                g_net[n][g_net_len[n]][1] = kept[c][1];
+                g_net_len[n]++;
+            }
+    }
+    g_net_ready = 1;
+}
+
+/* Writes the n-wire network as (i, j) pairs, i < j, in application order.
+ * Returns the number of comparators, or -1 for n outside 0..8. */
+int orc_network(int n, int* pairs_out) {
+    if (n < 0 || n > ORC_MAX_NET) return -1;
+    build_networks();
+    for (int c = 0; c < g_net_len[n]; c++) {
+        pairs_out[2 * c] = g_net[n][c][0];
+        pairs_out[2 * c + 1] = g_net[n][c][1];
+    }
+    return g_net_len[n];
+}
+
+/* ApplySortingNetwork (Algorithm 1/2): sorts a[0..n-1] with the n-network. */
+static void apply_network(const order_t* o, rec_t* a, int n) {
+    build_networks();
+    for (int c = 0; c < g_net_len[n]; c++) {
+        rec_t* x = &a[g_net[n][c][0]];
+        rec_t* y = &a[g_net[n][c][1]];
+        if (rec_less(o, y, x)) {
+            rec_t t = *x;
+            *x = *y;
+            *y = t;
+        }
+    }
+}
+
+/* Applies the n-network to each of `count` consecutive n-tuples of keys.
+ * perm (optional) receives, per tuple, the tuple-local position each output
+ * came from.  Used to test the networks exhaustively. */
+int orc_apply_network_batch(int n, int dtype, int stable, uint32_t* keys,
+                            uint32_t* perm, int64_t count) {
+    if (n < 0 || n > ORC_MAX_NET || count < 0) return -1;
+    order_t o = {dtype, stable};
+    rec_t r[ORC_MAX_NET];
+    for (int64_t t = 0; t < count; t++) {
+        for (int i = 0; i < n; i++) {
+            r[i].key = keys[t * n + i];
+            r[i].val = (uint32_t)i;
+            r[i].pos = (uint32_t)i;
+        }
+        apply_network(&o, r, n);
+        for (int i = 0; i < n; i++) {
+            keys[t * n + i] = r[i].key;
+            if (perm) perm[t * n + i] = r[i].val;
+        }
+    }
+    return 0;
+}
+
+/* --------------------------------------------------------- configurations */
+/* Table 3: which network sizes each configuration enables (bit k = size k). */
+int64_t orc_config_mask(const char* name) {
+    static const struct {
+        const char* name;
+        uint32_t mask;
+    } table[] = {
+        {"PowerOf2", (1u << 4) | (1u << 8)},
+        {"Even", (1u << 4) | (1u << 6) | (1u << 8)},
+        {"Odd", (1u << 3) | (1u << 5) | (1u << 7)},
+        {"3", (1u << 3)},
+        {"3To4", (1u << 3) | (1u << 4)},
+        {"3To5", (1u << 3) | (1u << 4) | (1u << 5)},
+        {"3To8", 0x1f8u},
+        {"6To8", (1u << 6) | (1u << 7) | (1u << 8)},
+        {"VarSort3", 0x0cu},
+        {"VarSort4", 0x1cu},
+        {"VarSort5", 0x3cu},
+        {"Classical", 0u},
+    };
+    for (size_t i = 0; i < sizeof table / sizeof table[0]; i++)
+        if (strcmp(name, table[i].name) == 0) return table[i].mask;
+    return -1;
+}
+
+/* ----------------------------------------------------------- merge sort --- */
+
+typedef struct {
+    order_t ord;
+    uint32_t netmask;
+    rec_t* scratch;
+    int64_t* leaf_hist; /* optional: elements handled by each network size */
+} ms_ctx;
+
+/* Merge(array, left, mid, right): the sorted runs a[left..mid] and
+ * a[mid+1..right] become one sorted run; the left run wins ties. */
+static void merge_runs(ms_ctx* c, rec_t* a, int64_t left, int64_t mid, int64_t right) {
+    int64_t i = left, j = mid + 1, k = 0;
+    rec_t* s = c->scratch;
+    while (i <= mid && j <= right) {
+        if (rec_less(&c->ord, &a[j], &a[i]))
+            s[k++] = a[j++];
+        else
+            s[k++] = a[i++];
+    }
+    while (i <= mid) s[k++] = a[i++];
+    while (j <= right) s[k++] = a[j++];
+    memcpy(&a[left], s, (size_t)k * sizeof(rec_t));
+}
+
+/* Algorithm 1, OptimizedMergeSort(array, left, right). */
+static void optimized_merge_sort(ms_ctx* c, rec_t* a, int64_t left, int64_t right) {
+    int64_t size = right - left + 1;
+    if (size >= 0 && size <= ORC_MAX_NET && (c->netmask >> size) & 1u) {
+        apply_network(&c->ord, &a[left], (int)size);
+        if (c->leaf_hist) c->leaf_hist[size] += size;
+        return;
+    }
+    if (left < right) {
+        int64_t mid = left + (right - left) / 2;
+        optimized_merge_sort(c, a, left, mid);
+        optimized_merge_sort(c, a, mid + 1, right);
+        merge_runs(c, a, left, mid, right);
+    }
+}
+
+/* ----------------------------------------------------------- quick sort --- */
+
+static void swap_rec(rec_t* x, rec_t* y) {
+    rec_t t = *x;
+    *x = *y;
+    *y = t;
+}
+
+/* MedianOfThree(array, low, high): puts a[low] <= a[mid] <= a[high] and
+ * returns mid, whose element is the pivot. */
+static int64_t median_of_three(const order_t* o, rec_t* a, int64_t low, int64_t high) {
+    int64_t mid = low + (high - low) / 2;
+    if (rec_less(o, &a[mid], &a[low])) swap_rec(&a[mid], &a[low]);
+    if (rec_less(o, &a[high], &a[low])) swap_rec(&a[high], &a[low]);
+    if (rec_less(o, &a[high], &a[mid])) swap_rec(&a[high], &a[mid]);
+    return mid;
+}
+
+/* HoarePartition(array, low, high, pivotIndex): Hoare's scheme.  Returns j
+ * with low <= j < high such that a[low..j] <= pivot <= a[j+1..high]. */
+static int64_t hoare_partition(const order_t* o, rec_t* a, int64_t low, int64_t high,
+                               int64_t pivot_index) {
+    rec_t pivot = a[pivot_index];
+    int64_t i = low - 1, j = high + 1;
+    for (;;) {
+        do i++; while (rec_less(o, &a[i], &pivot));
+        do j--; while (rec_less(o, &pivot, &a[j]));
+        if (i >= j) return j;
+        swap_rec(&a[i], &a[j]);
+    }
+}
+
+/* Algorithm 2, OptimizedQuickSort(array, low, high). */
+static void optimized_quick_sort(const order_t* o, uint32_t netmask, rec_t* a,
+                                 int64_t low, int64_t high) {
+    int64_t size = high - low + 1;
+    if (size >= 0 && size <= ORC_MAX_NET && (netmask >> size) & 1u) {
+        apply_network(o, &a[low], (int)size);
+        return;
+    }
+    if (low < high) {
+        int64_t pivot_index = median_of_three(o, a, low, high);
+        int64_t p = hoare_partition(o, a, low, high, pivot_index);
+        optimized_quick_sort(o, netmask, a, low, p);
+        optimized_quick_sort(o, netmask, a, p + 1, high);
+    }
+}
+
+/* ------------------------------------------------------------- drivers --- */
+
+static int sort_records(int algo, const order_t* o, uint32_t netmask, rec_t* r,
+                        int64_t n, rec_t* scratch, int64_t* leaf_hist) {
+    if (n <= 0) return 0;
+    if (algo == ORC_MS) {
+        ms_ctx c = {*o, netmask, scratch, leaf_hist};
+        optimized_merge_sort(&c, r, 0, n - 1);
+    } else {
+        optimized_quick_sort(o, netmask, r, 0, n - 1);
+    }
+    return 0;
+}
+
+static int check_args(int algo, int dtype, uint32_t netmask) {
+    if (algo != ORC_MS && algo != ORC_QS) return -4;
+    if (dtype != ORC_U32 && dtype != ORC_I32 && dtype != ORC_F32) return -3;
+    if (netmask & ~0x1feu) return -4; /* sizes 1..8 only */
+    return 0;
+}
+
+/*
+ * Sorts keys[0..n-1] (bits of dtype) in place, ascending.  If vals is not
+ * NULL it is permuted along with the keys.  If perm is not NULL it receives
+ * the original position of each output element.  stable != 0 orders equal
+ * keys by original position.  Returns 0, or a negative code on bad input.
+ */
+int orc_sort(int algo, int dtype, uint32_t netmask, int stable, uint32_t* keys,
+             uint32_t* vals, uint32_t* perm, int64_t n) {
+    int rc = check_args(algo, dtype, netmask);
+    if (rc) return rc;
+    if (n < 0 || n > 0xffffffffLL) return -2;
+    if (n == 0) return 0;
+    if (!keys) return -1;
+    order_t o = {dtype, stable};
+    rec_t* r = (rec_t*)malloc((size_t)n * sizeof(rec_t));
+    rec_t* s = algo == ORC_MS ? (rec_t*)malloc((size_t)n * sizeof(rec_t)) : NULL;
+    if (!r || (algo == ORC_MS && !s)) {
+        free(r);
+        free(s);
+        return -7;
+    }
+    for (int64_t i = 0; i < n; i++) {
+        r[i].key = keys[i];
+        r[i].val = vals ? vals[i] : (uint32_t)i;
+        r[i].pos = (uint32_t)i;
+    }
+    sort_records(algo, &o, netmask, r, n, s, NULL);
+    for (int64_t i = 0; i < n; i++) {
+        keys[i] = r[i].key;
+        if (vals) vals[i] = r[i].val;
+        if (perm) perm[i] = r[i].pos;
+    }
+    free(r);
+    free(s);
+    return 0;
+}
+
+/*
+ * Per-segment sort.  Segment s is keys[offsets[s] .. offsets[s+1]-1].
+ * perm (optional) receives the segment-local original position of each
+ * output element.  offsets must start at 0, never decrease and end at the
+ * total length; -2 otherwise.
+ */
+int orc_segmented_sort(int algo, int dtype, uint32_t netmask, int stable,
+                       uint32_t* keys, uint32_t* vals, uint32_t* perm,
+                       const uint32_t* offsets, int64_t num_segments) {
+    int rc = check_args(algo, dtype, netmask);
+    if (rc) return rc;
+    if (num_segments < 0) return -2;
+    if (num_segments == 0) return 0;
+    if (!offsets) return -1;
+    if (offsets[0] != 0) return -2;
+    int64_t longest = 0;
+    for (int64_t s = 0; s < num_segments; s++) {
+        if (offsets[s + 1] < offsets[s]) return -2;
+        int64_t len = (int64_t)offsets[s + 1] - offsets[s];
+        if (len > longest) longest = len;
+    }
+    if (longest == 0) return 0;
+    if (!keys) return -1;
+    order_t o = {dtype, stable};
+    rec_t* r = (rec_t*)malloc((size_t)longest * sizeof(rec_t));
+    rec_t* sc = (rec_t*)malloc((size_t)longest * sizeof(rec_t));
+    if (!r || !sc) {
+        free(r);
+        free(sc);
+        return -7;
+    }
+    for (int64_t s = 0; s < num_segments; s++) {
+        int64_t b = offsets[s], len = (int64_t)offsets[s + 1] - offsets[s];
+        for (int64_t i = 0; i < len; i++) {
+            r[i].key = keys[b + i];
+            r[i].val = vals ? vals[b + i] : (uint32_t)i;
+            r[i].pos = (uint32_t)i;
+        }
+        sort_records(algo, &o, netmask, r, len, sc, NULL);
+        for (int64_t i = 0; i < len; i++) {
+            keys[b + i] = r[i].key;
+            if (vals) vals[b + i] = r[i].val;
+            if (perm) perm[b + i] = r[i].pos;
+        }
+    }
+    free(r);
+    free(sc);
+    return 0;
+}
+
+/*
+ * Counts, for Algorithm 1 on an array of n elements, how many elements end
+ * in a network of each size (hist[0..8]).  Shows which leaves a
+ * configuration reaches for a given n; the data do not matter.
+ */
+int orc_alg1_leaf_histogram(int64_t n, uint32_t netmask, int64_t* hist) {
+    if (n < 0 || !hist) return -2;
+    for (int k = 0; k <= ORC_MAX_NET; k++) hist[k] = 0;
+    if (n == 0) return 0;
+    order_t o = {ORC_U32, 0};
+    rec_t* r = (rec_t*)calloc((size_t)n, sizeof(rec_t));
+    rec_t* s = (rec_t*)malloc((size_t)n * sizeof(rec_t));
+    if (!r || !s) {
+        free(r);
+        free(s);
+        return -7;
+    }
+    sort_records(ORC_MS, &o, netmask, r, n, s, hist);
+    free(r);
+    free(s);
+    return 0;
+}
+
+/*
+ * Backward of y = sort(x) along each row: y[r][i] = x[r][perm[r][i]], so
+ * d<g, y>/dx[r][perm[r][i]] = g[r][i].  Entries of perm outside [0, cols)
+ * make the call fail with -2 before anything is written.
+ */
+int orc_gather_backward(const float* grad_out, const int32_t* perm, float* grad_in,
+                        int64_t rows, int64_t cols) {
+    if (rows < 0 || cols < 0) return -2;
+    if (rows * cols == 0) return 0;
+    if (!grad_out || !perm || !grad_in) return -1;
+    for (int64_t e = 0; e < rows * cols; e++)
+        if (perm[e] < 0 || perm[e] >= cols) return -2;
+    for (int64_t r = 0; r < rows; r++)
+        for (int64_t i = 0; i < cols; i++)
+            grad_in[r * cols + perm[r * cols + i]] = grad_out[r * cols + i];
+    return 0;
+}

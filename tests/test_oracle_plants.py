@@ -1,0 +1,76 @@
+"""Plausible mistakes planted in a copy of the oracle must fail some pin.
+
+Each case edits one spot of oracle.c (a dropped term, a wrong sign or index,
+swapped operands), builds the copy with gcc and runs all pins on it in a child
+process.  This shows the pins would catch such a mistake in the oracle itself.
+"""
+import os
+import subprocess
+import sys
+
+import pytest
+
+import oracle
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(os.path.dirname(HERE), "oracle", "oracle.c")
+
+PLANTS = {
+    "network_comparator_reversed": (
+        "        if (rec_less(o, y, x)) {\n            rec_t t = *x;",
+        "        if (rec_less(o, x, y)) {\n            rec_t t = *x;"),
+    "batcher_merge_skips_last_comparator": (
+        "for (int i = lo + r; i + r < lo + n; i += step)",
+        "for (int i = lo + r; i + r < lo + n - step; i += step)"),
+    "redundant_comparators_kept": (
+        "            if (useful[c]) {", "            if (1) {"),
+    "merge_prefers_right_on_ties": (
+        "        if (rec_less(&c->ord, &a[j], &a[i]))",
+        "        if (!rec_less(&c->ord, &a[i], &a[j]))"),
+    "merge_drops_left_tail": (
+        "    while (i <= mid) s[k++] = a[i++];\n", "\n"),
+    "merge_split_off_by_one": (
+        "        optimized_merge_sort(c, a, mid + 1, right);\n        merge_runs(c, a, left, mid, right);",
+        "        optimized_merge_sort(c, a, mid + 1, right);\n        merge_runs(c, a, left, mid - (mid > left), right);"),
+    "quick_sort_skips_element": (
+        "        optimized_quick_sort(o, netmask, a, p + 1, high);",
+        "        optimized_quick_sort(o, netmask, a, p + 2, high);"),
+    "tie_break_reversed": (
+        "    return o->stable && a->pos < b->pos;", "    return o->stable && a->pos > b->pos;"),
+    "int32_compared_unsigned": (
+        "    if (dtype == ORC_I32) return (int32_t)a < (int32_t)b;",
+        "    if (dtype == ORC_I32) return a < b;"),
+    "f32_compared_as_bits": (
+        "        return fa < fb;                  /* IEEE: -0 < +0 is false       */",
+        "        return a < b;"),
+    "f32_nan_first": (
+        "        if (isnan(fb)) return 1;", "        if (isnan(fb)) return 0;"),
+    "table3_even_missing_6": (
+        '{"Even", (1u << 4) | (1u << 6) | (1u << 8)}', '{"Even", (1u << 4) | (1u << 8)}'),
+    "network_dispatch_off_by_one": (
+        "    if (size >= 0 && size <= ORC_MAX_NET && (c->netmask >> size) & 1u) {\n        apply_network(&c->ord, &a[left], (int)size);",
+        "    if (size >= 1 && size <= ORC_MAX_NET && (c->netmask >> size) & 1u) {\n        apply_network(&c->ord, &a[left], (int)size - 1);"),
+    "backward_scatters_the_wrong_way": (
+        "            grad_in[r * cols + perm[r * cols + i]] = grad_out[r * cols + i];",
+        "            grad_in[r * cols + i] = grad_out[r * cols + perm[r * cols + i]];"),
+}
+
+
+def test_clean_oracle_passes_runner(tmp_path):
+    so = oracle.build(SRC, str(tmp_path / "clean.so"))
+    r = subprocess.run([sys.executable, os.path.join(HERE, "plant_runner.py"), so],
+                       capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0, r.stdout + r.stderr
+
+
+@pytest.mark.parametrize("name", sorted(PLANTS))
+def test_planted_mistake_is_caught(tmp_path, name):
+    old, new = PLANTS[name]
+    text = open(SRC).read()
+    assert text.count(old) == 1, f"plant site for {name} not found exactly once"
+    src = tmp_path / "planted.c"
+    src.write_text(text.replace(old, new))
+    so = oracle.build(str(src), str(tmp_path / "planted.so"))
+    r = subprocess.run([sys.executable, os.path.join(HERE, "plant_runner.py"), so],
+                       capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, f"{name} passed every pin:\n{r.stdout}{r.stderr}"
