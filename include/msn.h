@@ -1,0 +1,200 @@
+/*
+ * msn.h — C ABI of libmsn: a GPU merge sort whose base cases are fixed
+ * sorting networks, for AMD Instinct MI355X (gfx950).
+ *
+ * Method: Aly, Jensen, ElAarag, "Improving Merge Sort and Quick Sort
+ * Performance by Utilizing AlphaDev's Sorting Networks as Base Cases",
+ * ACMSE 2025 (arXiv 2503.05934), Sec. 3, Algorithm 1: a merge sort that
+ * hands every subarray whose size matches a configured network size to that
+ * network instead of recursing further; Table 3 lists the network sets, and
+ * the 6-to-8 set is the paper's recommended one.  The problem each call
+ * solves is Algorithm 1's: rearrange an array into ascending order.  Here the
+ * recursion runs bottom-up: each GPU lane first applies one network to a
+ * fixed group of keys (8 keys for the 6-to-8 set, 4 for 3-to-5), and merges
+ * follow.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Data pointers (keys, values, offsets, permutations, workspace) are device
+ *    memory owned by the caller.  The library never allocates, frees or
+ *    synchronises and never reads device data on the host; all work is
+ *    enqueued on `stream` (a hipStream_t; NULL = the default stream) and the
+ *    call returns without waiting.  This makes every call safe to record into
+ *    a HIP graph.
+ *  - Keys are 32-bit: MSN_U32 (unsigned), MSN_I32 (two's complement) or
+ *    MSN_F32 (IEEE binary32).  Order is ascending.  For MSN_F32, -0.0 and
+ *    +0.0 compare equal, every NaN sorts after +inf and all NaNs compare
+ *    equal; outputs are bit copies of inputs, so -0.0 and NaN payloads
+ *    survive.  Because distinct float bit patterns can compare equal, float
+ *    keys are always sorted stably.
+ *  - Pairs (and float keys) are sorted stably: equal keys keep their input
+ *    order.
+ *  - In-place operation is allowed when an output pointer equals the
+ *    corresponding input pointer; any other overlap is an error.
+ *  - Sizes: n and every segment hold at most 2^31 - 1 elements.
+ *  - Pointers must be 4-byte aligned; 16-byte alignment enables wider loads.
+ *
+ * Return codes: 0 = success; < 0 = argument error found on the host before
+ * anything is enqueued (see MSN_ERR_*); > 0 = the hipError_t of a failed
+ * launch.  msn_status_string() names each code.
+ */
+#ifndef MSN_H
+#define MSN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* key types */
+#define MSN_U32 0
+#define MSN_I32 1
+#define MSN_F32 2
+
+/* base-case network sets (Table 3): the network size each lane applies */
+#define MSN_LEAF_6TO8 0 /* 8-key networks (6- and 7-key tails by padding) */
+#define MSN_LEAF_3TO5 1 /* 4-key networks (3-key tails by padding)        */
+
+/* status codes */
+#define MSN_OK 0
+#define MSN_ERR_NULL (-1)        /* required pointer is NULL                  */
+#define MSN_ERR_SIZE (-2)        /* size/offset/overlap out of range          */
+#define MSN_ERR_DTYPE (-3)       /* unknown key type                          */
+#define MSN_ERR_CONFIG (-4)      /* unknown leaf set, flag or tuning value    */
+#define MSN_ERR_WORKSPACE (-5)   /* workspace missing or too small            */
+#define MSN_ERR_UNSUPPORTED (-6) /* valid request this build cannot serve     */
+
+/* flags for msn_segmented_sort */
+#define MSN_ARGSORT 1u /* vals_in must be NULL; vals_out receives segment-local indices */
+
+/*
+ * Optional tuning.  Pass NULL for the defaults.  A zero field means "default".
+ * Every accepted setting yields the same bits; only speed differs.
+ *   merge_tile      outputs per workgroup in a global merge pass:
+ *                   2048, 4096 or 8192 (default 4096).
+ *   seg_lane_max    segments of at most this many keys are sorted by one lane
+ *                   with one network: 0..8 (default: the leaf size).
+ *   seg_wave_max    segments up to this length are sorted by one wavefront:
+ *                   up to 64 x leaf size (default 64 x leaf size).
+ *   seg_block_max   segments up to this length are sorted by one workgroup
+ *                   in LDS: up to 1024 x leaf size (default 1024 x leaf).
+ *   seg_grid        workgroups of the persistent segmented kernel
+ *                   (default: enough to fill every compute unit).
+ */
+typedef struct {
+    int32_t merge_tile;
+    int32_t seg_lane_max;
+    int32_t seg_wave_max;
+    int32_t seg_block_max;
+    int32_t seg_grid;
+    int32_t reserved[3];
+} msn_tuning;
+
+/*
+ * Bytes of workspace msn_sort_keys (pairs = 0) or msn_sort_pairs (pairs = 1)
+ * needs for n keys.  Writes *bytes; returns a status code.
+ */
+int msn_sort_workspace_bytes(int64_t n, int dtype, int pairs, size_t* bytes);
+
+/*
+ * Sorts n keys ascending: keys_out = sorted(keys_in).
+ *   keys_in, keys_out  device arrays of n 32-bit keys (may be equal).
+ *   leaf               MSN_LEAF_* base-case network set.
+ *   ws, ws_bytes       device workspace of at least
+ *                      msn_sort_workspace_bytes(n, dtype, 0) bytes.
+ * Paper: Sec. 3, Algorithm 1 (OptimizedMergeSort on the whole array).
+ */
+int msn_sort_keys(const void* keys_in, void* keys_out, int64_t n, int dtype, int leaf,
+                  const msn_tuning* tuning, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Stable key-value sort of n pairs: the keys as msn_sort_keys, and
+ * vals_out[i] = vals_in[p(i)] where p(i) is the input position of the i-th
+ * output key; equal keys keep input order.  vals_in == NULL asks for an
+ * argsort: vals_out[i] = p(i).
+ *   vals_in, vals_out  device arrays of n uint32 (vals_out required).
+ *   ws, ws_bytes       at least msn_sort_workspace_bytes(n, dtype, 1) bytes.
+ * Paper: Sec. 3, Algorithm 1; stability is this library's reading (the
+ * paper sorts bare keys).
+ */
+int msn_sort_pairs(const void* keys_in, const uint32_t* vals_in, void* keys_out,
+                   uint32_t* vals_out, int64_t n, int dtype, int leaf,
+                   const msn_tuning* tuning, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Bytes of workspace msn_segmented_sort needs.
+ */
+int msn_segmented_sort_workspace_bytes(int64_t n_total, int64_t num_segments, int dtype,
+                                       int pairs, size_t* bytes);
+
+/*
+ * Sorts each segment independently, in one persistent kernel launch after a
+ * small binning launch.  Segment s covers positions [offsets[s],
+ * offsets[s+1]) of the key (and value) arrays.
+ *   offsets        device uint32 array of num_segments + 1 entries, starting
+ *                  at 0, non-decreasing, ending at n_total (not checked on the
+ *                  device: a bad array gives undefined results).  NULL means
+ *                  equal rows: n_total must be a multiple of num_segments and
+ *                  every segment has n_total / num_segments keys.
+ *   vals_in/out    as msn_sort_pairs, per segment; both NULL sorts keys only.
+ *                  With flags & MSN_ARGSORT, vals_in must be NULL and
+ *                  vals_out[i] receives the index, local to its segment, of
+ *                  the input element that lands at i.
+ *   Empty segments are allowed.  Pairs and float keys are stable.
+ * Paper: Algorithm 1 applied to every segment; segments of at most 8 keys
+ * take one network, the role of the variable-size networks of Table 3.
+ */
+int msn_segmented_sort(const void* keys_in, const uint32_t* vals_in, void* keys_out,
+                       uint32_t* vals_out, const uint32_t* offsets, int64_t num_segments,
+                       int64_t n_total, int dtype, int leaf, unsigned flags,
+                       const msn_tuning* tuning, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Backward of a row-wise sort y[r][i] = x[r][perm[r][i]]:
+ * grad_in[r][perm[r][i]] = grad_out[r][i].  No arithmetic, so the result is
+ * exact.
+ *   grad_out, grad_in  device fp32 [rows x cols], row-major (must not overlap).
+ *   perm               device int32 [rows x cols]; each row must be a
+ *                      permutation of 0..cols-1 (as msn_segmented_sort's
+ *                      MSN_ARGSORT output is).  Entries outside [0, cols) are
+ *                      skipped, never written out of bounds.
+ * Not in the paper (it has no gradients); a sort's derivative routes each
+ * output gradient to the input the value came from.
+ */
+int msn_sort_backward(const float* grad_out, const int32_t* perm, float* grad_in,
+                      int64_t rows, int64_t cols, void* stream);
+
+/*
+ * Kernel timing (diagnostics, for benchmarks and profiling).  While enabled,
+ * the library brackets each kernel it launches with two hipEvents recorded on
+ * the launching stream (no synchronisation).  msn_timing_read waits for the
+ * recorded events and reports, per kernel kind, the number of launches, the
+ * elements they processed and the summed event time.  Not thread-safe; events
+ * are host-allocated by msn_timing_enable and freed by msn_timing_disable.
+ * Launches beyond max_launches are not timed.  Do not enable while capturing
+ * a HIP graph.
+ */
+typedef struct {
+    char kind[24];      /* "block_sort", "partition", "merge", "seg_init", ... */
+    int64_t launches;
+    int64_t elements;   /* keys (or rows x cols) processed, summed */
+    double total_ms;
+} msn_kernel_stats;
+
+int msn_timing_enable(int max_launches);
+int msn_timing_read(msn_kernel_stats* out, int capacity, int* count);
+int msn_timing_disable(void);
+
+/* Human-readable name of a status code. */
+const char* msn_status_string(int status);
+
+/* Library version, major * 10000 + minor * 100 + patch. */
+int msn_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MSN_H */

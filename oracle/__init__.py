@@ -63,6 +63,8 @@ class Oracle:
         lib.orc_alg1_leaf_histogram.restype = I
         lib.orc_gather_backward.argtypes = [P, P, P, I64, I64]
         lib.orc_gather_backward.restype = I
+        lib.orc_rank_bounds.argtypes = [I, P, I64, U32, P, P]
+        lib.orc_rank_bounds.restype = I
         self.lib = lib
 
     # -- networks ---------------------------------------------------------
@@ -165,6 +167,18 @@ class Oracle:
         if rc:
             raise ValueError(f"orc_alg1_leaf_histogram rc={rc}")
         return hist
+
+    def rank_bounds(self, keys, value, *, dtype="u32"):
+        """(number of keys before ``value``, number not after it) in dtype order."""
+        k = np.ascontiguousarray(keys, dtype=_NP_OF[dtype]).view(np.uint32)
+        v = int(np.asarray(value, dtype=_NP_OF[dtype]).view(np.uint32))
+        lt = np.zeros(1, dtype=np.int64)
+        le = np.zeros(1, dtype=np.int64)
+        rc = self.lib.orc_rank_bounds(DTYPES[dtype], k.ctypes.data, k.shape[0], v,
+                                      lt.ctypes.data, le.ctypes.data)
+        if rc:
+            raise ValueError(f"orc_rank_bounds rc={rc}")
+        return int(lt[0]), int(le[0])
 
     def gather_backward(self, grad_out, perm):
         """grad_in[r, perm[r, i]] = grad_out[r, i] for a batch of rows."""

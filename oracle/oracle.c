@@ -483,3 +483,24 @@ int orc_gather_backward(const float* grad_out, const int32_t* perm, float* grad_
             grad_in[r * cols + perm[r * cols + i]] = grad_out[r * cols + i];
     return 0;
 }
+
+/*
+ * Rank check for one output value v of a sort of keys[0..n-1]: *less counts
+ * keys ordered strictly before v, *less_equal those not ordered after it.
+ * y is the sorted output iff less(y[i]) <= i < less_equal(y[i]) for every i,
+ * so any sample of positions can be checked one by one at any size.
+ */
+int orc_rank_bounds(int dtype, const uint32_t* keys, int64_t n, uint32_t v, int64_t* less,
+                    int64_t* less_equal) {
+    if (dtype != ORC_U32 && dtype != ORC_I32 && dtype != ORC_F32) return -3;
+    if (n < 0) return -2;
+    if ((n > 0 && !keys) || !less || !less_equal) return -1;
+    int64_t lt = 0, le = 0;
+    for (int64_t i = 0; i < n; i++) {
+        if (key_less(dtype, keys[i], v)) lt++;
+        if (!key_less(dtype, v, keys[i])) le++;
+    }
+    *less = lt;
+    *less_equal = le;
+    return 0;
+}

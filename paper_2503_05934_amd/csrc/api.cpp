@@ -1,0 +1,299 @@
+// C ABI of libmsn (declared in include/msn.h): argument validation on the
+// host, then the kernel launches of sort.hip, segmented.hip, backward.hip.
+// Every check runs before anything is enqueued, so a rejected call never
+// touches the GPU.
+#include <string.h>
+
+#include <map>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace msn {
+
+int set_dynamic_lds(const void* kernel, size_t bytes) {
+    static std::mutex mu;
+    static std::unordered_map<const void*, size_t> done;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = done.find(kernel);
+    if (it != done.end() && it->second >= bytes) return 0;
+    const int rc =
+        (int)hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (rc == 0) done[kernel] = bytes;
+    return rc;
+}
+
+namespace {
+
+struct TimedLaunch {
+    const char* kind;
+    int64_t elements;
+    int ev0;
+    int ev1;
+};
+
+struct TimingState {
+    std::mutex mu;
+    bool on = false;
+    std::vector<hipEvent_t> events;
+    std::vector<TimedLaunch> launches;
+    size_t next = 0;
+};
+
+TimingState& timing() {
+    static TimingState t;
+    return t;
+}
+
+}  // namespace
+
+LaunchTimer::LaunchTimer(const char* kind, int64_t elements, hipStream_t stream)
+    : slot_(-1), stream_(stream) {
+    TimingState& t = timing();
+    std::lock_guard<std::mutex> lock(t.mu);
+    if (!t.on || t.next + 2 > t.events.size()) return;
+    slot_ = (int)t.launches.size();
+    t.launches.push_back({kind, elements, (int)t.next, (int)t.next + 1});
+    t.next += 2;
+    (void)hipEventRecord(t.events[t.launches[slot_].ev0], stream_);
+}
+
+LaunchTimer::~LaunchTimer() {
+    if (slot_ < 0) return;
+    TimingState& t = timing();
+    std::lock_guard<std::mutex> lock(t.mu);
+    (void)hipEventRecord(t.events[t.launches[slot_].ev1], stream_);
+}
+
+}  // namespace msn
+
+namespace {
+
+constexpr int64_t kMaxN = 0x7fffffffLL;
+
+bool valid_dtype(int d) { return d == MSN_U32 || d == MSN_I32 || d == MSN_F32; }
+int leaf_keys(int leaf) { return leaf == MSN_LEAF_6TO8 ? 8 : leaf == MSN_LEAF_3TO5 ? 4 : 0; }
+
+bool misaligned(const void* p) { return p && ((uintptr_t)p & 3u) != 0; }
+
+// Two ranges of n words either coincide (in-place) or do not overlap.
+bool bad_overlap(const void* a, const void* b, int64_t n) {
+    if (!a || !b || a == b) return false;
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b, len = (uintptr_t)n * 4;
+    return x < y + len && y < x + len;
+}
+
+int merge_tile_of(const msn_tuning* t, int* out) {
+    int mt = t && t->merge_tile ? t->merge_tile : msn::kDefaultMergeTile;
+    if (mt != 2048 && mt != 4096 && mt != 8192) return MSN_ERR_CONFIG;
+    *out = mt;
+    return MSN_OK;
+}
+
+int sort_common(const void* keys_in, const uint32_t* vals_in, void* keys_out, uint32_t* vals_out,
+                int64_t n, int dtype, int leaf, const msn_tuning* tuning, void* ws,
+                size_t ws_bytes, void* stream, bool pairs) {
+    if (!valid_dtype(dtype)) return MSN_ERR_DTYPE;
+    const int k = leaf_keys(leaf);
+    if (!k) return MSN_ERR_CONFIG;
+    int mt = 0;
+    if (int rc = merge_tile_of(tuning, &mt)) return rc;
+    if (n < 0 || n > kMaxN) return MSN_ERR_SIZE;
+    if (n == 0) return MSN_OK;
+    if (!keys_in || !keys_out) return MSN_ERR_NULL;
+    if (pairs && !vals_out) return MSN_ERR_NULL;
+    if (misaligned(keys_in) || misaligned(keys_out) || misaligned(vals_in) || misaligned(vals_out) ||
+        misaligned(ws))
+        return MSN_ERR_UNSUPPORTED;
+    if (bad_overlap(keys_in, keys_out, n) || bad_overlap(vals_in, vals_out, n) ||
+        (pairs && (bad_overlap(keys_out, vals_out, n) || keys_out == (void*)vals_out)))
+        return MSN_ERR_SIZE;
+    const int vmode = !pairs ? msn::kNoVals : vals_in ? msn::kVals : msn::kArg;
+    const size_t need = msn::sort_ws_bytes(n, vmode != msn::kNoVals);
+    if (!ws || ws_bytes < need) return MSN_ERR_WORKSPACE;
+    msn::SortArgs a{static_cast<const uint32_t*>(keys_in), vals_in,
+                    static_cast<uint32_t*>(keys_out), vals_out, n, dtype, k, vmode, mt, ws,
+                    ws_bytes, static_cast<hipStream_t>(stream)};
+    return msn::launch_sort(a);
+}
+
+}  // namespace
+
+extern "C" {
+
+int msn_version(void) { return 10000; }
+
+int msn_timing_enable(int max_launches) {
+    if (max_launches <= 0 || max_launches > (1 << 20)) return MSN_ERR_SIZE;
+    msn::TimingState& t = msn::timing();
+    std::lock_guard<std::mutex> lock(t.mu);
+    for (hipEvent_t e : t.events) (void)hipEventDestroy(e);
+    t.events.assign((size_t)max_launches * 2, nullptr);
+    for (auto& e : t.events)
+        if (int rc = (int)hipEventCreate(&e)) {
+            t.events.clear();
+            t.on = false;
+            return rc;
+        }
+    t.launches.clear();
+    t.next = 0;
+    t.on = true;
+    return MSN_OK;
+}
+
+int msn_timing_read(msn_kernel_stats* out, int capacity, int* count) {
+    if (!count || (capacity > 0 && !out)) return MSN_ERR_NULL;
+    msn::TimingState& t = msn::timing();
+    std::lock_guard<std::mutex> lock(t.mu);
+    std::map<std::string, msn_kernel_stats> acc;
+    for (const auto& l : t.launches) {
+        if (int rc = (int)hipEventSynchronize(t.events[l.ev1])) return rc;
+        float ms = 0.f;
+        if (int rc = (int)hipEventElapsedTime(&ms, t.events[l.ev0], t.events[l.ev1])) return rc;
+        msn_kernel_stats& k = acc[l.kind];
+        strncpy(k.kind, l.kind, sizeof k.kind - 1);
+        k.launches += 1;
+        k.elements += l.elements;
+        k.total_ms += ms;
+    }
+    int i = 0;
+    for (const auto& kv : acc) {
+        if (i < capacity) out[i] = kv.second;
+        ++i;
+    }
+    *count = i;
+    return MSN_OK;
+}
+
+int msn_timing_disable(void) {
+    msn::TimingState& t = msn::timing();
+    std::lock_guard<std::mutex> lock(t.mu);
+    for (hipEvent_t e : t.events) (void)hipEventDestroy(e);
+    t.events.clear();
+    t.launches.clear();
+    t.next = 0;
+    t.on = false;
+    return MSN_OK;
+}
+
+const char* msn_status_string(int status) {
+    switch (status) {
+        case MSN_OK: return "ok";
+        case MSN_ERR_NULL: return "required pointer is NULL";
+        case MSN_ERR_SIZE: return "size, offset or overlap out of range";
+        case MSN_ERR_DTYPE: return "unknown key type";
+        case MSN_ERR_CONFIG: return "unknown leaf set, flag or tuning value";
+        case MSN_ERR_WORKSPACE: return "workspace missing or too small";
+        case MSN_ERR_UNSUPPORTED: return "request not supported (alignment)";
+        default: return status > 0 ? "HIP launch error" : "unknown status";
+    }
+}
+
+int msn_sort_workspace_bytes(int64_t n, int dtype, int pairs, size_t* bytes) {
+    if (!bytes) return MSN_ERR_NULL;
+    if (!valid_dtype(dtype)) return MSN_ERR_DTYPE;
+    if (n < 0 || n > kMaxN) return MSN_ERR_SIZE;
+    *bytes = msn::sort_ws_bytes(n, pairs != 0);
+    return MSN_OK;
+}
+
+int msn_sort_keys(const void* keys_in, void* keys_out, int64_t n, int dtype, int leaf,
+                  const msn_tuning* tuning, void* ws, size_t ws_bytes, void* stream) {
+    return sort_common(keys_in, nullptr, keys_out, nullptr, n, dtype, leaf, tuning, ws, ws_bytes,
+                       stream, false);
+}
+
+int msn_sort_pairs(const void* keys_in, const uint32_t* vals_in, void* keys_out,
+                   uint32_t* vals_out, int64_t n, int dtype, int leaf, const msn_tuning* tuning,
+                   void* ws, size_t ws_bytes, void* stream) {
+    return sort_common(keys_in, vals_in, keys_out, vals_out, n, dtype, leaf, tuning, ws, ws_bytes,
+                       stream, true);
+}
+
+int msn_segmented_sort_workspace_bytes(int64_t n_total, int64_t num_segments, int dtype,
+                                       int pairs, size_t* bytes) {
+    if (!bytes) return MSN_ERR_NULL;
+    if (!valid_dtype(dtype)) return MSN_ERR_DTYPE;
+    if (n_total < 0 || n_total > kMaxN || num_segments < 0 || num_segments > kMaxN)
+        return MSN_ERR_SIZE;
+    *bytes = msn::seg_ws_bytes(n_total, num_segments, pairs != 0);
+    return MSN_OK;
+}
+
+int msn_segmented_sort(const void* keys_in, const uint32_t* vals_in, void* keys_out,
+                       uint32_t* vals_out, const uint32_t* offsets, int64_t num_segments,
+                       int64_t n_total, int dtype, int leaf, unsigned flags,
+                       const msn_tuning* tuning, void* ws, size_t ws_bytes, void* stream) {
+    if (!valid_dtype(dtype)) return MSN_ERR_DTYPE;
+    const int k = leaf_keys(leaf);
+    if (!k) return MSN_ERR_CONFIG;
+    if (flags & ~MSN_ARGSORT) return MSN_ERR_CONFIG;
+    const bool argsort = (flags & MSN_ARGSORT) != 0;
+    if (argsort && vals_in) return MSN_ERR_CONFIG;
+    if (!argsort && !vals_in && vals_out) return MSN_ERR_CONFIG;
+    if ((argsort || vals_in) && !vals_out) return MSN_ERR_NULL;
+    if (n_total < 0 || n_total > kMaxN || num_segments < 0 || num_segments > kMaxN)
+        return MSN_ERR_SIZE;
+    if (num_segments == 0) return n_total == 0 ? MSN_OK : MSN_ERR_SIZE;
+    if (!offsets && n_total % num_segments != 0) return MSN_ERR_SIZE;
+
+    const int tile = k * msn::kBlockThreads;
+    int lane_max = k, wave_max = msn::kWave * k, block_max = tile, grid = 0;
+    if (tuning) {
+        if (tuning->seg_lane_max) lane_max = tuning->seg_lane_max;
+        if (tuning->seg_wave_max) wave_max = tuning->seg_wave_max;
+        if (tuning->seg_block_max) block_max = tuning->seg_block_max;
+        grid = tuning->seg_grid;
+        if (lane_max < 0 || lane_max > k || wave_max < lane_max || wave_max > msn::kWave * k ||
+            block_max < wave_max || block_max > tile || grid < 0)
+            return MSN_ERR_CONFIG;
+    }
+    if (n_total == 0) return MSN_OK;
+    if (!keys_in || !keys_out) return MSN_ERR_NULL;
+    if (misaligned(keys_in) || misaligned(keys_out) || misaligned(vals_in) || misaligned(vals_out) ||
+        misaligned(ws) || misaligned(offsets))
+        return MSN_ERR_UNSUPPORTED;
+    if (bad_overlap(keys_in, keys_out, n_total) || bad_overlap(vals_in, vals_out, n_total) ||
+        (vals_out && (bad_overlap(keys_out, vals_out, n_total) || keys_out == (void*)vals_out)))
+        return MSN_ERR_SIZE;
+    const int vmode = argsort ? msn::kArg : vals_in ? msn::kVals : msn::kNoVals;
+    const size_t need = msn::seg_ws_bytes(n_total, num_segments, vmode != msn::kNoVals);
+    if (!ws || ws_bytes < need) return MSN_ERR_WORKSPACE;
+    msn::SegArgs a{static_cast<const uint32_t*>(keys_in),
+                   vals_in,
+                   static_cast<uint32_t*>(keys_out),
+                   vals_out,
+                   offsets,
+                   num_segments,
+                   n_total,
+                   dtype,
+                   k,
+                   vmode,
+                   lane_max,
+                   wave_max,
+                   block_max,
+                   grid,
+                   ws,
+                   ws_bytes,
+                   static_cast<hipStream_t>(stream)};
+    return msn::launch_segmented(a);
+}
+
+int msn_sort_backward(const float* grad_out, const int32_t* perm, float* grad_in, int64_t rows,
+                      int64_t cols, void* stream) {
+    if (rows < 0 || cols < 0 || cols > kMaxN || (cols > 0 && rows > kMaxN / cols))
+        return MSN_ERR_SIZE;
+    if (rows == 0 || cols == 0) return MSN_OK;
+    if (!grad_out || !perm || !grad_in) return MSN_ERR_NULL;
+    if (misaligned(grad_out) || misaligned(perm) || misaligned(grad_in))
+        return MSN_ERR_UNSUPPORTED;
+    if (bad_overlap(grad_out, grad_in, rows * cols) || (const void*)grad_out == (void*)grad_in)
+        return MSN_ERR_SIZE;
+    return msn::launch_backward(grad_out, perm, grad_in, rows, cols,
+                                static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,128 @@
+// Workgroup-wide sort of one tile of up to K * 1024 keys (steps a1-a4: key
+// map, per-lane network, wavefront bitonic merge, LDS merge path).  Used by
+// the flat sort's first sweep and by the segmented kernel for segments that
+// fit one workgroup.
+#pragma once
+
+#include <type_traits>
+
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace msn {
+
+template <int DT, int K, bool STABLE>
+struct TileTraits {
+    using T = std::conditional_t<STABLE, uint64_t, uint32_t>;
+    static constexpr int kTile = K * kBlockThreads;
+    static constexpr size_t kLdsBytes = (size_t)lds_words<T>(kTile) * sizeof(T);
+    static_assert(!STABLE || kLdsBytes >= (size_t)2 * kTile * 4, "staging must fit");
+};
+
+// Sorts kin[0..nv) into kout[0..nv) (nv <= K*1024).  STABLE sorts
+// (key, position) composites; VM selects the payload: vout[i] = vin[p(i)]
+// (kVals) or val_base + p(i) (kArg), p(i) = tile position of output i.  Float
+// keys are copied bit for bit from the input.  All threads of the workgroup
+// must call this (it contains barriers).  vec: kin/kout/vin/vout are 16-byte
+// aligned.  kout may equal kin (and vout vin): each position is read and
+// written only by its owning thread, or read before a barrier that precedes
+// every write.
+template <int DT, int K, bool STABLE, int VM>
+__device__ __forceinline__ void block_sort_tile(const uint32_t* kin, const uint32_t* vin,
+                                                uint32_t* kout, uint32_t* vout, int nv,
+                                                uint32_t val_base, void* smem, bool vec) {
+    using Tr = TileTraits<DT, K, STABLE>;
+    using T = typename Tr::T;
+    static_assert(STABLE || (DT != kF32 && VM == kNoVals), "float keys and pairs sort stably");
+    T* s = reinterpret_cast<T*>(smem);
+    const int tid = threadIdx.x;
+    const int first = tid * K;
+
+    uint32_t x[K];
+    if (vec && first + K <= nv) {
+#pragma unroll
+        for (int q = 0; q < K / 4; ++q) {
+            const uint4 w = *reinterpret_cast<const uint4*>(kin + first + 4 * q);
+            x[4 * q + 0] = w.x;
+            x[4 * q + 1] = w.y;
+            x[4 * q + 2] = w.z;
+            x[4 * q + 3] = w.w;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < K; ++j) x[j] = (first + j < nv) ? kin[first + j] : 0u;
+    }
+    T v[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        if constexpr (STABLE) {
+            v[j] = (first + j < nv)
+                       ? (((uint64_t)ord_key<DT>(x[j]) << 32) | (uint32_t)(first + j))
+                       : ~0ull;
+        } else {
+            v[j] = (first + j < nv) ? ord_key<DT>(x[j]) : 0xffffffffu;
+        }
+    }
+
+    const int span = span_for(nv, kWave * K);
+    block_sort_regs<T, K>(v, s, span);
+
+    if constexpr (!STABLE) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) x[j] = unord_key<DT>(v[j]);
+        if (vec && first + K <= nv) {
+#pragma unroll
+            for (int q = 0; q < K / 4; ++q)
+                *reinterpret_cast<uint4*>(kout + first + 4 * q) =
+                    make_uint4(x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+                if (first + j < nv) kout[first + j] = x[j];
+        }
+    } else {
+        // Stage what must be gathered by position (float bits, payload).
+        uint32_t* sbits = reinterpret_cast<uint32_t*>(smem);
+        uint32_t* svals = sbits + Tr::kTile;
+        constexpr bool kNeedBits = DT == kF32;
+        constexpr bool kNeedVals = VM == kVals;
+        __syncthreads();
+        if constexpr (kNeedBits || kNeedVals) {
+            for (int i = tid; i < nv; i += kBlockThreads) {
+                if constexpr (kNeedBits) sbits[i] = kin[i];
+                if constexpr (kNeedVals) svals[i] = vin[i];
+            }
+        }
+        __syncthreads();
+        uint32_t y[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const uint32_t tag = (uint32_t)v[j];
+            const bool live = first + j < nv;
+            const uint32_t t = live ? tag : 0u;
+            if constexpr (kNeedBits) x[j] = sbits[t];
+            else x[j] = unord_key<DT>((uint32_t)(v[j] >> 32));
+            if constexpr (VM == kVals) y[j] = svals[t];
+            else y[j] = val_base + t;
+        }
+        if (vec && first + K <= nv) {
+#pragma unroll
+            for (int q = 0; q < K / 4; ++q) {
+                *reinterpret_cast<uint4*>(kout + first + 4 * q) =
+                    make_uint4(x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3]);
+                if constexpr (VM != kNoVals)
+                    *reinterpret_cast<uint4*>(vout + first + 4 * q) =
+                        make_uint4(y[4 * q], y[4 * q + 1], y[4 * q + 2], y[4 * q + 3]);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+                if (first + j < nv) {
+                    kout[first + j] = x[j];
+                    if constexpr (VM != kNoVals) vout[first + j] = y[j];
+                }
+        }
+    }
+}
+
+}  // namespace msn

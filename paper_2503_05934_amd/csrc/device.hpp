@@ -1,0 +1,283 @@
+// Device building blocks of the network-leaf merge sort (gfx950, wave64).
+//
+// Paper (arXiv 2503.05934), Sec. 3, Algorithm 1: a merge sort that sorts
+// small subarrays with fixed sorting networks and merges the rest.  On the GPU
+// the recursion is run bottom-up:
+//   1. every lane loads K consecutive keys and sorts them with one K-input
+//      network held in VGPRs (the base case; K = 8 for the 6-to-8 set of
+//      Table 3, K = 4 for 3-to-5);
+//   2. a wavefront merges its 64 runs into one run of 64*K keys with bitonic
+//      merges over cross-lane exchanges;
+//   3. a workgroup merges its wavefront runs in LDS by merge path;
+//   4. global passes merge pairs of runs until one run remains.
+// Every merge is stable: on equal keys the left run's element goes first, as
+// in the paper's Merge.  Networks and bitonic stages are not stable, so when
+// stability matters the key carries its tile position in its low 32 bits
+// ("composite key") until the first merge-path level.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "internal.hpp"
+
+namespace msn {
+
+// ------------------------------------------------------------ key order ---
+// Order-preserving map of a key's bits to an unsigned 32-bit word.  uint32 is
+// the identity, int32 flips the sign bit.  float32 first replaces -0 by +0
+// and every NaN by one quiet NaN (they compare equal), then flips negative
+// numbers bitwise and sets the sign bit of the rest, so that unsigned order is
+// IEEE order with NaN above +inf.  The largest value a float can map to is
+// 0xFFC00000.
+template <int DT>
+__device__ __forceinline__ uint32_t ord_key(uint32_t b) {
+    if constexpr (DT == kU32) {
+        return b;
+    } else if constexpr (DT == kI32) {
+        return b ^ 0x80000000u;
+    } else {
+        const uint32_t mag = b & 0x7fffffffu;
+        b = (mag == 0u) ? 0u : b;
+        b = (mag > 0x7f800000u) ? 0x7fc00000u : b;
+        return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+    }
+}
+
+// Inverse of ord_key for the bijective maps (uint32, int32).
+template <int DT>
+__device__ __forceinline__ uint32_t unord_key(uint32_t o) {
+    if constexpr (DT == kI32) return o ^ 0x80000000u;
+    return o;
+}
+
+// ------------------------------------------------------ compare-exchange ---
+__device__ __forceinline__ uint32_t kmin(uint32_t a, uint32_t b) { return a < b ? a : b; }
+__device__ __forceinline__ uint32_t kmax(uint32_t a, uint32_t b) { return a < b ? b : a; }
+__device__ __forceinline__ uint64_t kmin(uint64_t a, uint64_t b) { return a < b ? a : b; }
+__device__ __forceinline__ uint64_t kmax(uint64_t a, uint64_t b) { return a < b ? b : a; }
+
+template <typename T>
+__device__ __forceinline__ void cx(T& a, T& b) {
+    const T lo = kmin(a, b);
+    const T hi = kmax(a, b);
+    a = lo;
+    b = hi;
+}
+
+// --------------------------------------------------------------- networks ---
+// Fixed sorting networks, branch-free min/max in registers.  Both are
+// Batcher's odd-even merge sort (Knuth, TAOCP 3, Sec. 5.3.4), written out in
+// parallel layers: 8 inputs = 19 comparators in 6 layers, 4 inputs = 5 in 3.
+// Fewer live keys (a tail) are handled by padding with the largest value,
+// which never moves and so equals the pruned smaller network.
+template <typename T>
+__device__ __forceinline__ void network8(T (&v)[8]) {
+    cx(v[0], v[1]); cx(v[2], v[3]); cx(v[4], v[5]); cx(v[6], v[7]);
+    cx(v[0], v[2]); cx(v[1], v[3]); cx(v[4], v[6]); cx(v[5], v[7]);
+    cx(v[1], v[2]); cx(v[5], v[6]);
+    cx(v[0], v[4]); cx(v[1], v[5]); cx(v[2], v[6]); cx(v[3], v[7]);
+    cx(v[2], v[4]); cx(v[3], v[5]);
+    cx(v[1], v[2]); cx(v[3], v[4]); cx(v[5], v[6]);
+}
+
+template <typename T>
+__device__ __forceinline__ void network4(T (&v)[4]) {
+    cx(v[0], v[1]); cx(v[2], v[3]);
+    cx(v[0], v[2]); cx(v[1], v[3]);
+    cx(v[1], v[2]);
+}
+
+template <typename T, int K>
+__device__ __forceinline__ void leaf_network(T (&v)[K]) {
+    static_assert(K == 8 || K == 4, "leaf size");
+    if constexpr (K == 8) network8(v); else network4(v);
+}
+
+// -------------------------------------------------------- lane exchanges ---
+// Value of x in lane (lane ^ mask).  xor masks below 32 use ds_swizzle's
+// bit-mode (and = 0x1f, xor = mask), which stays inside 32-lane halves; 32
+// uses ds_bpermute across the halves.  Neither touches LDS memory.
+template <int MASK>
+__device__ __forceinline__ uint32_t xor_lane(uint32_t x) {
+    static_assert(MASK > 0 && MASK < 64, "mask");
+    if constexpr (MASK < 32) {
+        return (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, (MASK << 10) | 0x1f);
+    } else {
+        const int src = ((int)(threadIdx.x & 63) ^ MASK) << 2;
+        return (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)x);
+    }
+}
+
+template <int MASK>
+__device__ __forceinline__ uint64_t xor_lane(uint64_t x) {
+    const uint32_t lo = xor_lane<MASK>((uint32_t)x);
+    const uint32_t hi = xor_lane<MASK>((uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// ----------------------------------------------------- wavefront merging ---
+// Runs of G lanes (G*K keys, lane-major: key e sits in lane e / K, slot
+// e % K) are merged pairwise into runs of 2G lanes by a bitonic merge:
+//   flip  : key e of the pair meets key (2GK-1-e): lane l meets lane
+//           l ^ (2G-1), slot j meets slot K-1-j; the lower key keeps the min.
+//   clean : distance d = GK/2, ..., 1: key e meets e + d; for d >= K that is
+//           lane l ^ (d/K) in the same slot, below K it is inside the lane.
+template <typename T, int K, int G>
+__device__ __forceinline__ void wave_merge_level(T (&v)[K], int lane) {
+    {
+        T o[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) o[j] = xor_lane<2 * G - 1>(v[K - 1 - j]);
+        const bool upper = (lane & G) != 0;
+#pragma unroll
+        for (int j = 0; j < K; ++j) v[j] = upper ? kmax(v[j], o[j]) : kmin(v[j], o[j]);
+    }
+    if constexpr (G >= 2) {
+        // cross-lane half-cleaners, lane distance G/2 ... 1
+#pragma unroll
+        for (int m = G / 2; m >= 1; m >>= 1) {
+            const bool upper = (lane & m) != 0;
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                T o;
+                switch (m) {
+                    case 1: o = xor_lane<1>(v[j]); break;
+                    case 2: o = xor_lane<2>(v[j]); break;
+                    case 4: o = xor_lane<4>(v[j]); break;
+                    case 8: o = xor_lane<8>(v[j]); break;
+                    default: o = xor_lane<16>(v[j]); break;
+                }
+                v[j] = upper ? kmax(v[j], o) : kmin(v[j], o);
+            }
+        }
+    }
+    // in-lane half-cleaners, distance K/2 ... 1
+#pragma unroll
+    for (int d = K / 2; d >= 1; d >>= 1) {
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if ((j & d) == 0) cx(v[j], v[j + d]);
+    }
+}
+
+// 64 sorted lane runs of K keys -> one sorted run of 64*K keys per wavefront.
+template <typename T, int K>
+__device__ __forceinline__ void wave_merge(T (&v)[K], int lane) {
+    wave_merge_level<T, K, 1>(v, lane);
+    wave_merge_level<T, K, 2>(v, lane);
+    wave_merge_level<T, K, 4>(v, lane);
+    wave_merge_level<T, K, 8>(v, lane);
+    wave_merge_level<T, K, 16>(v, lane);
+    wave_merge_level<T, K, 32>(v, lane);
+}
+
+// --------------------------------------------------------------- LDS maps ---
+// Padded LDS index: one spare slot every 32 words (every 16 for 64-bit keys)
+// so that the strided accesses of merge path do not pile onto few banks.
+template <typename T>
+__device__ __forceinline__ int lds_idx(int i) {
+    return sizeof(T) == 8 ? i + (i >> 4) : i + (i >> 5);
+}
+template <typename T>
+__host__ __device__ constexpr int lds_words(int n) {
+    return sizeof(T) == 8 ? n + (n >> 4) + 1 : n + (n >> 5) + 1;
+}
+
+// Merge path (Green, McColl, Bader 2012): number of elements of A among the
+// first d outputs of the stable merge of A (la keys) and B (lb keys), both
+// sorted; A wins ties.  `less` compares two stored keys.
+template <typename T, typename Less>
+__device__ __forceinline__ int corank_lds(const T* s, int a0, int la, int b0, int lb, int d,
+                                          Less less) {
+    int lo = d > lb ? d - lb : 0;
+    int hi = d < la ? d : la;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (!less(s[lds_idx<T>(b0 + d - 1 - mid)], s[lds_idx<T>(a0 + mid)]))
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// Sequential stable merge of N outputs starting at A[i], B[j] (LDS runs
+// [a0, a0+la) and [b0, b0+lb)).  One LDS read per output; reads past a run's
+// end are clamped to `limit` and their values ignored.  src[k] receives the
+// (unpadded) LDS position of output k.
+template <typename T, int N, bool SRC, typename Less>
+__device__ __forceinline__ void serial_merge(const T* s, int a0, int la, int b0, int lb, int i,
+                                             int j, int limit, T (&out)[N], int (&src)[N],
+                                             Less less) {
+    T a = s[lds_idx<T>(min(a0 + i, limit))];
+    T b = s[lds_idx<T>(min(b0 + j, limit))];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const bool take_a = (i < la) && (j >= lb || !less(b, a));
+        out[k] = take_a ? a : b;
+        if constexpr (SRC) src[k] = take_a ? a0 + i : b0 + j;
+        i += take_a ? 1 : 0;
+        j += take_a ? 0 : 1;
+        const int nxt = take_a ? a0 + i : b0 + j;
+        const T x = s[lds_idx<T>(min(nxt, limit))];
+        a = take_a ? x : a;
+        b = take_a ? b : x;
+    }
+}
+
+struct PlainLess {
+    template <typename T>
+    __device__ __forceinline__ bool operator()(T x, T y) const { return x < y; }
+};
+
+template <int DT>
+struct OrdLess {
+    __device__ __forceinline__ bool operator()(uint32_t x, uint32_t y) const {
+        return ord_key<DT>(x) < ord_key<DT>(y);
+    }
+};
+
+// --------------------------------------------------------- block sorting ---
+// Sorts the K*kBlockThreads keys held as v[] by all threads of a workgroup
+// (thread t holds keys t*K .. t*K+K-1, already in registers).  `span` (a power
+// of two, at least 64*K) is how many leading keys matter: lanes beyond it
+// still take part in barriers but skip the work.  On return thread t holds
+// outputs t*K .. t*K+K-1 of the sorted span.  s is LDS of lds_words<T>(K *
+// kBlockThreads) words.
+template <typename T, int K>
+__device__ __forceinline__ void block_sort_regs(T (&v)[K], T* s, int span) {
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const bool active = tid * K < span;
+    if (active) {
+        leaf_network<T, K>(v);
+        wave_merge<T, K>(v, lane);
+    }
+    int dummy[K];
+    for (int L = kWave * K; L < span; L <<= 1) {
+        if (active) {
+#pragma unroll
+            for (int j = 0; j < K; ++j) s[lds_idx<T>(tid * K + j)] = v[j];
+        }
+        __syncthreads();
+        if (active) {
+            const int d_all = tid * K;
+            const int base = d_all & ~(2 * L - 1);
+            const int d = d_all - base;
+            const int i = corank_lds(s, base, L, base + L, L, d, PlainLess{});
+            serial_merge<T, K, false>(s, base, L, base + L, L, i, d - i, span - 1, v, dummy,
+                                      PlainLess{});
+        }
+        __syncthreads();
+    }
+}
+
+// Smallest power of two >= max(n, lo).
+__device__ __forceinline__ int span_for(int n, int lo) {
+    int s = lo;
+    while (s < n) s <<= 1;
+    return s;
+}
+
+}  // namespace msn

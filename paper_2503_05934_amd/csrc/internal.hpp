@@ -1,0 +1,96 @@
+// Host-side declarations shared by the C ABI (api.cpp) and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "msn.h"
+
+namespace msn {
+
+constexpr int kWave = 64;
+constexpr int kBlockThreads = 1024;  // block sort: 16 wavefronts
+constexpr int kMergeThreads = 256;   // global merge pass
+
+enum KeyType : int { kU32 = 0, kI32 = 1, kF32 = 2 };
+
+// Values travelling with the keys.
+enum ValMode : int {
+    kNoVals = 0,  // keys only
+    kVals = 1,    // caller's uint32 payload
+    kArg = 2,     // payload = index (argsort); generated, never read
+};
+
+struct SortArgs {
+    const uint32_t* kin;
+    const uint32_t* vin;  // kVals only
+    uint32_t* kout;
+    uint32_t* vout;       // kVals / kArg
+    int64_t n;
+    int dtype;
+    int leaf_k;           // keys per lane in the base case: 8 or 4
+    int vmode;
+    int merge_tile;       // 2048, 4096 or 8192
+    void* ws;
+    size_t ws_bytes;
+    hipStream_t stream;
+};
+
+struct SegArgs {
+    const uint32_t* kin;
+    const uint32_t* vin;
+    uint32_t* kout;
+    uint32_t* vout;
+    const uint32_t* offsets;  // NULL = equal rows
+    int64_t num_segments;
+    int64_t n_total;
+    int dtype;
+    int leaf_k;
+    int vmode;                // kArg = segment-local argsort
+    int lane_max, wave_max, block_max, grid;
+    void* ws;
+    size_t ws_bytes;
+    hipStream_t stream;
+};
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+constexpr int kMinMergeTile = 2048;
+constexpr int kDefaultMergeTile = 4096;
+
+// Workspace of the flat sort: ping-pong keys (+ values) and one merge-path
+// split per merge tile.
+inline size_t sort_ws_bytes(int64_t n, bool vals) {
+    const size_t nk = align_up((size_t)n * 4, 256);
+    const size_t nv = vals ? nk : 0;
+    const size_t tiles = (size_t)((n + kMinMergeTile - 1) / kMinMergeTile) + 1;
+    return nk + nv + align_up(tiles * 4, 256);
+}
+
+size_t seg_ws_bytes(int64_t n_total, int64_t num_segments, bool vals);
+
+// Raises a kernel's dynamic-LDS limit to `bytes` (needed beyond 64 KiB); done
+// once per kernel and process.  Returns a hipError_t value.
+int set_dynamic_lds(const void* kernel, size_t bytes);
+
+// Brackets one kernel launch with hipEvents when timing is enabled
+// (msn_timing_enable); a no-op otherwise.
+class LaunchTimer {
+   public:
+    LaunchTimer(const char* kind, int64_t elements, hipStream_t stream);
+    ~LaunchTimer();
+    LaunchTimer(const LaunchTimer&) = delete;
+    LaunchTimer& operator=(const LaunchTimer&) = delete;
+
+   private:
+    int slot_;
+    hipStream_t stream_;
+};
+
+int launch_sort(const SortArgs& a);
+int launch_segmented(const SegArgs& a);
+int launch_backward(const float* grad_out, const int32_t* perm, float* grad_in, int64_t rows,
+                    int64_t cols, hipStream_t stream);
+
+}  // namespace msn

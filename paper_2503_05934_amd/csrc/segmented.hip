@@ -1,0 +1,455 @@
+// Batched (segmented) sort: many independent arrays of uneven length in one
+// persistent kernel launch.  Algorithm 1 of the paper (Sec. 3) is applied to
+// every segment; the work unit is chosen by segment length:
+//   lane   (<= lane_max keys, at most one leaf): one lane, one network with
+//          padding -- the role of the paper's variable-size networks
+//          (Table 3, VarSort);
+//   wave   (<= wave_max): one wavefront, network + bitonic merges;
+//   block  (<= block_max): one workgroup, network + bitonic + LDS merges;
+//   big    (> block_max): one workgroup sorts the segment's tiles in turn and
+//          then merges them pass by pass through global memory.
+// A binning launch sorts segment ids into per-class lists; the persistent
+// launch then pulls work items (largest classes first) from one atomic
+// counter until the list is exhausted.  No workgroup ever waits for another,
+// so any grid size terminates.
+#include "block_tile.hpp"
+
+namespace msn {
+
+enum SegClass : int {
+    kCLane = 0,
+    kCWave = 1,
+    kCBlock = 2,
+    kCBig1 = 3,  // (1, 2] x block_max
+    kCBig2 = 4,  // (2, 4] x block_max
+    kCBig3 = 5,  // > 4 x block_max
+    kNumClasses = 6
+};
+
+struct SegState {
+    uint32_t count[8];
+    uint32_t head;
+    uint32_t pad[7];
+};
+
+constexpr int kSegMergeKPT = 8;                                // keys per thread, big merges
+constexpr int kSegMergeTile = kSegMergeKPT * kBlockThreads;    // 8192 outputs per step
+constexpr int kSegBoundWords = kBlockThreads + 4;
+
+size_t seg_ws_bytes(int64_t n_total, int64_t num_segments, bool vals) {
+    const size_t nk = align_up((size_t)n_total * 4, 256);
+    const size_t lists = align_up((size_t)num_segments * 4 * kNumClasses, 256);
+    return nk + (vals ? nk : 0) + lists + align_up(sizeof(SegState), 256);
+}
+
+__device__ __forceinline__ void seg_bounds(const uint32_t* offsets, uint32_t s, uint32_t uni_len,
+                                           uint32_t& off, uint32_t& len) {
+    if (offsets) {
+        off = offsets[s];
+        len = offsets[s + 1] - off;
+    } else {
+        off = s * uni_len;
+        len = uni_len;
+    }
+}
+
+// Zeroes the class counters and the work-queue head (a kernel, not a memset,
+// so that graph replays reset it reliably).
+__global__ void k_seg_init(SegState* st) {
+    if (threadIdx.x < sizeof(SegState) / 4) reinterpret_cast<uint32_t*>(st)[threadIdx.x] = 0u;
+}
+
+__global__ __launch_bounds__(256) void k_seg_bin(const uint32_t* __restrict__ offsets,
+                                                 int64_t num_segments, uint32_t uni_len,
+                                                 int lane_max, int wave_max, int block_max,
+                                                 SegState* st, uint32_t* __restrict__ lists) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= num_segments) return;
+    uint32_t off, len;
+    seg_bounds(offsets, (uint32_t)s, uni_len, off, len);
+    const uint32_t b = (uint32_t)block_max;
+    int cls;
+    if (len <= (uint32_t)lane_max) cls = kCLane;
+    else if (len <= (uint32_t)wave_max) cls = kCWave;
+    else if (len <= b) cls = kCBlock;
+    else if (len <= 2 * b) cls = kCBig1;
+    else if (len <= 4 * b) cls = kCBig2;
+    else cls = kCBig3;
+    const uint32_t pos = atomicAdd(&st->count[cls], 1u);
+    lists[(int64_t)cls * num_segments + pos] = (uint32_t)s;
+}
+
+// ------------------------------------------------------------ lane tasks ---
+template <int DT, int K, bool STABLE, int VM>
+__device__ __forceinline__ void lane_task(const uint32_t* kin, const uint32_t* vin,
+                                          uint32_t* kout, uint32_t* vout, uint32_t off,
+                                          int len) {
+    using T = typename TileTraits<DT, K, STABLE>::T;
+    uint32_t raw[K], pv[K];
+    T v[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const bool live = j < len;
+        raw[j] = live ? kin[off + j] : 0u;
+        if constexpr (VM == kVals) pv[j] = live ? vin[off + j] : 0u;
+        if constexpr (STABLE)
+            v[j] = live ? (((uint64_t)ord_key<DT>(raw[j]) << 32) | (uint32_t)j) : ~0ull;
+        else
+            v[j] = live ? ord_key<DT>(raw[j]) : 0xffffffffu;
+    }
+    leaf_network<T, K>(v);
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        if (j >= len) break;
+        if constexpr (!STABLE) {
+            kout[off + j] = unord_key<DT>(v[j]);
+        } else {
+            const uint32_t tag = (uint32_t)v[j];
+            uint32_t key = unord_key<DT>((uint32_t)(v[j] >> 32));
+            uint32_t val = tag;
+#pragma unroll
+            for (int q = 0; q < K; ++q) {
+                if constexpr (DT == kF32) key = (tag == (uint32_t)q) ? raw[q] : key;
+                if constexpr (VM == kVals) val = (tag == (uint32_t)q) ? pv[q] : val;
+            }
+            kout[off + j] = key;
+            if constexpr (VM != kNoVals) vout[off + j] = val;
+        }
+    }
+}
+
+// ------------------------------------------------------------ wave tasks ---
+// One wavefront sorts one segment of at most 64*K keys.  wst: this wave's
+// private LDS staging (2 * 64 * K words) for position gathers.
+template <int DT, int K, bool STABLE, int VM>
+__device__ __forceinline__ void wave_task(const uint32_t* kin, const uint32_t* vin,
+                                          uint32_t* kout, uint32_t* vout, uint32_t off, int len,
+                                          uint32_t* wst) {
+    using T = typename TileTraits<DT, K, STABLE>::T;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int first = lane * K;
+    T v[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const bool live = first + j < len;
+        const uint32_t x = live ? kin[off + first + j] : 0u;
+        if constexpr (STABLE)
+            v[j] = live ? (((uint64_t)ord_key<DT>(x) << 32) | (uint32_t)(first + j)) : ~0ull;
+        else
+            v[j] = live ? ord_key<DT>(x) : 0xffffffffu;
+    }
+    leaf_network<T, K>(v);
+    wave_merge<T, K>(v, lane);
+    if constexpr (!STABLE) {
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (first + j < len) kout[off + first + j] = unord_key<DT>(v[j]);
+    } else {
+        constexpr bool kNeedBits = DT == kF32;
+        constexpr bool kNeedVals = VM == kVals;
+        uint32_t* sbits = wst;
+        uint32_t* svals = wst + kWave * K;
+        if constexpr (kNeedBits || kNeedVals) {
+            for (int i = lane; i < len; i += kWave) {
+                if constexpr (kNeedBits) sbits[i] = kin[off + i];
+                if constexpr (kNeedVals) svals[i] = vin[off + i];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            if (first + j < len) {
+                const uint32_t tag = (uint32_t)v[j];
+                uint32_t key;
+                if constexpr (kNeedBits) key = sbits[tag];
+                else key = unord_key<DT>((uint32_t)(v[j] >> 32));
+                kout[off + first + j] = key;
+                if constexpr (VM == kVals) vout[off + first + j] = svals[tag];
+                if constexpr (VM == kArg) vout[off + first + j] = tag;
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------- big tasks ---
+// Stable merge-path split in global memory (same rule as the flat passes).
+template <int DT>
+__device__ __forceinline__ int corank_global(const uint32_t* A, int la, const uint32_t* B, int lb,
+                                             int d) {
+    int lo = d > lb ? d - lb : 0;
+    int hi = d < la ? d : la;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (!(ord_key<DT>(B[d - 1 - mid]) < ord_key<DT>(A[mid])))
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// One merge pass over a whole segment by one workgroup: runs of L become
+// runs of 2L, kSegMergeTile outputs per step.
+template <int DT, bool VALS>
+__device__ void wg_merge_pass(const uint32_t* ks, const uint32_t* vs, uint32_t* kd, uint32_t* vd,
+                              int len, int L, void* smem) {
+    int32_t* sb = reinterpret_cast<int32_t*>(smem);
+    uint32_t* sk = reinterpret_cast<uint32_t*>(sb + kSegBoundWords);
+    uint32_t* sv = sk + lds_words<uint32_t>(kSegMergeTile);
+    const int tid = threadIdx.x;
+    const int ntiles = (len + kSegMergeTile - 1) / kSegMergeTile;
+    for (int t0 = 0; t0 < ntiles; t0 += kBlockThreads) {
+        const int nt = min(kBlockThreads, ntiles - t0);
+        if (tid <= nt && t0 + tid < ntiles) {
+            const int g0 = (t0 + tid) * kSegMergeTile;
+            const int base = g0 & ~(2 * L - 1);
+            const int la = min(L, len - base);
+            const int lb = min(L, len - base - la);
+            sb[tid] = corank_global<DT>(ks + base, la, ks + base + la, lb, g0 - base);
+        }
+        __syncthreads();
+        for (int t = t0; t < t0 + nt; ++t) {
+            const int g0 = t * kSegMergeTile;
+            const int base = g0 & ~(2 * L - 1);
+            const int la = min(L, len - base);
+            const int lb = min(L, len - base - la);
+            const int plen = la + lb;
+            const int d0 = g0 - base;
+            const int d1 = min(d0 + kSegMergeTile, plen);
+            const int i0 = sb[t - t0];
+            const int i1 = (d1 == plen) ? la : sb[t + 1 - t0];
+            const int na = i1 - i0;
+            const int cnt = d1 - d0;
+            const int nb = cnt - na;
+            const int j0 = d0 - i0;
+            for (int x = tid; x < cnt; x += kBlockThreads) {
+                const int src = x < na ? base + i0 + x : base + la + j0 + (x - na);
+                sk[lds_idx<uint32_t>(x)] = ks[src];
+                if constexpr (VALS) sv[lds_idx<uint32_t>(x)] = vs[src];
+            }
+            __syncthreads();
+            const int d = tid * kSegMergeKPT;
+            if (d < cnt) {
+                const int i = corank_lds(sk, 0, na, na, nb, d, OrdLess<DT>{});
+                uint32_t o[kSegMergeKPT];
+                int srcpos[kSegMergeKPT];
+                serial_merge<uint32_t, kSegMergeKPT, VALS>(sk, 0, na, na, nb, i, d - i, cnt - 1,
+                                                           o, srcpos, OrdLess<DT>{});
+#pragma unroll
+                for (int k = 0; k < kSegMergeKPT; ++k) {
+                    if (d + k < cnt) {
+                        kd[g0 + d + k] = o[k];
+                        if constexpr (VALS) vd[g0 + d + k] = sv[lds_idx<uint32_t>(srcpos[k])];
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+template <int DT, int K, bool STABLE, int VM>
+__device__ void big_task(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
+                         uint32_t* wk, uint32_t* wv, uint32_t off, int len, void* smem) {
+    constexpr int kTile = K * kBlockThreads;
+    const int chunks = (len + kTile - 1) / kTile;
+    int passes = 0;
+    while ((1 << passes) < chunks) ++passes;
+    uint32_t* kb[2] = {kout + off, wk + off};
+    uint32_t* vb[2] = {VM != kNoVals ? vout + off : nullptr, VM != kNoVals ? wv + off : nullptr};
+    int cur = passes & 1;
+    auto al = [](const void* p) { return ((uintptr_t)p & 15u) == 0; };
+    const bool vec = al(kin + off) && al(kb[0]) && al(kb[1]) &&
+                     (VM == kNoVals || (al(vb[0]) && al(vb[1]))) &&
+                     (VM != kVals || al(vin + off));
+    for (int c = 0; c < chunks; ++c) {
+        const int nv = min(kTile, len - c * kTile);
+        block_sort_tile<DT, K, STABLE, VM>(kin + off + c * kTile,
+                                           VM == kVals ? vin + off + c * kTile : nullptr,
+                                           kb[cur] + c * kTile,
+                                           VM != kNoVals ? vb[cur] + c * kTile : nullptr, nv,
+                                           (uint32_t)(c * kTile), smem, vec);
+        __syncthreads();
+    }
+    for (int p = 0; p < passes; ++p) {
+        const int L = kTile << p;
+        wg_merge_pass<DT, VM != kNoVals>(kb[cur], vb[cur], kb[cur ^ 1], vb[cur ^ 1], len, L, smem);
+        cur ^= 1;
+    }
+}
+
+// ------------------------------------------------------- persistent kernel ---
+template <int DT, int K, bool STABLE, int VM>
+struct SegTraits {
+    static constexpr size_t kTileLds = TileTraits<DT, K, STABLE>::kLdsBytes;
+    static constexpr size_t kWaveLds = (size_t)(kBlockThreads / kWave) * 2 * kWave * K * 4;
+    static constexpr size_t kMergeLds =
+        (size_t)kSegBoundWords * 4 +
+        (size_t)lds_words<uint32_t>(kSegMergeTile) * 4 * (VM != kNoVals ? 2 : 1);
+    static constexpr size_t kLds = kTileLds > kWaveLds
+                                       ? (kTileLds > kMergeLds ? kTileLds : kMergeLds)
+                                       : (kWaveLds > kMergeLds ? kWaveLds : kMergeLds);
+};
+
+template <int DT, int K, bool STABLE, int VM>
+__global__ __launch_bounds__(kBlockThreads) void k_segmented(
+    const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, uint32_t* wk,
+    uint32_t* wv, const uint32_t* __restrict__ offsets, int64_t num_segments, uint32_t uni_len,
+    SegState* st, const uint32_t* __restrict__ lists) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ uint32_t s_item;
+    const int tid = threadIdx.x;
+
+    const uint32_t n_lane = st->count[kCLane];
+    const uint32_t n_wave = st->count[kCWave];
+    const uint32_t n_block = st->count[kCBlock];
+    const uint32_t n_big1 = st->count[kCBig1];
+    const uint32_t n_big2 = st->count[kCBig2];
+    const uint32_t n_big3 = st->count[kCBig3];
+    constexpr uint32_t kWavesPerBlock = kBlockThreads / kWave;
+    const uint32_t wave_items = (n_wave + kWavesPerBlock - 1) / kWavesPerBlock;
+    const uint32_t lane_items = (n_lane + kBlockThreads - 1) / kBlockThreads;
+    // queue order: big3, big2, big1, block, wave items, lane items
+    const uint32_t e0 = n_big3;
+    const uint32_t e1 = e0 + n_big2;
+    const uint32_t e2 = e1 + n_big1;
+    const uint32_t e3 = e2 + n_block;
+    const uint32_t e4 = e3 + wave_items;
+    const uint32_t e5 = e4 + lane_items;
+    const uint32_t* L = lists;
+    const int64_t S = num_segments;
+
+    for (;;) {
+        if (tid == 0) s_item = atomicAdd(&st->head, 1u);
+        __syncthreads();
+        const uint32_t item = s_item;
+        __syncthreads();
+        if (item >= e5) break;
+        if (item < e3) {
+            uint32_t seg;
+            if (item < e0) seg = L[kCBig3 * S + item];
+            else if (item < e1) seg = L[kCBig2 * S + (item - e0)];
+            else if (item < e2) seg = L[kCBig1 * S + (item - e1)];
+            else seg = L[kCBlock * S + (item - e2)];
+            uint32_t off, len;
+            seg_bounds(offsets, seg, uni_len, off, len);
+            if (item < e2) {
+                big_task<DT, K, STABLE, VM>(kin, vin, kout, vout, wk, wv, off, (int)len, smem);
+            } else {
+                auto al = [](const void* p) { return ((uintptr_t)p & 15u) == 0; };
+                const bool vec = al(kin + off) && al(kout + off) &&
+                                 (VM == kNoVals || al(vout + off)) &&
+                                 (VM != kVals || al(vin + off));
+                block_sort_tile<DT, K, STABLE, VM>(kin + off, VM == kVals ? vin + off : nullptr,
+                                                   kout + off,
+                                                   VM != kNoVals ? vout + off : nullptr,
+                                                   (int)len, 0u, smem, vec);
+            }
+        } else if (item < e4) {
+            const uint32_t w = (uint32_t)tid / kWave;
+            const uint32_t idx = (item - e3) * kWavesPerBlock + w;
+            if (idx < n_wave) {
+                uint32_t off, len;
+                seg_bounds(offsets, L[kCWave * S + idx], uni_len, off, len);
+                uint32_t* wst = reinterpret_cast<uint32_t*>(smem) + (size_t)w * 2 * kWave * K;
+                wave_task<DT, K, STABLE, VM>(kin, vin, kout, vout, off, (int)len, wst);
+            }
+        } else {
+            const uint32_t idx = (item - e4) * kBlockThreads + (uint32_t)tid;
+            if (idx < n_lane) {
+                uint32_t off, len;
+                seg_bounds(offsets, L[kCLane * S + idx], uni_len, off, len);
+                lane_task<DT, K, STABLE, VM>(kin, vin, kout, vout, off, (int)len);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ host ---
+namespace {
+
+template <int DT, int K, bool STABLE, int VM>
+int launch_seg_kernel(const SegArgs& a, uint32_t* wk, uint32_t* wv, SegState* st,
+                      const uint32_t* lists, uint32_t uni_len) {
+    using Tr = SegTraits<DT, K, STABLE, VM>;
+    auto kern = &k_segmented<DT, K, STABLE, VM>;
+    if (int rc = set_dynamic_lds(reinterpret_cast<const void*>(kern), Tr::kLds)) return rc;
+    int grid = a.grid;
+    if (grid <= 0) {
+        static int cached = 0;
+        if (cached == 0) {
+            int dev = 0, cus = 0, per_cu = 0;
+            if (int rc = (int)hipGetDevice(&dev)) return rc;
+            if (int rc = (int)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
+                                                    dev))
+                return rc;
+            if (int rc = (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                    &per_cu, reinterpret_cast<const void*>(kern), kBlockThreads, Tr::kLds))
+                return rc;
+            cached = cus * (per_cu > 0 ? per_cu : 1);
+        }
+        grid = cached;
+    }
+    {
+        LaunchTimer timer("segmented", a.n_total, a.stream);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlockThreads), Tr::kLds, a.stream, a.kin,
+                           a.vin, a.kout, a.vout, wk, wv, a.offsets, a.num_segments, uni_len, st,
+                           lists);
+    }
+    return (int)hipGetLastError();
+}
+
+template <int DT, int K>
+int dispatch_seg(const SegArgs& a, uint32_t* wk, uint32_t* wv, SegState* st,
+                 const uint32_t* lists, uint32_t uni_len) {
+    if (a.vmode == kVals) return launch_seg_kernel<DT, K, true, kVals>(a, wk, wv, st, lists, uni_len);
+    if (a.vmode == kArg) return launch_seg_kernel<DT, K, true, kArg>(a, wk, wv, st, lists, uni_len);
+    if constexpr (DT == kF32)
+        return launch_seg_kernel<DT, K, true, kNoVals>(a, wk, wv, st, lists, uni_len);
+    else
+        return launch_seg_kernel<DT, K, false, kNoVals>(a, wk, wv, st, lists, uni_len);
+}
+
+}  // namespace
+
+int launch_segmented(const SegArgs& a) {
+    if (a.num_segments == 0 || a.n_total == 0) return 0;
+    const bool vals = a.vmode != kNoVals;
+    uint8_t* ws = static_cast<uint8_t*>(a.ws);
+    const size_t nk = align_up((size_t)a.n_total * 4, 256);
+    uint32_t* wk = reinterpret_cast<uint32_t*>(ws);
+    uint32_t* wv = vals ? reinterpret_cast<uint32_t*>(ws + nk) : nullptr;
+    uint32_t* lists = reinterpret_cast<uint32_t*>(ws + nk + (vals ? nk : 0));
+    SegState* st = reinterpret_cast<SegState*>(
+        ws + nk + (vals ? nk : 0) +
+        align_up((size_t)a.num_segments * 4 * kNumClasses, 256));
+    const uint32_t uni_len = a.offsets ? 0u : (uint32_t)(a.n_total / a.num_segments);
+
+    {
+        LaunchTimer timer("seg_init", 1, a.stream);
+        hipLaunchKernelGGL(k_seg_init, dim3(1), dim3(64), 0, a.stream, st);
+    }
+    if (int rc = (int)hipGetLastError()) return rc;
+    {
+        LaunchTimer timer("seg_bin", a.num_segments, a.stream);
+        hipLaunchKernelGGL(k_seg_bin, dim3((unsigned)((a.num_segments + 255) / 256)), dim3(256),
+                           0, a.stream, a.offsets, a.num_segments, uni_len, a.lane_max,
+                           a.wave_max, a.block_max, st, lists);
+    }
+    if (int rc = (int)hipGetLastError()) return rc;
+    switch (a.dtype) {
+        case kU32:
+            return a.leaf_k == 8 ? dispatch_seg<kU32, 8>(a, wk, wv, st, lists, uni_len)
+                                 : dispatch_seg<kU32, 4>(a, wk, wv, st, lists, uni_len);
+        case kI32:
+            return a.leaf_k == 8 ? dispatch_seg<kI32, 8>(a, wk, wv, st, lists, uni_len)
+                                 : dispatch_seg<kI32, 4>(a, wk, wv, st, lists, uni_len);
+        default:
+            return a.leaf_k == 8 ? dispatch_seg<kF32, 8>(a, wk, wv, st, lists, uni_len)
+                                 : dispatch_seg<kF32, 4>(a, wk, wv, st, lists, uni_len);
+    }
+}
+
+}  // namespace msn

@@ -1,0 +1,247 @@
+// Flat (single-array) sort: first sweep = block sort of K*1024-key tiles,
+// then global merge-path passes that double the run length until one run
+// remains (paper Sec. 3, Algorithm 1, run bottom-up).
+#include "block_tile.hpp"
+
+namespace msn {
+
+// ----------------------------------------------------------- first sweep ---
+template <int DT, int K, bool STABLE, int VM>
+__global__ __launch_bounds__(kBlockThreads) void k_block_sort(const uint32_t* kin,
+                                                              const uint32_t* vin,
+                                                              uint32_t* kout, uint32_t* vout,
+                                                              int64_t n, int vec) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int kTile = K * kBlockThreads;
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    const int nv = (int)((n - base) < kTile ? (n - base) : kTile);
+    block_sort_tile<DT, K, STABLE, VM>(kin + base, VM == kVals ? vin + base : nullptr,
+                                       kout + base, VM != kNoVals ? vout + base : nullptr, nv,
+                                       (uint32_t)base, smem, vec != 0);
+}
+
+// ------------------------------------------------------- merge-path split ---
+// For merge tile t of a pass that merges runs of length L: the number of
+// elements of the pair's left run among the tile's first output position.
+// One binary search per tile (Green, McColl, Bader 2012); stable (left run
+// wins ties).
+template <int DT>
+__global__ __launch_bounds__(256) void k_partition(const uint32_t* __restrict__ kin,
+                                                   int32_t* __restrict__ part, int64_t n,
+                                                   int64_t L, int mt, int ntiles) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntiles) return;
+    const int64_t g0 = (int64_t)t * mt;
+    const int64_t base = g0 & ~(2 * L - 1);
+    const int64_t la = (n - base) < L ? (n - base) : L;
+    const int64_t rest = n - base - la;
+    const int64_t lb = rest < L ? rest : L;
+    const int64_t d = g0 - base;
+    const uint32_t* A = kin + base;
+    const uint32_t* B = A + la;
+    int64_t lo = d > lb ? d - lb : 0;
+    int64_t hi = d < la ? d : la;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (!(ord_key<DT>(B[d - 1 - mid]) < ord_key<DT>(A[mid])))
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    part[t] = (int32_t)lo;
+}
+
+// ------------------------------------------------------ global merge pass ---
+// Workgroup t writes outputs [t*MT, (t+1)*MT) of the pass: it copies its
+// slices of the two runs (split points from k_partition) into LDS with
+// coalesced loads, each thread finds its own split inside the tile by merge
+// path and merges KPT outputs sequentially, and the results go out as
+// 16-byte stores.  Payloads are gathered from LDS by source position.
+template <int DT, int KPT, bool VALS>
+__global__ __launch_bounds__(kMergeThreads) void k_merge(const uint32_t* __restrict__ kin,
+                                                         const uint32_t* __restrict__ vin,
+                                                         uint32_t* __restrict__ kout,
+                                                         uint32_t* __restrict__ vout,
+                                                         const int32_t* __restrict__ part,
+                                                         int64_t n, int64_t L, int vec) {
+    constexpr int MT = KPT * kMergeThreads;
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint32_t* sk = reinterpret_cast<uint32_t*>(smem);
+    uint32_t* sv = sk + lds_words<uint32_t>(MT);
+
+    const int t = blockIdx.x;
+    const int64_t g0 = (int64_t)t * MT;
+    const int64_t base = g0 & ~(2 * L - 1);
+    const int64_t la = (n - base) < L ? (n - base) : L;
+    const int64_t rest = n - base - la;
+    const int64_t lb = rest < L ? rest : L;
+    const int64_t plen = la + lb;
+    const int64_t d0 = g0 - base;
+    const int64_t d1 = (d0 + MT) < plen ? (d0 + MT) : plen;
+    const int64_t i0 = part[t];
+    const int64_t i1 = (d1 == plen) ? la : (int64_t)part[t + 1];
+    const int na = (int)(i1 - i0);
+    const int cnt = (int)(d1 - d0);
+    const int nb = cnt - na;
+    const int64_t j0 = d0 - i0;
+    const uint32_t* A = kin + base + i0;
+    const uint32_t* B = kin + base + la + j0;
+
+    for (int x = threadIdx.x; x < cnt; x += kMergeThreads) {
+        sk[lds_idx<uint32_t>(x)] = x < na ? A[x] : B[x - na];
+        if constexpr (VALS) {
+            const uint32_t* VA = vin + base + i0;
+            const uint32_t* VB = vin + base + la + j0;
+            sv[lds_idx<uint32_t>(x)] = x < na ? VA[x] : VB[x - na];
+        }
+    }
+    __syncthreads();
+
+    const int d = threadIdx.x * KPT;
+    if (d >= cnt) return;
+    const int i = corank_lds(sk, 0, na, na, nb, d, OrdLess<DT>{});
+    uint32_t o[KPT];
+    int src[KPT];
+    serial_merge<uint32_t, KPT, VALS>(sk, 0, na, na, nb, i, d - i, cnt - 1, o, src,
+                                      OrdLess<DT>{});
+    uint32_t* ko = kout + g0 + d;
+    if (vec && d + KPT <= cnt) {
+#pragma unroll
+        for (int q = 0; q < KPT / 4; ++q)
+            *reinterpret_cast<uint4*>(ko + 4 * q) =
+                make_uint4(o[4 * q], o[4 * q + 1], o[4 * q + 2], o[4 * q + 3]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < KPT; ++k)
+            if (d + k < cnt) ko[k] = o[k];
+    }
+    if constexpr (VALS) {
+        uint32_t y[KPT];
+#pragma unroll
+        for (int k = 0; k < KPT; ++k) y[k] = sv[lds_idx<uint32_t>(min(src[k], cnt - 1))];
+        uint32_t* vo = vout + g0 + d;
+        if (vec && d + KPT <= cnt) {
+#pragma unroll
+            for (int q = 0; q < KPT / 4; ++q)
+                *reinterpret_cast<uint4*>(vo + 4 * q) =
+                    make_uint4(y[4 * q], y[4 * q + 1], y[4 * q + 2], y[4 * q + 3]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < KPT; ++k)
+                if (d + k < cnt) vo[k] = y[k];
+        }
+    }
+}
+
+// ------------------------------------------------------------------ host ---
+namespace {
+
+template <typename Kern>
+int ensure_lds(Kern kern, size_t bytes) {
+    return set_dynamic_lds(reinterpret_cast<const void*>(kern), bytes);
+}
+
+template <int DT, int K, bool STABLE, int VM>
+int launch_block_sort(const SortArgs& a, uint32_t* kdst, uint32_t* vdst, int vec) {
+    using Tr = TileTraits<DT, K, STABLE>;
+    auto kern = &k_block_sort<DT, K, STABLE, VM>;
+    if (int rc = ensure_lds(kern, Tr::kLdsBytes)) return rc;
+    const int64_t blocks = (a.n + Tr::kTile - 1) / Tr::kTile;
+    {
+        LaunchTimer timer("block_sort", a.n, a.stream);
+        hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kBlockThreads), Tr::kLdsBytes,
+                           a.stream, a.kin, a.vin, kdst, vdst, a.n, vec);
+    }
+    return (int)hipGetLastError();
+}
+
+template <int DT, int K>
+int dispatch_block_sort(const SortArgs& a, uint32_t* kdst, uint32_t* vdst, int vec) {
+    if (a.vmode == kVals) return launch_block_sort<DT, K, true, kVals>(a, kdst, vdst, vec);
+    if (a.vmode == kArg) return launch_block_sort<DT, K, true, kArg>(a, kdst, vdst, vec);
+    if constexpr (DT == kF32) return launch_block_sort<DT, K, true, kNoVals>(a, kdst, vdst, vec);
+    else return launch_block_sort<DT, K, false, kNoVals>(a, kdst, vdst, vec);
+}
+
+template <int DT, int KPT, bool VALS>
+int launch_merge(const SortArgs& a, const uint32_t* ks, const uint32_t* vs, uint32_t* kd,
+                 uint32_t* vd, int32_t* part, int64_t L, int vec) {
+    constexpr int MT = KPT * kMergeThreads;
+    const int ntiles = (int)((a.n + MT - 1) / MT);
+    {
+        LaunchTimer timer("partition", ntiles, a.stream);
+        hipLaunchKernelGGL(k_partition<DT>, dim3((ntiles + 255) / 256), dim3(256), 0, a.stream,
+                           ks, part, a.n, L, MT, ntiles);
+    }
+    if (int rc = (int)hipGetLastError()) return rc;
+    auto kern = &k_merge<DT, KPT, VALS>;
+    const size_t lds = (size_t)lds_words<uint32_t>(MT) * 4 * (VALS ? 2 : 1);
+    if (int rc = ensure_lds(kern, lds)) return rc;
+    {
+        LaunchTimer timer("merge", a.n, a.stream);
+        hipLaunchKernelGGL(kern, dim3(ntiles), dim3(kMergeThreads), lds, a.stream, ks, vs, kd, vd,
+                           part, a.n, L, vec);
+    }
+    return (int)hipGetLastError();
+}
+
+template <int DT, bool VALS>
+int dispatch_merge(const SortArgs& a, const uint32_t* ks, const uint32_t* vs, uint32_t* kd,
+                   uint32_t* vd, int32_t* part, int64_t L, int vec) {
+    switch (a.merge_tile) {
+        case 2048: return launch_merge<DT, 8, VALS>(a, ks, vs, kd, vd, part, L, vec);
+        case 8192: return launch_merge<DT, 32, VALS>(a, ks, vs, kd, vd, part, L, vec);
+        default: return launch_merge<DT, 16, VALS>(a, ks, vs, kd, vd, part, L, vec);
+    }
+}
+
+template <int DT>
+int run_sort(const SortArgs& a) {
+    const int tile = a.leaf_k * kBlockThreads;
+    const int64_t runs = (a.n + tile - 1) / tile;
+    int passes = 0;
+    while (((int64_t)1 << passes) < runs) ++passes;
+
+    const bool vals = a.vmode != kNoVals;
+    uint8_t* ws = static_cast<uint8_t*>(a.ws);
+    const size_t nk = align_up((size_t)a.n * 4, 256);
+    uint32_t* wk = reinterpret_cast<uint32_t*>(ws);
+    uint32_t* wv = vals ? reinterpret_cast<uint32_t*>(ws + nk) : nullptr;
+    int32_t* part = reinterpret_cast<int32_t*>(ws + nk + (vals ? nk : 0));
+
+    // Ping-pong so that the last pass lands in the output.
+    uint32_t* kb[2] = {a.kout, wk};
+    uint32_t* vb[2] = {a.vout, wv};
+    auto aligned = [](const void* p) { return ((uintptr_t)p & 15u) == 0; };
+    const int vec = aligned(a.kin) && aligned(a.kout) && aligned(wk) &&
+                    (!vals || (aligned(a.vout) && aligned(wv) &&
+                               (a.vmode != kVals || aligned(a.vin))));
+
+    int cur = passes & 1;
+    int rc = a.leaf_k == 8 ? dispatch_block_sort<DT, 8>(a, kb[cur], vb[cur], vec)
+                           : dispatch_block_sort<DT, 4>(a, kb[cur], vb[cur], vec);
+    if (rc) return rc;
+    for (int p = 0; p < passes; ++p) {
+        const int64_t L = (int64_t)tile << p;
+        const int nxt = cur ^ 1;
+        rc = vals ? dispatch_merge<DT, true>(a, kb[cur], vb[cur], kb[nxt], vb[nxt], part, L, vec)
+                  : dispatch_merge<DT, false>(a, kb[cur], nullptr, kb[nxt], nullptr, part, L,
+                                              vec);
+        if (rc) return rc;
+        cur = nxt;
+    }
+    return 0;
+}
+
+}  // namespace
+
+int launch_sort(const SortArgs& a) {
+    if (a.n == 0) return 0;
+    switch (a.dtype) {
+        case kU32: return run_sort<kU32>(a);
+        case kI32: return run_sort<kI32>(a);
+        default: return run_sort<kF32>(a);
+    }
+}
+
+}  // namespace msn

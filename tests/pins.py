@@ -269,6 +269,19 @@ def pin_backward(orc):
             assert abs(fd - gi[r, j]) <= 1e-5 * max(1.0, abs(fd)), (r, j, fd, gi[r, j])
 
 
+def pin_rank_bounds(orc):
+    """Rank bounds equal numpy's searchsorted on the sorted keys."""
+    rng = np.random.default_rng(11)
+    for dtype, x in (("u32", rng.integers(0, 50, 5000, dtype=np.uint32)),
+                     ("i32", rng.integers(-50, 50, 5000).astype(np.int32)),
+                     ("f32", (np.round(rng.standard_normal(5000) * 4) / 4).astype(np.float32))):
+        s = np.sort(x)
+        for v in list(x[:40]) + [s[0], s[-1]]:
+            lt, le = orc.rank_bounds(x, v, dtype=dtype)
+            assert lt == int(np.searchsorted(s, v, side="left")), (dtype, v)
+            assert le == int(np.searchsorted(s, v, side="right")), (dtype, v)
+
+
 ALL_PINS = [
     pin_network_zero_one,
     pin_network_permutations,
@@ -282,4 +295,5 @@ ALL_PINS = [
     pin_segmented,
     pin_row_argsort,
     pin_backward,
+    pin_rank_bounds,
 ]

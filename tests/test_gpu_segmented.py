@@ -1,0 +1,183 @@
+"""Segmented sort (one persistent launch) against the oracle, bit-exact."""
+import itertools
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2503_05934_amd as msn
+from paper_2503_05934_amd import workloads
+from gpu_util import bits, float_keys, gpu, host, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def orc():
+    return oracle.load()
+
+
+def offsets_of(lengths):
+    return np.concatenate([[0], np.cumsum(lengths)]).astype(np.uint32)
+
+
+# every work class: empty, lane (<= 8), wave (<= 512), block (<= 8192), and
+# the three big classes (<= 2x, <= 4x, > 4x of a block)
+CLASS_LENGTHS = [0, 1, 2, 3, 5, 8, 9, 17, 100, 255, 256, 511, 512, 513, 2000, 4096, 8191, 8192,
+                 8193, 12000, 16384, 16385, 30000, 32768, 32769, 65536, 0, 7, 0, 4, 3]
+
+
+def mixed_lengths(seed, count=600):
+    rng = np.random.default_rng(seed)
+    lengths = np.floor(np.exp(rng.uniform(0, np.log(70000), count))).astype(np.int64)
+    lengths[rng.random(count) < 0.1] = 0
+    return np.concatenate([CLASS_LENGTHS, lengths])
+
+
+def seg_keys(total, dtype, seed):
+    if dtype == "f32":
+        return float_keys(total, seed)
+    rng = np.random.default_rng(seed)
+    hi = 2**31 if dtype == "i32" else 2**32
+    x = rng.integers(0, hi, total, dtype=np.int64)
+    x[rng.random(total) < 0.3] = 12345  # ties
+    return x.astype(np.int32 if dtype == "i32" else np.uint32)
+
+
+@pytest.mark.parametrize("leaf", ["6To8", "3To5"])
+@pytest.mark.parametrize("dtype", ["i32", "u32", "f32"])
+def test_segmented_all_classes(orc, dtype, leaf):
+    lengths = mixed_lengths(seed=len(dtype) + 3 * (leaf == "3To5"), count=120)
+    off = offsets_of(lengths)
+    x = seg_keys(int(off[-1]), dtype, seed=4)
+    say(f"segmented keys dtype={dtype} leaf={leaf} S={len(lengths)} n={int(off[-1])}")
+    y = msn.segmented_sort(gpu(x), gpu(off), leaf=leaf)
+    ref = orc.segmented_sort(x, off, dtype=dtype, stable=True)
+    assert np.array_equal(bits(host(y)), bits(ref))
+
+    v = np.random.default_rng(8).integers(0, 2**32, x.shape[0], dtype=np.uint32)
+    say(f"segmented pairs dtype={dtype} leaf={leaf}")
+    ko, vo = msn.segmented_sort(gpu(x), gpu(off), gpu(v), leaf=leaf)
+    rk, rv = orc.segmented_sort(x, off, vals=v, dtype=dtype, stable=True)
+    assert np.array_equal(bits(host(ko)), bits(rk))
+    assert np.array_equal(host(vo), rv)
+
+    say(f"segmented argsort dtype={dtype} leaf={leaf}")
+    ko, po = msn.segmented_sort(gpu(x), gpu(off), argsort=True, leaf=leaf)
+    _, rp = orc.segmented_sort(x, off, dtype=dtype, stable=True, want_perm=True)
+    assert np.array_equal(bits(host(ko)), bits(rk))
+    assert np.array_equal(host(po).view(np.uint32), rp)
+
+
+def test_segmented_batched_recipe(orc):
+    # the batched workload's recipe (log-uniform 3..65536, 30 % presorted) at
+    # 1,500 segments so the oracle finishes in seconds
+    x, off, _ = workloads.segments(1500, seed=0)
+    say(f"segmented recipe S=1500 n={x.shape[0]}")
+    y = msn.segmented_sort(gpu(x), gpu(off))
+    ref = orc.segmented_sort(x, off, dtype="i32", config="Classical")
+    assert np.array_equal(host(y), ref)
+
+
+@pytest.mark.parametrize("leaf", ["6To8", "3To5"])
+def test_thresholds_do_not_change_bits(orc, leaf):
+    k = 8 if leaf == "6To8" else 4
+    lengths = mixed_lengths(seed=11, count=200)
+    off = offsets_of(lengths)
+    x = seg_keys(int(off[-1]), "i32", seed=12)
+    ref = orc.segmented_sort(x, off, dtype="i32")
+    for tun in ({}, {"seg_lane_max": 1}, {"seg_lane_max": 1, "seg_wave_max": 1},
+                {"seg_lane_max": 1, "seg_wave_max": 1, "seg_block_max": 1},
+                {"seg_wave_max": 64 * k, "seg_block_max": 1024 * k, "seg_grid": 3}):
+        say(f"segmented thresholds leaf={leaf} tuning={tun}")
+        y = msn.segmented_sort(gpu(x), gpu(off), leaf=leaf, tuning=tun)
+        assert np.array_equal(host(y), ref), tun
+
+
+@pytest.mark.parametrize("leaf", ["6To8", "3To5"])
+def test_networks_exhaustive_on_gpu(leaf):
+    """Every permutation and every 0-1 input of up to 8 keys, one segment
+    each: on the lane path this is the leaf network alone (0-1 principle)."""
+    segs = []
+    for n in range(0, 9):
+        segs += [np.array(p, dtype=np.int32) for p in itertools.permutations(range(n))]
+        segs += [np.array(t, dtype=np.int32) for t in itertools.product([0, 1], repeat=n)]
+    lengths = np.array([len(s) for s in segs])
+    off = offsets_of(lengths)
+    x = np.concatenate(segs).astype(np.int32)
+    ref = np.concatenate([np.sort(s) for s in segs]).astype(np.int32)
+    for tun in ({}, {"seg_lane_max": 1}, {"seg_lane_max": 1, "seg_wave_max": 1}):
+        say(f"exhaustive networks leaf={leaf} tuning={tun} S={len(segs)}")
+        y = msn.segmented_sort(gpu(x), gpu(off), leaf=leaf, tuning=tun)
+        assert np.array_equal(host(y), ref), tun
+        ko, po = msn.segmented_sort(gpu(x), gpu(off), argsort=True, leaf=leaf, tuning=tun)
+        refp = np.concatenate([np.argsort(s, kind="stable") for s in segs]).astype(np.int32)
+        assert np.array_equal(host(po), refp), tun
+
+
+def test_equal_rows_without_offsets(orc):
+    rows, cols = 37, 3000
+    x = seg_keys(rows * cols, "u32", seed=3)
+    off = (np.arange(rows + 1) * cols).astype(np.uint32)
+    say("segmented equal rows (offsets=None)")
+    y = msn.segmented_sort(gpu(x), None, num_segments=rows)
+    assert np.array_equal(host(y), orc.segmented_sort(x, off, dtype="u32"))
+
+
+def test_only_empty_and_tiny_segments(orc):
+    lengths = np.array([0] * 50 + [1] * 50 + [0, 2, 0, 3])
+    off = offsets_of(lengths)
+    x = seg_keys(int(off[-1]), "i32", seed=1)
+    say("segmented tiny segments")
+    y = msn.segmented_sort(gpu(x), gpu(off))
+    assert np.array_equal(host(y), orc.segmented_sort(x, off, dtype="i32"))
+
+
+def test_segmented_in_place(orc):
+    lengths = mixed_lengths(seed=5, count=80)
+    off = offsets_of(lengths)
+    x = seg_keys(int(off[-1]), "f32", seed=6)
+    rk, rp = orc.segmented_sort(x, off, dtype="f32", stable=True, want_perm=True)
+    t = gpu(x)
+    say("segmented in place keys")
+    msn.segmented_sort(t, gpu(off), out_keys=t)
+    assert np.array_equal(bits(host(t)), bits(rk))
+    t = gpu(x)
+    v = gpu(np.arange(x.shape[0], dtype=np.uint32))
+    say("segmented in place pairs")
+    msn.segmented_sort(t, gpu(off), v, out_keys=t, out_vals=v)
+    glob = np.concatenate([off[s] + rp[off[s]:off[s + 1]] for s in range(len(lengths))])
+    assert np.array_equal(bits(host(t)), bits(rk))
+    assert np.array_equal(host(v), glob.astype(np.uint32))
+
+
+def test_hip_graph_replays_match_eager(orc):
+    lengths = mixed_lengths(seed=9, count=150)
+    off = offsets_of(lengths)
+    x = seg_keys(int(off[-1]), "i32", seed=10)
+    ref = orc.segmented_sort(x, off, dtype="i32")
+    kin, offs = gpu(x), gpu(off)
+    out = torch.empty_like(kin)
+    n, S = x.shape[0], len(lengths)
+    from paper_2503_05934_amd import _lib
+    ws = torch.empty(_lib.segmented_workspace_bytes(n, S, 1, False), dtype=torch.uint8,
+                     device=kin.device)
+    say("segmented eager before capture")
+    msn.segmented_sort(kin, offs, out_keys=out, workspace=ws)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(out), ref)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    say("segmented graph capture")
+    with torch.cuda.graph(g, stream=s):
+        msn.segmented_sort(kin, offs, out_keys=out, workspace=ws)
+    for r in range(4):
+        out.zero_()
+        ws.fill_(0xAB)
+        torch.cuda.synchronize()
+        say(f"graph replay {r}")
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(host(out), ref), r

@@ -1,0 +1,134 @@
+"""Flat sorts on the GPU against the oracle, element by element (bit-exact)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2503_05934_amd as msn
+from paper_2503_05934_amd import workloads
+from gpu_util import BOUNDARY_SIZES, bits, gpu, host, make_keys, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def orc():
+    return oracle.load()
+
+
+@pytest.mark.parametrize("leaf", ["6To8", "3To5"])
+@pytest.mark.parametrize("dtype", ["u32", "i32", "f32"])
+def test_sort_keys_boundary_sizes(orc, dtype, leaf):
+    for n in BOUNDARY_SIZES:
+        x = make_keys(n, dtype, seed=n)
+        say(f"sort_keys dtype={dtype} leaf={leaf} n={n}")
+        y = host(msn.sort(gpu(x), leaf=leaf))
+        ref = orc.sort(x, dtype=dtype, stable=True, config=leaf)
+        assert np.array_equal(bits(y), bits(ref)), (dtype, leaf, n)
+
+
+def test_cfg1_10k_int32(orc):
+    x = workloads.keys(10_000, "random", "i32", 0)
+    say("sort_keys 10,000 int32 seed 0")
+    y = host(msn.sort(gpu(x), leaf="6To8"))
+    assert np.array_equal(y, orc.sort(x, dtype="i32", config="6To8"))
+
+
+_CFG2 = {}
+
+
+@pytest.mark.parametrize("leaf", ["6To8", "3To5"])
+@pytest.mark.parametrize("dist", workloads.DISTRIBUTIONS)
+def test_cfg2_1m_int32(orc, dist, leaf):
+    x = workloads.keys(1_000_000, dist, "i32", 0)
+    if dist not in _CFG2:
+        _CFG2[dist] = orc.sort(x, dtype="i32", config="6To8")
+    say(f"sort_keys 1e6 int32 dist={dist} leaf={leaf}")
+    y = host(msn.sort(gpu(x), leaf=leaf))
+    assert np.array_equal(y, _CFG2[dist])
+
+
+@pytest.mark.parametrize("leaf", ["6To8", "3To5"])
+@pytest.mark.parametrize("dtype", ["u32", "i32", "f32"])
+def test_sort_pairs_stable(orc, dtype, leaf):
+    rng = np.random.default_rng(21)
+    for n in [1, 7, 9, 513, 8191, 8193, 40000, 262145]:
+        if dtype == "f32":
+            k = make_keys(n, "f32", seed=n)
+        else:
+            k = rng.integers(0, 64, n).astype(np.uint32 if dtype == "u32" else np.int32)
+            if dtype == "i32":
+                k -= 32
+        v = rng.integers(0, 2**32, n, dtype=np.uint32)
+        say(f"sort_pairs dtype={dtype} leaf={leaf} n={n}")
+        ko, vo = msn.sort_pairs(gpu(k), gpu(v), leaf=leaf)
+        rk, rv = orc.sort(k, vals=v, dtype=dtype, stable=True, config=leaf)
+        assert np.array_equal(bits(host(ko)), bits(rk)), (dtype, n)
+        assert np.array_equal(host(vo), rv), (dtype, n)
+        say(f"argsort dtype={dtype} leaf={leaf} n={n}")
+        ko, po = msn.sort_pairs(gpu(k), None, leaf=leaf)
+        _, rp = orc.sort(k, dtype=dtype, stable=True, config=leaf, want_perm=True)
+        assert np.array_equal(bits(host(ko)), bits(rk))
+        assert np.array_equal(host(po).view(np.uint32), rp), (dtype, n)
+
+
+def test_pairs_many_ties_payload_index(orc):
+    n = (1 << 21) + 4097
+    k, v = workloads.pairs(n, seed=3)
+    say(f"sort_pairs keys<2^16 payload=index n={n}")
+    ko, vo = msn.sort_pairs(gpu(k), gpu(v))
+    rk, rv = orc.sort(k, vals=v, dtype="u32", stable=True)
+    assert np.array_equal(host(ko), rk)
+    assert np.array_equal(host(vo), rv)
+
+
+@pytest.mark.parametrize("dtype", ["u32", "f32"])
+def test_in_place(orc, dtype):
+    for n in [5000, 8192 * 3 + 1, 100000]:
+        x = make_keys(n, dtype, seed=7 + n)
+        ref = orc.sort(x, dtype=dtype, stable=True)
+        say(f"sort_keys in place dtype={dtype} n={n}")
+        t = gpu(x)
+        msn.sort(t, out=t)
+        assert np.array_equal(bits(host(t)), bits(ref))
+        say(f"sort_pairs in place dtype={dtype} n={n}")
+        t = gpu(x)
+        vals = gpu(np.arange(n, dtype=np.uint32))
+        msn.sort_pairs(t, vals, out_keys=t, out_vals=vals)
+        _, rp = orc.sort(x, dtype=dtype, stable=True, want_perm=True)
+        assert np.array_equal(bits(host(t)), bits(ref))
+        assert np.array_equal(host(vals), rp)
+
+
+def test_merge_tiles_give_identical_bits(orc):
+    n = 300007
+    x = make_keys(n, "u32", seed=5)
+    ref = orc.sort(x, dtype="u32")
+    for mt in (2048, 4096, 8192):
+        say(f"sort_keys merge_tile={mt}")
+        y = host(msn.sort(gpu(x), tuning={"merge_tile": mt}))
+        assert np.array_equal(y, ref), mt
+        say(f"sort_pairs merge_tile={mt}")
+        k, v = workloads.pairs(n, seed=9, key_hi=1000)
+        ko, vo = msn.sort_pairs(gpu(k), gpu(v), tuning={"merge_tile": mt})
+        rk, rv = orc.sort(k, vals=v, stable=True)
+        assert np.array_equal(host(ko), rk) and np.array_equal(host(vo), rv), mt
+
+
+def test_unaligned_views(orc):
+    # offsets by one element: 4-byte aligned, not 16-byte aligned
+    n = 50001
+    x = make_keys(n + 1, "i32", seed=1)
+    t = gpu(x)[1:]
+    say("sort_keys on a view offset by one element")
+    y = host(msn.sort(t))
+    assert np.array_equal(y, orc.sort(x[1:], dtype="i32"))
+
+
+def test_sort_is_deterministic():
+    x = gpu(make_keys(1 << 20, "f32", seed=2))
+    say("sort_pairs f32 twice")
+    a = msn.sort_pairs(x)
+    b = msn.sort_pairs(x)
+    assert torch.equal(a[0].view(torch.int32), b[0].view(torch.int32))
+    assert torch.equal(a[1], b[1])
