@@ -198,7 +198,7 @@ def bench_keys(args):
         "config": {"workload": f"sort_keys: 2^{int(np.log2(n))} uint32 keys, uniform random "
                                f"over [0, 2^32), seed 0, {leaf} leaves",
                    "n": n, "leaf": leaf, "dist": args.dists[0],
-                   "merge_tile": args.merge_tile or 4096},
+                   "merge_tile": args.merge_tile or 8192},
         "roofline": roof,
         "hbm_schedule": {"bytes_per_key": sched,
                          "implied_gkeys_at_peak": HBM_PEAK_GBPS / sched,

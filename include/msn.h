@@ -73,7 +73,7 @@ extern "C" {
  * Optional tuning.  Pass NULL for the defaults.  A zero field means "default".
  * Every accepted setting yields the same bits; only speed differs.
  *   merge_tile      outputs per workgroup in a global merge pass:
- *                   2048, 4096 or 8192 (default 4096).
+ *                   2048, 4096 or 8192 (default 8192).
  *   seg_lane_max    segments of at most this many keys are sorted by one lane
  *                   with one network: 0..8 (default: the leaf size).
  *   seg_wave_max    segments up to this length are sorted by one wavefront:

@@ -57,7 +57,7 @@ struct SegArgs {
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 constexpr int kMinMergeTile = 2048;
-constexpr int kDefaultMergeTile = 4096;
+constexpr int kDefaultMergeTile = 8192;
 
 // Workspace of the flat sort: ping-pong keys (+ values) and one merge-path
 // split per merge tile.

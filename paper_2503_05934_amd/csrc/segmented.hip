@@ -224,10 +224,23 @@ __device__ void wg_merge_pass(const uint32_t* ks, const uint32_t* vs, uint32_t* 
             const int cnt = d1 - d0;
             const int nb = cnt - na;
             const int j0 = d0 - i0;
-            for (int x = tid; x < cnt; x += kBlockThreads) {
-                const int src = x < na ? base + i0 + x : base + la + j0 + (x - na);
-                sk[lds_idx<uint32_t>(x)] = ks[src];
-                if constexpr (VALS) sv[lds_idx<uint32_t>(x)] = vs[src];
+            {
+                uint32_t rk[kSegMergeKPT], rv[kSegMergeKPT];
+#pragma unroll
+                for (int q = 0; q < kSegMergeKPT; ++q) {
+                    const int x = min(tid + q * kBlockThreads, cnt - 1);
+                    const int src = x < na ? base + i0 + x : base + la + j0 + (x - na);
+                    rk[q] = ks[src];
+                    if constexpr (VALS) rv[q] = vs[src];
+                }
+#pragma unroll
+                for (int q = 0; q < kSegMergeKPT; ++q) {
+                    const int x = tid + q * kBlockThreads;
+                    if (x < cnt) {
+                        sk[lds_idx<uint32_t>(x)] = rk[q];
+                        if constexpr (VALS) sv[lds_idx<uint32_t>(x)] = rv[q];
+                    }
+                }
             }
             __syncthreads();
             const int d = tid * kSegMergeKPT;
