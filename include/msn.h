@@ -77,7 +77,7 @@ extern "C" {
  *   seg_lane_max    segments of at most this many keys are sorted by one lane
  *                   with one network: 0..8 (default: the leaf size).
  *   seg_wave_max    segments up to this length are sorted by one wavefront:
- *                   up to 64 x leaf size (default 64 x leaf size).
+ *                   up to 128 x leaf size (default 128 x leaf size).
  *   seg_block_max   segments up to this length are sorted by one workgroup
  *                   in LDS: up to 1024 x leaf size (default 1024 x leaf).
  *   seg_grid        workgroups of the persistent segmented kernel

@@ -240,14 +240,15 @@ int msn_segmented_sort(const void* keys_in, const uint32_t* vals_in, void* keys_
     if (num_segments == 0) return n_total == 0 ? MSN_OK : MSN_ERR_SIZE;
     if (!offsets && n_total % num_segments != 0) return MSN_ERR_SIZE;
 
-    const int tile = k * msn::kBlockThreads;
-    int lane_max = k, wave_max = msn::kWave * k, block_max = tile, grid = 0;
+    const int tile = 2 * k * msn::kBlockThreads;    // 2k keys per lane in a workgroup
+    const int wave_tile = 2 * k * msn::kWave;
+    int lane_max = k, wave_max = wave_tile, block_max = tile, grid = 0;
     if (tuning) {
         if (tuning->seg_lane_max) lane_max = tuning->seg_lane_max;
         if (tuning->seg_wave_max) wave_max = tuning->seg_wave_max;
         if (tuning->seg_block_max) block_max = tuning->seg_block_max;
         grid = tuning->seg_grid;
-        if (lane_max < 0 || lane_max > k || wave_max < lane_max || wave_max > msn::kWave * k ||
+        if (lane_max < 0 || lane_max > k || wave_max < lane_max || wave_max > wave_tile ||
             block_max < wave_max || block_max > tile || grid < 0)
             return MSN_ERR_CONFIG;
     }

@@ -1,5 +1,5 @@
-// Workgroup-wide sort of one tile of up to K * 1024 keys (steps a1-a4: key
-// map, per-lane network, wavefront bitonic merge, LDS merge path).  Used by
+// Workgroup-wide sort of one tile of up to 2K * 512 keys (steps a1-a4: key
+// map, per-lane networks, wavefront bitonic merge, LDS merge path).  Used by
 // the flat sort's first sweep and by the segmented kernel for segments that
 // fit one workgroup.
 #pragma once
@@ -14,12 +14,14 @@ namespace msn {
 template <int DT, int K, bool STABLE>
 struct TileTraits {
     using T = std::conditional_t<STABLE, uint64_t, uint32_t>;
-    static constexpr int kTile = K * kBlockThreads;
-    static constexpr size_t kLdsBytes = (size_t)lds_words<T>(kTile) * sizeof(T);
+    static constexpr int kKPL = keys_per_lane<K>();
+    static constexpr int kTile = kKPL * kBlockThreads;
+    static constexpr size_t kLdsBytes =
+        (size_t)block_lds_words<T, kKPL>(kTile) * sizeof(T);
     static_assert(!STABLE || kLdsBytes >= (size_t)2 * kTile * 4, "staging must fit");
 };
 
-// Sorts kin[0..nv) into kout[0..nv) (nv <= K*1024).  STABLE sorts
+// Sorts kin[0..nv) into kout[0..nv) (nv <= 2K*512).  STABLE sorts
 // (key, position) composites; VM selects the payload: vout[i] = vin[p(i)]
 // (kVals) or val_base + p(i) (kArg), p(i) = tile position of output i.  Float
 // keys are copied bit for bit from the input.  All threads of the workgroup
@@ -36,12 +38,13 @@ __device__ __forceinline__ void block_sort_tile(const uint32_t* kin, const uint3
     static_assert(STABLE || (DT != kF32 && VM == kNoVals), "float keys and pairs sort stably");
     T* s = reinterpret_cast<T*>(smem);
     const int tid = threadIdx.x;
-    const int first = tid * K;
+    constexpr int KPL = Tr::kKPL;
+    const int first = tid * KPL;
 
-    uint32_t x[K];
-    if (vec && first + K <= nv) {
+    uint32_t x[KPL];
+    if (vec && first + KPL <= nv) {
 #pragma unroll
-        for (int q = 0; q < K / 4; ++q) {
+        for (int q = 0; q < KPL / 4; ++q) {
             const uint4 w = *reinterpret_cast<const uint4*>(kin + first + 4 * q);
             x[4 * q + 0] = w.x;
             x[4 * q + 1] = w.y;
@@ -50,11 +53,11 @@ __device__ __forceinline__ void block_sort_tile(const uint32_t* kin, const uint3
         }
     } else {
 #pragma unroll
-        for (int j = 0; j < K; ++j) x[j] = (first + j < nv) ? kin[first + j] : 0u;
+        for (int j = 0; j < KPL; ++j) x[j] = (first + j < nv) ? kin[first + j] : 0u;
     }
-    T v[K];
+    T v[KPL];
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
+    for (int j = 0; j < KPL; ++j) {
         if constexpr (STABLE) {
             v[j] = (first + j < nv)
                        ? (((uint64_t)ord_key<DT>(x[j]) << 32) | (uint32_t)(first + j))
@@ -64,20 +67,20 @@ __device__ __forceinline__ void block_sort_tile(const uint32_t* kin, const uint3
         }
     }
 
-    const int span = span_for(nv, kWave * K);
+    const int span = span_for(nv, kWave * KPL);
     block_sort_regs<T, K>(v, s, span);
 
     if constexpr (!STABLE) {
 #pragma unroll
-        for (int j = 0; j < K; ++j) x[j] = unord_key<DT>(v[j]);
-        if (vec && first + K <= nv) {
+        for (int j = 0; j < KPL; ++j) x[j] = unord_key<DT>(v[j]);
+        if (vec && first + KPL <= nv) {
 #pragma unroll
-            for (int q = 0; q < K / 4; ++q)
+            for (int q = 0; q < KPL / 4; ++q)
                 *reinterpret_cast<uint4*>(kout + first + 4 * q) =
                     make_uint4(x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3]);
         } else {
 #pragma unroll
-            for (int j = 0; j < K; ++j)
+            for (int j = 0; j < KPL; ++j)
                 if (first + j < nv) kout[first + j] = x[j];
         }
     } else {
@@ -94,9 +97,9 @@ __device__ __forceinline__ void block_sort_tile(const uint32_t* kin, const uint3
             }
         }
         __syncthreads();
-        uint32_t y[K];
+        uint32_t y[KPL];
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
+        for (int j = 0; j < KPL; ++j) {
             const uint32_t tag = (uint32_t)v[j];
             const bool live = first + j < nv;
             const uint32_t t = live ? tag : 0u;
@@ -105,9 +108,9 @@ __device__ __forceinline__ void block_sort_tile(const uint32_t* kin, const uint3
             if constexpr (VM == kVals) y[j] = svals[t];
             else y[j] = val_base + t;
         }
-        if (vec && first + K <= nv) {
+        if (vec && first + KPL <= nv) {
 #pragma unroll
-            for (int q = 0; q < K / 4; ++q) {
+            for (int q = 0; q < KPL / 4; ++q) {
                 *reinterpret_cast<uint4*>(kout + first + 4 * q) =
                     make_uint4(x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3]);
                 if constexpr (VM != kNoVals)
@@ -116,7 +119,7 @@ __device__ __forceinline__ void block_sort_tile(const uint32_t* kin, const uint3
             }
         } else {
 #pragma unroll
-            for (int j = 0; j < K; ++j)
+            for (int j = 0; j < KPL; ++j)
                 if (first + j < nv) {
                     kout[first + j] = x[j];
                     if constexpr (VM != kNoVals) vout[first + j] = y[j];

@@ -95,13 +95,34 @@ __device__ __forceinline__ void leaf_network(T (&v)[K]) {
 }
 
 // -------------------------------------------------------- lane exchanges ---
-// Value of x in lane (lane ^ mask).  xor masks below 32 use ds_swizzle's
-// bit-mode (and = 0x1f, xor = mask), which stays inside 32-lane halves; 32
-// uses ds_bpermute across the halves.  Neither touches LDS memory.
+// Value of x in lane (lane ^ mask).  Patterns that DPP can express inside a
+// row of 16 lanes go through the VALU's data-parallel-primitive moves:
+// quad_perm for masks 1, 2, 3, row_ror:8 for 8, row_half_mirror (lane i <-
+// 7 - i) for 7 and row_mirror (i <- 15 - i) for 15.  Other masks below 32 use
+// ds_swizzle's bit mode (and = 0x1f, xor = mask) inside 32-lane halves, and
+// masks of 32 and above use ds_bpermute.  None of them touches LDS memory.
 template <int MASK>
 __device__ __forceinline__ uint32_t xor_lane(uint32_t x) {
     static_assert(MASK > 0 && MASK < 64, "mask");
-    if constexpr (MASK < 32) {
+    constexpr int kQuadXor1 = 0xb1;   // quad_perm [1,0,3,2]
+    constexpr int kQuadXor2 = 0x4e;   // quad_perm [2,3,0,1]
+    constexpr int kQuadXor3 = 0x1b;   // quad_perm [3,2,1,0]
+    constexpr int kRowRor8 = 0x128;
+    constexpr int kRowMirror = 0x140;
+    constexpr int kRowHalfMirror = 0x141;
+    if constexpr (MASK == 1) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, kQuadXor1, 0xf, 0xf, true);
+    } else if constexpr (MASK == 2) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, kQuadXor2, 0xf, 0xf, true);
+    } else if constexpr (MASK == 3) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, kQuadXor3, 0xf, 0xf, true);
+    } else if constexpr (MASK == 7) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, kRowHalfMirror, 0xf, 0xf, true);
+    } else if constexpr (MASK == 8) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, kRowRor8, 0xf, 0xf, true);
+    } else if constexpr (MASK == 15) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, kRowMirror, 0xf, 0xf, true);
+    } else if constexpr (MASK < 32) {
         return (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, (MASK << 10) | 0x1f);
     } else {
         const int src = ((int)(threadIdx.x & 63) ^ MASK) << 2;
@@ -238,36 +259,114 @@ struct OrdLess {
     }
 };
 
+// Largest value of a register key: the padding of short runs and the
+// sentinel that closes every LDS run.
+template <typename T>
+__device__ __forceinline__ constexpr T key_max() {
+    return sizeof(T) == 8 ? (T)~0ull : (T)0xffffffffu;
+}
+
+// Sequential merge of N outputs from LDS runs that are each followed by at
+// least N copies of key_max(): no bounds checks are needed, because a used-up
+// run offers the maximum, which is taken only when the other run's key is the
+// maximum too (the same value; composite keys never reach it).  pa, pb:
+// (unpadded) positions of the next key of each run.
+template <typename T, int N>
+__device__ __forceinline__ void serial_merge_closed(const T* s, int pa, int pb, T (&out)[N]) {
+    const int sum0 = pa + pb;  // grows by one per output
+    T a = s[lds_idx<T>(pa)];
+    T b = s[lds_idx<T>(pb)];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const bool take_a = !(b < a);
+        out[k] = take_a ? a : b;
+        pa += take_a ? 1 : 0;
+        const int p = take_a ? pa : sum0 + k + 1 - pa;
+        const T x = s[lds_idx<T>(p)];
+        a = take_a ? x : a;
+        b = take_a ? b : x;
+    }
+}
+
+// Two sorted runs v[0..H) and v[H..2H) in one lane -> one sorted run
+// (bitonic: flip, then half-cleaners inside each half).
+template <typename T, int N>
+__device__ __forceinline__ void lane_merge_halves(T (&v)[N]) {
+    constexpr int H = N / 2;
+#pragma unroll
+    for (int j = 0; j < H; ++j) cx(v[j], v[N - 1 - j]);
+#pragma unroll
+    for (int d = H / 2; d >= 1; d >>= 1) {
+#pragma unroll
+        for (int j = 0; j < N; ++j)
+            if ((j & d) == 0) cx(v[j], v[j + d]);
+    }
+}
+
 // --------------------------------------------------------- block sorting ---
-// Sorts the K*kBlockThreads keys held as v[] by all threads of a workgroup
-// (thread t holds keys t*K .. t*K+K-1, already in registers).  `span` (a power
-// of two, at least 64*K) is how many leading keys matter: lanes beyond it
-// still take part in barriers but skip the work.  On return thread t holds
-// outputs t*K .. t*K+K-1 of the sorted span.  s is LDS of lds_words<T>(K *
-// kBlockThreads) words.
+// Keys per lane in the block sort: two base-case groups of K keys.
+template <int K>
+constexpr int keys_per_lane() { return 2 * K; }
+
+// LDS words block_sort_regs needs for a tile of n keys: the keys, KPL
+// sentinels after each of the (at most n / (64*KPL)) runs, and padding.
+template <typename T, int KPL>
+__host__ __device__ constexpr int block_lds_words(int n) {
+    return lds_words<T>(n + (n / (kWave * KPL)) * KPL + KPL);
+}
+
+// Sorts the KPL*kBlockThreads keys held as v[] by all threads of a workgroup
+// (thread t holds keys t*KPL .. t*KPL+KPL-1 in registers, KPL = 2K).  Each
+// lane applies the K-key network to both of its groups and merges them; the
+// wavefront merges its 64 lane runs by bitonic exchanges; then LDS merge-path
+// levels double the run length up to `span` (a power of two, at least
+// 64*KPL): lanes beyond it still take part in barriers but skip the work.  On
+// return thread t holds outputs t*KPL .. t*KPL+KPL-1 of the sorted span.  s is
+// LDS of block_lds_words<T, KPL>(KPL * kBlockThreads) words.
 template <typename T, int K>
-__device__ __forceinline__ void block_sort_regs(T (&v)[K], T* s, int span) {
+__device__ __forceinline__ void block_sort_regs(T (&v)[2 * K], T* s, int span) {
+    constexpr int KPL = 2 * K;
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
-    const bool active = tid * K < span;
+    const bool active = tid * KPL < span;
     if (active) {
-        leaf_network<T, K>(v);
-        wave_merge<T, K>(v, lane);
-    }
-    int dummy[K];
-    for (int L = kWave * K; L < span; L <<= 1) {
-        if (active) {
+        T lo[K], hi[K];
 #pragma unroll
-            for (int j = 0; j < K; ++j) s[lds_idx<T>(tid * K + j)] = v[j];
+        for (int j = 0; j < K; ++j) {
+            lo[j] = v[j];
+            hi[j] = v[K + j];
+        }
+        leaf_network<T, K>(lo);
+        leaf_network<T, K>(hi);
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            v[j] = lo[j];
+            v[K + j] = hi[j];
+        }
+        lane_merge_halves<T, KPL>(v);
+        wave_merge<T, KPL>(v, lane);
+    }
+    for (int L = kWave * KPL; L < span; L <<= 1) {
+        // run r occupies [r*(L+KPL), r*(L+KPL)+L), then KPL sentinels
+        const int e = tid * KPL;
+        const int run = e / L;
+        if (active) {
+            const int pos = e + run * KPL;
+#pragma unroll
+            for (int j = 0; j < KPL; ++j) s[lds_idx<T>(pos + j)] = v[j];
+            if ((e % L) == L - KPL) {
+#pragma unroll
+                for (int j = 0; j < KPL; ++j) s[lds_idx<T>(pos + KPL + j)] = key_max<T>();
+            }
         }
         __syncthreads();
         if (active) {
-            const int d_all = tid * K;
-            const int base = d_all & ~(2 * L - 1);
-            const int d = d_all - base;
-            const int i = corank_lds(s, base, L, base + L, L, d, PlainLess{});
-            serial_merge<T, K, false>(s, base, L, base + L, L, i, d - i, span - 1, v, dummy,
-                                      PlainLess{});
+            const int ra = run & ~1;
+            const int a0 = ra * (L + KPL);
+            const int b0 = a0 + L + KPL;
+            const int d = e - ra * L;
+            const int i = corank_lds(s, a0, L, b0, L, d, PlainLess{});
+            serial_merge_closed<T, KPL>(s, a0 + i, b0 + d - i, v);
         }
         __syncthreads();
     }

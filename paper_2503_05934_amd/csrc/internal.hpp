@@ -10,7 +10,7 @@
 namespace msn {
 
 constexpr int kWave = 64;
-constexpr int kBlockThreads = 1024;  // block sort: 16 wavefronts
+constexpr int kBlockThreads = 512;   // block sort: 8 wavefronts x 16 keys per lane
 constexpr int kMergeThreads = 256;   // global merge pass
 
 enum KeyType : int { kU32 = 0, kI32 = 1, kF32 = 2 };

@@ -4,7 +4,7 @@
 //   lane   (<= lane_max keys, at most one leaf): one lane, one network with
 //          padding -- the role of the paper's variable-size networks
 //          (Table 3, VarSort);
-//   wave   (<= wave_max): one wavefront, network + bitonic merges;
+//   wave   (<= wave_max): one wavefront, networks + bitonic merges;
 //   block  (<= block_max): one workgroup, network + bitonic + LDS merges;
 //   big    (> block_max): one workgroup sorts the segment's tiles in turn and
 //          then merges them pass by pass through global memory.
@@ -32,7 +32,7 @@ struct SegState {
     uint32_t pad[7];
 };
 
-constexpr int kSegMergeKPT = 8;                                // keys per thread, big merges
+constexpr int kSegMergeKPT = 16;                               // keys per thread, big merges
 constexpr int kSegMergeTile = kSegMergeKPT * kBlockThreads;    // 8192 outputs per step
 constexpr int kSegBoundWords = kBlockThreads + 4;
 
@@ -119,18 +119,20 @@ __device__ __forceinline__ void lane_task(const uint32_t* kin, const uint32_t* v
 }
 
 // ------------------------------------------------------------ wave tasks ---
-// One wavefront sorts one segment of at most 64*K keys.  wst: this wave's
-// private LDS staging (2 * 64 * K words) for position gathers.
+// One wavefront sorts one segment of at most 64*KPL keys (KPL = 2K keys per
+// lane).  wst: this wave's private LDS staging (2 * 64 * KPL words) for
+// position gathers.
 template <int DT, int K, bool STABLE, int VM>
 __device__ __forceinline__ void wave_task(const uint32_t* kin, const uint32_t* vin,
                                           uint32_t* kout, uint32_t* vout, uint32_t off, int len,
                                           uint32_t* wst) {
     using T = typename TileTraits<DT, K, STABLE>::T;
+    constexpr int KPL = keys_per_lane<K>();
     const int lane = threadIdx.x & (kWave - 1);
-    const int first = lane * K;
-    T v[K];
+    const int first = lane * KPL;
+    T v[KPL];
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
+    for (int j = 0; j < KPL; ++j) {
         const bool live = first + j < len;
         const uint32_t x = live ? kin[off + first + j] : 0u;
         if constexpr (STABLE)
@@ -138,17 +140,32 @@ __device__ __forceinline__ void wave_task(const uint32_t* kin, const uint32_t* v
         else
             v[j] = live ? ord_key<DT>(x) : 0xffffffffu;
     }
-    leaf_network<T, K>(v);
-    wave_merge<T, K>(v, lane);
+    {
+        T lo[K], hi[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            lo[j] = v[j];
+            hi[j] = v[K + j];
+        }
+        leaf_network<T, K>(lo);
+        leaf_network<T, K>(hi);
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            v[j] = lo[j];
+            v[K + j] = hi[j];
+        }
+    }
+    lane_merge_halves<T, KPL>(v);
+    wave_merge<T, KPL>(v, lane);
     if constexpr (!STABLE) {
 #pragma unroll
-        for (int j = 0; j < K; ++j)
+        for (int j = 0; j < KPL; ++j)
             if (first + j < len) kout[off + first + j] = unord_key<DT>(v[j]);
     } else {
         constexpr bool kNeedBits = DT == kF32;
         constexpr bool kNeedVals = VM == kVals;
         uint32_t* sbits = wst;
-        uint32_t* svals = wst + kWave * K;
+        uint32_t* svals = wst + kWave * KPL;
         if constexpr (kNeedBits || kNeedVals) {
             for (int i = lane; i < len; i += kWave) {
                 if constexpr (kNeedBits) sbits[i] = kin[off + i];
@@ -159,7 +176,7 @@ __device__ __forceinline__ void wave_task(const uint32_t* kin, const uint32_t* v
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
+        for (int j = 0; j < KPL; ++j) {
             if (first + j < len) {
                 const uint32_t tag = (uint32_t)v[j];
                 uint32_t key;
@@ -266,7 +283,7 @@ __device__ void wg_merge_pass(const uint32_t* ks, const uint32_t* vs, uint32_t* 
 template <int DT, int K, bool STABLE, int VM>
 __device__ void big_task(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
                          uint32_t* wk, uint32_t* wv, uint32_t off, int len, void* smem) {
-    constexpr int kTile = K * kBlockThreads;
+    constexpr int kTile = TileTraits<DT, K, STABLE>::kTile;
     const int chunks = (len + kTile - 1) / kTile;
     int passes = 0;
     while ((1 << passes) < chunks) ++passes;
@@ -297,7 +314,8 @@ __device__ void big_task(const uint32_t* kin, const uint32_t* vin, uint32_t* kou
 template <int DT, int K, bool STABLE, int VM>
 struct SegTraits {
     static constexpr size_t kTileLds = TileTraits<DT, K, STABLE>::kLdsBytes;
-    static constexpr size_t kWaveLds = (size_t)(kBlockThreads / kWave) * 2 * kWave * K * 4;
+    static constexpr size_t kWaveLds =
+        (size_t)(kBlockThreads / kWave) * 2 * kWave * keys_per_lane<K>() * 4;
     static constexpr size_t kMergeLds =
         (size_t)kSegBoundWords * 4 +
         (size_t)lds_words<uint32_t>(kSegMergeTile) * 4 * (VM != kNoVals ? 2 : 1);
@@ -366,7 +384,8 @@ __global__ __launch_bounds__(kBlockThreads) void k_segmented(
             if (idx < n_wave) {
                 uint32_t off, len;
                 seg_bounds(offsets, L[kCWave * S + idx], uni_len, off, len);
-                uint32_t* wst = reinterpret_cast<uint32_t*>(smem) + (size_t)w * 2 * kWave * K;
+                uint32_t* wst = reinterpret_cast<uint32_t*>(smem) +
+                                (size_t)w * 2 * kWave * keys_per_lane<K>();
                 wave_task<DT, K, STABLE, VM>(kin, vin, kout, vout, off, (int)len, wst);
             }
         } else {

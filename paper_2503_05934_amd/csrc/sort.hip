@@ -14,7 +14,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_block_sort(const uint32_t* ki
                                                               uint32_t* kout, uint32_t* vout,
                                                               int64_t n, int vec) {
     extern __shared__ __align__(16) unsigned char smem[];
-    constexpr int kTile = K * kBlockThreads;
+    constexpr int kTile = TileTraits<DT, K, STABLE>::kTile;
     const int64_t base = (int64_t)blockIdx.x * kTile;
     const int nv = (int)((n - base) < kTile ? (n - base) : kTile);
     block_sort_tile<DT, K, STABLE, VM>(kin + base, VM == kVals ? vin + base : nullptr,
@@ -319,7 +319,7 @@ int dispatch_merge(const SortArgs& a, const uint32_t* ks, const uint32_t* vs, ui
 
 template <int DT>
 int run_sort(const SortArgs& a) {
-    const int tile = a.leaf_k * kBlockThreads;
+    const int tile = 2 * a.leaf_k * kBlockThreads;  // run length after the first sweep
     const int64_t runs = (a.n + tile - 1) / tile;
     int passes = 0;
     while (((int64_t)1 << passes) < runs) ++passes;
