@@ -213,25 +213,276 @@ def bench_keys(args):
     return out
 
 
+def _roof(stats, kind, bytes_per_launch_fn, peak=HBM_PEAK_GBPS):
+    m = stats.get(kind)
+    if not m:
+        return None
+    avg_s = m["avg_ms"] / 1e3
+    per_launch = bytes_per_launch_fn(m)
+    achieved = per_launch / avg_s / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": peak, "unit": "GB/s",
+            "frac": achieved / peak, "traffic": None, "kernel": kind,
+            "avg_launch_ms": m["avg_ms"], "launches": m["launches"],
+            "algorithmic_bytes_per_launch": per_launch}
+
+
+def _timed_with_kernel_stats(fn, steps, warmup):
+    import torch
+
+    from paper_2503_05934_amd import _lib
+
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    _lib.timing_enable(256 * (steps + 1))
+    ms, wall = time_steps(fn, steps, 0)
+    stats = _lib.timing_read()
+    _lib.timing_disable()
+    return ms, wall, stats
+
+
+def bench_pairs(args):
+    """Stable key-value sort: 2^28 uint32 keys from [0, 2^16), payload = index."""
+    import torch
+
+    import paper_2503_05934_amd as msn
+    from paper_2503_05934_amd import workloads
+
+    dev = torch.device("cuda:0")
+    n = args.n
+    log(f"[bench] generating {n} pairs (keys < 2^16, payload = index)")
+    k_np, v_np = workloads.pairs(n, seed=0)
+    k = torch.from_numpy(k_np).to(dev)
+    v = torch.from_numpy(v_np).to(dev)
+    plan = msn.SortPlan(n, torch.uint32, dev, pairs=True, leaf=args.leaf)
+    ms, wall, stats = _timed_with_kernel_stats(lambda: plan.run(k, v), args.steps, args.warmup)
+    ko, vo = plan.out, plan.out_vals
+    # stable and a permutation: keys non-decreasing, payload rising inside equal keys,
+    # every index once, and keys_out[i] == keys_in[vals_out[i]]
+    ki = ko.view(torch.int32).to(torch.int64)
+    vi = vo.view(torch.int32).to(torch.int64)
+    ok = bool((ki[1:] >= ki[:-1]).all())
+    ok &= bool(((ki[1:] > ki[:-1]) | (vi[1:] > vi[:-1])).all())
+    ok &= bool((torch.bincount(vi, minlength=n) == 1).all())
+    ok &= bool(torch.equal(k.view(torch.int32)[vi], ko.view(torch.int32)))
+    if not ok:
+        raise SystemExit("[bench] pairs output check failed")
+    return {
+        "metric": "Gkeys/s, 2^28 uint32 key-value pairs (keys < 2^16, payload = index), 1 GPU",
+        "value": n / (ms / 1e3) / 1e9, "unit": "Gkeys/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"sort_pairs: 2^{int(np.log2(n))} uint32 keys uniform in "
+                               "[0, 2^16), uint32 payload = index, stable", "n": n,
+                   "leaf": args.leaf},
+        "roofline": _roof(stats, "merge", lambda m: 16.0 * n),
+        "hbm_schedule": {"bytes_per_key": reference_schedule_bytes(n, 8),
+                         "implied_gkeys_at_peak": HBM_PEAK_GBPS / reference_schedule_bytes(n, 8)},
+        "kernels_ms_per_step": {kk: vv["total_ms"] / args.steps for kk, vv in stats.items()},
+        "checked": "stable permutation (O(n) invariants on the GPU)",
+    }
+
+
+def bench_segmented(args):
+    """100,000 int32 arrays, lengths log-uniform in [3, 65536], 30 % presorted,
+    one graph-captured segmented sort vs one msn_sort_keys launch per array."""
+    import ctypes
+
+    import torch
+
+    import paper_2503_05934_amd as msn
+    from paper_2503_05934_amd import _lib, workloads
+
+    dev = torch.device("cuda:0")
+    S = args.segments
+    log(f"[bench] generating {S} segments")
+    x_np, off_np, _ = workloads.segments(S, seed=0)
+    n = x_np.shape[0]
+    x = torch.from_numpy(x_np).to(dev)
+    off = torch.from_numpy(off_np).to(dev)
+    tuning = None
+    if not args.no_autotune:
+        from paper_2503_05934_amd import autotune
+
+        log("[bench] autotuning segmented thresholds")
+        tuning = autotune.tuned_segmented_params(x, off, num_segments=S, leaf=args.leaf,
+                                                 force=args.retune)
+    out = torch.empty_like(x)
+    ws = torch.empty(_lib.segmented_workspace_bytes(n, S, 1, False), dtype=torch.uint8,
+                     device=dev)
+    run = lambda: msn.segmented_sort(x, off, leaf=args.leaf, tuning=tuning, out_keys=out,
+                                     workspace=ws)
+    run()
+    torch.cuda.synchronize()
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=stream):
+        run()
+    ms, wall = time_steps(graph.replay, args.steps, args.warmup)
+    ms_eager, _, stats = _timed_with_kernel_stats(run, args.steps, 1)
+    # per-segment order check on the GPU: out non-decreasing except across segment starts
+    o = out.to(torch.int64)
+    starts = torch.zeros(n, dtype=torch.bool, device=dev)
+    starts[off[:-1].to(torch.int64)[off[:-1].to(torch.int64) < n]] = True
+    okd = (o[1:] >= o[:-1]) | starts[1:]
+    ok = bool(okd.all()) and x.to(torch.int64).sum().item() == o.sum().item()
+    if not ok:
+        raise SystemExit("[bench] segmented output check failed")
+    # baseline: one flat sort launch sequence per array, same GPU, eager
+    log("[bench] per-array baseline (one msn_sort_keys call per segment)")
+    L = _lib.lib()
+    wsb = _lib.sort_workspace_bytes(int((off_np[1:] - off_np[:-1]).max()), 1, False)
+    ws2 = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    out2 = torch.empty_like(x)
+    st = _lib.stream_handle(dev)
+    base_in, base_out = x.data_ptr(), out2.data_ptr()
+    offs = off_np.astype(np.int64)
+    lc = _lib.leaf_code(args.leaf)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for s_ in range(S):
+        a, b = int(offs[s_]), int(offs[s_ + 1])
+        rc = L.msn_sort_keys(ctypes.c_void_p(base_in + 4 * a), ctypes.c_void_p(base_out + 4 * a),
+                             b - a, 1, lc, None, ctypes.c_void_p(ws2.data_ptr()), wsb, st)
+        if rc:
+            raise SystemExit(f"[bench] msn_sort_keys failed: {rc}")
+    e1.record()
+    torch.cuda.synchronize()
+    base_ms = e0.elapsed_time(e1)
+    base_wall = time.perf_counter() - t0
+    if not torch.equal(out, out2):
+        raise SystemExit("[bench] per-array baseline disagrees with the segmented sort")
+    return {
+        "metric": "Gkeys/s, batched segmented sort: 100,000 int32 arrays, lengths log-uniform "
+                  "in [3, 65536], 30% presorted, 1 GPU",
+        "value": n / (ms / 1e3) / 1e9, "unit": "Gkeys/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "i32", "data": "synthetic",
+        "config": {"workload": "segmented_sort, one hipGraph replay per step", "segments": S,
+                   "keys": n, "leaf": args.leaf, "tuning": tuning},
+        "eager_ms_per_step": ms_eager,
+        "per_array_baseline": {"ms": base_ms, "wall_s": base_wall,
+                               "gkeys_per_s": n / (base_ms / 1e3) / 1e9,
+                               "how": "one msn_sort_keys call per segment, eager, same GPU"},
+        "speedup_vs_per_array": base_ms / ms,
+        "roofline": _roof(stats, "segmented", lambda m: 8.0 * n),
+        "kernels_ms_per_step": {kk: vv["total_ms"] / args.steps for kk, vv in stats.items()},
+    }
+
+
+def bench_rows(args):
+    """4096 x 8192 fp32 rows: stable row sort (values + int32 perm) and the
+    backward scatter, timed separately."""
+    import torch
+
+    import paper_2503_05934_amd as msn
+    from paper_2503_05934_amd import workloads
+
+    dev = torch.device("cuda:0")
+    R, C = args.rows, args.cols
+    log(f"[bench] generating {R}x{C} fp32 rows ({args.variant})")
+    x_np, g_np, redraws = workloads.rows(R, C, variant=args.variant, seed=0)
+    x = torch.from_numpy(x_np).to(dev)
+    g = torch.from_numpy(g_np).to(dev)
+    vals, perm = msn.sort_rows(x, leaf=args.leaf)
+    fwd = lambda: msn.sort_rows(x, leaf=args.leaf)
+    ms_f, _, st_f = _timed_with_kernel_stats(fwd, args.steps, args.warmup)
+    out = torch.empty_like(g)
+    bwd = lambda: msn.sort_backward(g, perm, out=out)
+    ms_b, _, st_b = _timed_with_kernel_stats(bwd, args.steps, args.warmup)
+    ne = R * C
+    ok = bool(torch.equal(x.gather(1, perm.to(torch.int64)).view(torch.int32),
+                          vals.view(torch.int32)))
+    ok &= bool(torch.equal(out.gather(1, perm.to(torch.int64)), g))
+    if not ok:
+        raise SystemExit("[bench] rows output check failed")
+    return {
+        "metric": "Gelem/s, differentiable fp32 row sort 4096 x 8192 (forward values+perm, "
+                  "backward scatter), 1 GPU",
+        "value": ne / (ms_f / 1e3) / 1e9, "unit": "Gelem/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_f, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"sort_rows + sort_backward, {R}x{C} fp32 Normal(0,1) "
+                               f"{args.variant}", "rows": R, "cols": C, "redraws": redraws,
+                   "leaf": args.leaf},
+        "backward": {"ms": ms_b, "gelem_per_s": ne / (ms_b / 1e3) / 1e9,
+                     "roofline": _roof(st_b, "backward", lambda m: 12.0 * ne)},
+        "roofline": _roof(st_f, "segmented", lambda m: 12.0 * ne),
+        "kernels_ms_per_step": {kk: vv["total_ms"] / args.steps for kk, vv in st_f.items()},
+    }
+
+
+def bench_small(args):
+    """10,000 and 1,000,000 int32 keys (three distributions), both leaf sets;
+    one graph replay per timed step.  These inputs fit in the 256 MB
+    Infinity Cache, so the numbers are cache-resident."""
+    import torch
+
+    import paper_2503_05934_amd as msn
+    from paper_2503_05934_amd import workloads
+
+    dev = torch.device("cuda:0")
+    table = {}
+    for n, dists in ((10_000, ["random"]), (1_000_000, list(workloads.DISTRIBUTIONS))):
+        for dist in dists:
+            x = torch.from_numpy(workloads.keys(n, dist, "i32", seed=0)).to(dev)
+            for leaf in ("6To8", "3To5"):
+                plan = msn.SortPlan(n, torch.int32, dev, leaf=leaf)
+                plan.run(x)
+                torch.cuda.synchronize()
+                s = torch.cuda.Stream()
+                s.wait_stream(torch.cuda.current_stream())
+                gph = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(gph, stream=s):
+                    plan.run(x)
+                ms, _ = time_steps(gph.replay, max(args.steps, 20), args.warmup)
+                table[f"n={n} {dist} {leaf}"] = {"us": ms * 1e3,
+                                                 "gkeys_per_s": n / (ms / 1e3) / 1e9}
+                log(f"[bench] n={n} {dist} {leaf}: {ms * 1e3:.1f} us")
+    head = table["n=1000000 random 6To8"]
+    return {
+        "metric": "Gkeys/s, 1,000,000 int32 keys (and 10,000), 6-to-8 vs 3-to-5 leaves, 1 GPU",
+        "value": head["gkeys_per_s"], "unit": "Gkeys/s", "n_gpus": 1,
+        "steps": max(args.steps, 20), "warmup": args.warmup, "ms_per_step": head["us"] / 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "i32",
+        "data": "synthetic",
+        "config": {"workload": "sort_keys 1e6 int32 random (cache-resident), graph replay"},
+        "table": table,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="keys", choices=["keys"])
+    ap.add_argument("--workload", default="keys",
+                    choices=["keys", "pairs", "segmented", "rows", "small"])
     ap.add_argument("--n", type=int, default=1 << 28)
     ap.add_argument("--leaf", default="6To8", choices=["6To8", "3To5"])
     ap.add_argument("--merge-tile", type=int, default=0)
     ap.add_argument("--dists", default="random,sorted,nearly")
     ap.add_argument("--cpu-sample", type=int, default=1 << 26)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--segments", type=int, default=100_000)
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--retune", action="store_true", help="ignore the autotuner cache")
+    ap.add_argument("--rows", type=int, default=4096)
+    ap.add_argument("--cols", type=int, default=8192)
+    ap.add_argument("--variant", default="tiefree", choices=["tiefree", "ties"])
     args = ap.parse_args()
     args.dists = [d for d in args.dists.split(",") if d]
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(this build has no multi-GPU path)", file=sys.stderr)
         return 2
-    out = bench_keys(args)
+    fn = {"keys": bench_keys, "pairs": bench_pairs, "segmented": bench_segmented,
+          "rows": bench_rows, "small": bench_small}[args.workload]
+    out = fn(args)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -49,9 +49,16 @@ def _tuning_ptr(tuning):
 
 def sort(keys: torch.Tensor, *, leaf="6To8", tuning=None, out: torch.Tensor | None = None,
          workspace: torch.Tensor | None = None, stream=None) -> torch.Tensor:
-    """Ascending sort of a 1-D uint32/int32/float32 GPU tensor."""
+    """Ascending sort of a 1-D uint32/int32/float32 GPU tensor.
+
+    tuning: None (defaults), a dict of msn_tuning fields, or "auto" (the
+    autotuner's cached or freshly measured choice for this shape).
+    """
     dt = _check_keys(keys)
     n = keys.numel()
+    if tuning == "auto":
+        from . import autotune
+        tuning = autotune.tuned_sort_params(keys, pairs=False, leaf=leaf)
     out = torch.empty_like(keys) if out is None else out
     ws_bytes = _lib.sort_workspace_bytes(n, dt, False)
     ws = _workspace(ws_bytes, keys.device) if workspace is None else workspace
@@ -67,6 +74,9 @@ def sort_pairs(keys: torch.Tensor, vals: torch.Tensor | None = None, *, leaf="6T
     """Stable key-value sort.  vals=None returns the argsort (int32 indices)."""
     dt = _check_keys(keys)
     n = keys.numel()
+    if tuning == "auto":
+        from . import autotune
+        tuning = autotune.tuned_sort_params(keys, pairs=True, leaf=leaf)
     if vals is not None:
         if vals.shape != keys.shape or vals.element_size() != 4 or not vals.is_contiguous():
             raise ValueError("vals must be a contiguous 32-bit tensor shaped like keys")
@@ -102,6 +112,10 @@ def segmented_sort(keys: torch.Tensor, offsets: torch.Tensor | None = None,
         raise ValueError("give offsets or num_segments")
     if argsort and vals is not None:
         raise ValueError("argsort takes no vals")
+    if tuning == "auto":
+        from . import autotune
+        tuning = autotune.tuned_segmented_params(keys, offsets, num_segments=num_segments,
+                                                 vals=vals, argsort=argsort, leaf=leaf)
     pairs = argsort or vals is not None
     ok = torch.empty_like(keys) if out_keys is None else out_keys
     ov = None
