@@ -44,8 +44,9 @@ def reference_schedule_bytes(n: int, width: int) -> int:
 
 
 def load_traffic(kernel_file: str):
-    """Per-launch HBM bytes of the merge kernel from committed rocprofv3 PMC
-    summaries, if they were taken on the current kernel source."""
+    """Per-launch HBM bytes of the keys-only merge kernel from the committed
+    rocprofv3 PMC summary, if it was taken on the current kernel source
+    (merge_keys.hpp + device.hpp); None otherwise."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", kernel_file)
@@ -56,7 +57,7 @@ def load_traffic(kernel_file: str):
         if ":" in line and line.startswith("- "):
             k, v = line[2:].split(":", 1)
             fields[k.strip()] = v.strip()
-    src = os.path.join(ROOT, "paper_2503_05934_amd", "csrc", "sort.hip")
+    src = os.path.join(ROOT, "paper_2503_05934_amd", "csrc", "merge_keys.hpp")
     dev = os.path.join(ROOT, "paper_2503_05934_amd", "csrc", "device.hpp")
     h = hashlib.sha256(open(src, "rb").read() + open(dev, "rb").read()).hexdigest()[:16]
     if fields.get("source_sha256_16") != h:
@@ -171,7 +172,7 @@ def bench_keys(args):
                 avg_s = m["avg_ms"] / 1e3
                 bytes_per_launch = 8.0 * n
                 achieved = bytes_per_launch / avg_s / 1e9
-                traffic = load_traffic("k_merge_2p28_u32_traffic.md")
+                traffic = load_traffic("k_merge_keys_2p28_u32_traffic.md")
                 roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS,
                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
                         "kernel": "k_merge (global merge-path pass)",
@@ -455,13 +456,36 @@ def bench_small(args):
     }
 
 
+def bench_copy(args):
+    """A plain device-to-device copy of n uint32 words: the achievable
+    read+write bandwidth, and the reference kernel that calibrates the HBM
+    byte counters (FETCH_SIZE / WRITE_SIZE) for a known size."""
+    import torch
+
+    dev = torch.device("cuda:0")
+    n = args.n
+    x = torch.arange(n, dtype=torch.int32, device=dev)
+    y = torch.empty_like(x)
+    ms, _ = time_steps(lambda: y.copy_(x), args.steps, args.warmup)
+    if not torch.equal(x, y):
+        raise SystemExit("[bench] copy check failed")
+    gbps = 8.0 * n / (ms / 1e3) / 1e9
+    return {"metric": "GB/s, device copy of 2^28 uint32 (read + write)", "value": gbps,
+            "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+            "config": {"workload": f"torch copy_ of {n} int32 words", "n": n,
+                       "bytes_read": 4 * n, "bytes_written": 4 * n},
+            "frac_of_peak": gbps / HBM_PEAK_GBPS}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="keys",
-                    choices=["keys", "pairs", "segmented", "rows", "small"])
+                    choices=["keys", "pairs", "segmented", "rows", "small", "copy"])
     ap.add_argument("--n", type=int, default=1 << 28)
     ap.add_argument("--leaf", default="6To8", choices=["6To8", "3To5"])
     ap.add_argument("--merge-tile", type=int, default=0)
@@ -481,7 +505,7 @@ def main():
               "(this build has no multi-GPU path)", file=sys.stderr)
         return 2
     fn = {"keys": bench_keys, "pairs": bench_pairs, "segmented": bench_segmented,
-          "rows": bench_rows, "small": bench_small}[args.workload]
+          "rows": bench_rows, "small": bench_small, "copy": bench_copy}[args.workload]
     out = fn(args)
     print(json.dumps(out), flush=True)
     return 0
