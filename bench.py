@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E, 8 TB/s
 METRIC = "Gkeys/s + % HBM roofline, 2^28 uint32 keys (random/sorted/nearly-sorted), 1 GPU"
-T_RUN = 8192                    # run length after the first sweep (6-to-8 leaves)
+T_RUN = 8192                    # run length of the reference binary schedule
 
 
 def log(msg):
@@ -135,8 +135,9 @@ def bench_keys(args):
     dev = torch.device("cuda:0")
     n = args.n
     leaf = args.leaf
-    plan = msn.SortPlan(n, torch.uint32, dev, leaf=leaf,
-                        tuning={"merge_tile": args.merge_tile} if args.merge_tile else None)
+    tuning = {k: v for k, v in (("merge_tile", args.merge_tile),
+                                ("block_tile", args.block_tile)) if v}
+    plan = msn.SortPlan(n, torch.uint32, dev, leaf=leaf, tuning=tuning or None)
     results = {}
     roof = None
     keys_random = None
@@ -199,7 +200,8 @@ def bench_keys(args):
         "config": {"workload": f"sort_keys: 2^{int(np.log2(n))} uint32 keys, uniform random "
                                f"over [0, 2^32), seed 0, {leaf} leaves",
                    "n": n, "leaf": leaf, "dist": args.dists[0],
-                   "merge_tile": args.merge_tile or 8192},
+                   "merge_tile": args.merge_tile or 8192,
+                   "block_tile": args.block_tile or 2048 * (8 if leaf == "6To8" else 4)},
         "roofline": roof,
         "hbm_schedule": {"bytes_per_key": sched,
                          "implied_gkeys_at_peak": HBM_PEAK_GBPS / sched,
@@ -489,6 +491,7 @@ def main():
     ap.add_argument("--n", type=int, default=1 << 28)
     ap.add_argument("--leaf", default="6To8", choices=["6To8", "3To5"])
     ap.add_argument("--merge-tile", type=int, default=0)
+    ap.add_argument("--block-tile", type=int, default=0)
     ap.add_argument("--dists", default="random,sorted,nearly")
     ap.add_argument("--cpu-sample", type=int, default=1 << 26)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")

@@ -82,6 +82,11 @@ extern "C" {
  *                   in LDS: up to 1024 x leaf size (default 1024 x leaf).
  *   seg_grid        workgroups of the persistent segmented kernel
  *                   (default: enough to fill every compute unit).
+ *   block_tile      run length after the first sweep of msn_sort_keys /
+ *                   msn_sort_pairs: 1024, 2048 or 4096 x leaf size (default
+ *                   2048 x leaf size).  Only integer keys-only sorts use runs
+ *                   above 1024 x leaf size; other sorts accept the value and
+ *                   keep 1024 x leaf size.
  */
 typedef struct {
     int32_t merge_tile;
@@ -89,7 +94,8 @@ typedef struct {
     int32_t seg_wave_max;
     int32_t seg_block_max;
     int32_t seg_grid;
-    int32_t reserved[3];
+    int32_t block_tile;
+    int32_t reserved[2];
 } msn_tuning;
 
 /*

@@ -40,7 +40,8 @@ class Tuning(ctypes.Structure):
         ("seg_wave_max", ctypes.c_int32),
         ("seg_block_max", ctypes.c_int32),
         ("seg_grid", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 3),
+        ("block_tile", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 2),
     ]
 
     def as_dict(self) -> dict:

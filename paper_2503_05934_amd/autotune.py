@@ -80,8 +80,10 @@ def workload_key(op: str, dtype: int, pairs: bool, leaf: int, n: int, segments: 
             f"|s2^{size_bucket(segments)}")
 
 
-def sort_candidates() -> list[dict]:
-    return [{"merge_tile": mt} for mt in (2048, 4096, 8192)]
+def sort_candidates(leaf_keys: int = 8, integer_keys_only: bool = True) -> list[dict]:
+    tiles = (1024, 2048, 4096) if integer_keys_only else (1024,)
+    return [{"merge_tile": mt, "block_tile": bt * leaf_keys}
+            for mt in (2048, 4096, 8192) for bt in tiles]
 
 
 def segmented_candidates(leaf_keys: int, n_total: int, num_segments: int) -> list[dict]:
@@ -156,7 +158,8 @@ def tuned_sort_params(keys: torch.Tensor, *, pairs: bool, leaf, reps: int = 3,
             return sort_pairs(keys, None, leaf=leaf, tuning=t)
         return (sort(keys, leaf=leaf, tuning=t),)
 
-    best, _ = tune(run, sort_candidates(), reps)
+    k = 8 if lc == _lib.MSN_LEAF_6TO8 else 4
+    best, _ = tune(run, sort_candidates(k, not pairs and dt != _lib.MSN_F32), reps)
     store(key, best)
     return best
 

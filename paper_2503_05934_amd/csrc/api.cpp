@@ -93,14 +93,23 @@ int merge_tile_of(const msn_tuning* t, int* out) {
     return MSN_OK;
 }
 
+// First-sweep run length: 1024, 2048 or 4096 x the leaf size (default 2048 K).
+int block_tile_of(const msn_tuning* t, int k, int* out) {
+    int bt = t && t->block_tile ? t->block_tile : msn::kDefaultBlockTileMult * k;
+    if (bt != 1024 * k && bt != 2048 * k && bt != 4096 * k) return MSN_ERR_CONFIG;
+    *out = bt;
+    return MSN_OK;
+}
+
 int sort_common(const void* keys_in, const uint32_t* vals_in, void* keys_out, uint32_t* vals_out,
                 int64_t n, int dtype, int leaf, const msn_tuning* tuning, void* ws,
                 size_t ws_bytes, void* stream, bool pairs) {
     if (!valid_dtype(dtype)) return MSN_ERR_DTYPE;
     const int k = leaf_keys(leaf);
     if (!k) return MSN_ERR_CONFIG;
-    int mt = 0;
+    int mt = 0, bt = 0;
     if (int rc = merge_tile_of(tuning, &mt)) return rc;
+    if (int rc = block_tile_of(tuning, k, &bt)) return rc;
     if (n < 0 || n > kMaxN) return MSN_ERR_SIZE;
     if (n == 0) return MSN_OK;
     if (!keys_in || !keys_out) return MSN_ERR_NULL;
@@ -115,7 +124,7 @@ int sort_common(const void* keys_in, const uint32_t* vals_in, void* keys_out, ui
     const size_t need = msn::sort_ws_bytes(n, vmode != msn::kNoVals);
     if (!ws || ws_bytes < need) return MSN_ERR_WORKSPACE;
     msn::SortArgs a{static_cast<const uint32_t*>(keys_in), vals_in,
-                    static_cast<uint32_t*>(keys_out), vals_out, n, dtype, k, vmode, mt, ws,
+                    static_cast<uint32_t*>(keys_out), vals_out, n, dtype, k, vmode, mt, bt, ws,
                     ws_bytes, static_cast<hipStream_t>(stream)};
     return msn::launch_sort(a);
 }

@@ -11,11 +11,17 @@
 
 namespace msn {
 
-template <int DT, int K, bool STABLE>
+// Tile shapes of the block sort (SHAPE): 0 = 512 threads x 2K keys per lane
+// (the default, and the only one for stable sorts); 1 = 1024 threads x 2K;
+// 2 = 1024 threads x 4K (32768-key runs for the 6-to-8 set, 137 KiB of LDS).
+// Shapes 1 and 2 serve the first sweep of flat integer keys-only sorts.
+template <int DT, int K, bool STABLE, int SHAPE = 0>
 struct TileTraits {
     using T = std::conditional_t<STABLE, uint64_t, uint32_t>;
-    static constexpr int kKPL = keys_per_lane<K>();
-    static constexpr int kTile = kKPL * kBlockThreads;
+    static_assert(SHAPE == 0 || !STABLE, "large tiles hold 32-bit keys only");
+    static constexpr int kThreads = SHAPE == 0 ? kBlockThreads : 2 * kBlockThreads;
+    static constexpr int kKPL = SHAPE == 2 ? 2 * keys_per_lane<K>() : keys_per_lane<K>();
+    static constexpr int kTile = kKPL * kThreads;
     static constexpr size_t kLdsBytes =
         (size_t)block_lds_words<T, kKPL>(kTile) * sizeof(T);
     static_assert(!STABLE || kLdsBytes >= (size_t)2 * kTile * 4, "staging must fit");
@@ -29,11 +35,11 @@ struct TileTraits {
 // aligned.  kout may equal kin (and vout vin): each position is read and
 // written only by its owning thread, or read before a barrier that precedes
 // every write.
-template <int DT, int K, bool STABLE, int VM>
+template <int DT, int K, bool STABLE, int VM, int SHAPE = 0>
 __device__ __forceinline__ void block_sort_tile(const uint32_t* kin, const uint32_t* vin,
                                                 uint32_t* kout, uint32_t* vout, int nv,
                                                 uint32_t val_base, void* smem, bool vec) {
-    using Tr = TileTraits<DT, K, STABLE>;
+    using Tr = TileTraits<DT, K, STABLE, SHAPE>;
     using T = typename Tr::T;
     static_assert(STABLE || (DT != kF32 && VM == kNoVals), "float keys and pairs sort stably");
     T* s = reinterpret_cast<T*>(smem);
@@ -68,7 +74,7 @@ __device__ __forceinline__ void block_sort_tile(const uint32_t* kin, const uint3
     }
 
     const int span = span_for(nv, kWave * KPL);
-    block_sort_regs<T, K>(v, s, span);
+    block_sort_regs<T, K, KPL>(v, s, span);
 
     if constexpr (!STABLE) {
 #pragma unroll
@@ -91,7 +97,7 @@ __device__ __forceinline__ void block_sort_tile(const uint32_t* kin, const uint3
         constexpr bool kNeedVals = VM == kVals;
         __syncthreads();
         if constexpr (kNeedBits || kNeedVals) {
-            for (int i = tid; i < nv; i += kBlockThreads) {
+            for (int i = tid; i < nv; i += Tr::kThreads) {
                 if constexpr (kNeedBits) sbits[i] = kin[i];
                 if constexpr (kNeedVals) svals[i] = vin[i];
             }

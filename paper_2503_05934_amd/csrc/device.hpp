@@ -288,19 +288,46 @@ __device__ __forceinline__ void serial_merge_closed(const T* s, int pa, int pb, 
     }
 }
 
-// Two sorted runs v[0..H) and v[H..2H) in one lane -> one sorted run
-// (bitonic: flip, then half-cleaners inside each half).
+// Adjacent sorted runs of R keys in one lane's v[0..N) -> sorted runs of 2R
+// (bitonic: flip each pair of runs, then half-cleaners inside each run).
+template <typename T, int N, int R>
+__device__ __forceinline__ void lane_merge_runs(T (&v)[N]) {
+#pragma unroll
+    for (int b = 0; b < N; b += 2 * R) {
+#pragma unroll
+        for (int j = 0; j < R; ++j) cx(v[b + j], v[b + 2 * R - 1 - j]);
+#pragma unroll
+        for (int d = R / 2; d >= 1; d >>= 1) {
+#pragma unroll
+            for (int j = 0; j < 2 * R; ++j)
+                if ((j & d) == 0) cx(v[b + j], v[b + j + d]);
+        }
+    }
+}
+
+// Two sorted runs v[0..N/2) and v[N/2..N) in one lane -> one sorted run.
 template <typename T, int N>
 __device__ __forceinline__ void lane_merge_halves(T (&v)[N]) {
-    constexpr int H = N / 2;
+    lane_merge_runs<T, N, N / 2>(v);
+}
+
+// Each group of K keys in v[0..N) sorted by the K-key network, then the
+// groups merged in-lane into one sorted run of N keys.
+template <typename T, int K, int N>
+__device__ __forceinline__ void lane_sort(T (&v)[N]) {
 #pragma unroll
-    for (int j = 0; j < H; ++j) cx(v[j], v[N - 1 - j]);
+    for (int g = 0; g < N; g += K) {
+        T w[K];
 #pragma unroll
-    for (int d = H / 2; d >= 1; d >>= 1) {
+        for (int j = 0; j < K; ++j) w[j] = v[g + j];
+        leaf_network<T, K>(w);
 #pragma unroll
-        for (int j = 0; j < N; ++j)
-            if ((j & d) == 0) cx(v[j], v[j + d]);
+        for (int j = 0; j < K; ++j) v[g + j] = w[j];
     }
+    if constexpr (N >= 2 * K) lane_merge_runs<T, N, K>(v);
+    if constexpr (N >= 4 * K) lane_merge_runs<T, N, 2 * K>(v);
+    if constexpr (N >= 8 * K) lane_merge_runs<T, N, 4 * K>(v);
+    static_assert(N == K || N == 2 * K || N == 4 * K || N == 8 * K, "keys per lane");
 }
 
 // --------------------------------------------------------- block sorting ---
@@ -315,35 +342,21 @@ __host__ __device__ constexpr int block_lds_words(int n) {
     return lds_words<T>(n + (n / (kWave * KPL)) * KPL + KPL);
 }
 
-// Sorts the KPL*kBlockThreads keys held as v[] by all threads of a workgroup
-// (thread t holds keys t*KPL .. t*KPL+KPL-1 in registers, KPL = 2K).  Each
-// lane applies the K-key network to both of its groups and merges them; the
-// wavefront merges its 64 lane runs by bitonic exchanges; then LDS merge-path
-// levels double the run length up to `span` (a power of two, at least
-// 64*KPL): lanes beyond it still take part in barriers but skip the work.  On
-// return thread t holds outputs t*KPL .. t*KPL+KPL-1 of the sorted span.  s is
-// LDS of block_lds_words<T, KPL>(KPL * kBlockThreads) words.
-template <typename T, int K>
-__device__ __forceinline__ void block_sort_regs(T (&v)[2 * K], T* s, int span) {
-    constexpr int KPL = 2 * K;
+// Sorts the KPL*(threads) keys held as v[] by all threads of a workgroup
+// (thread t holds keys t*KPL .. t*KPL+KPL-1 in registers; KPL is a multiple
+// of K).  Each lane applies the K-key network to each of its groups and
+// merges them; the wavefront merges its 64 lane runs by bitonic exchanges;
+// then LDS merge-path levels double the run length up to `span` (a power of
+// two, at least 64*KPL): lanes beyond it still take part in barriers but skip
+// the work.  On return thread t holds outputs t*KPL .. t*KPL+KPL-1 of the
+// sorted span.  s is LDS of block_lds_words<T, KPL>(tile keys) words.
+template <typename T, int K, int KPL>
+__device__ __forceinline__ void block_sort_regs(T (&v)[KPL], T* s, int span) {
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const bool active = tid * KPL < span;
     if (active) {
-        T lo[K], hi[K];
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-            lo[j] = v[j];
-            hi[j] = v[K + j];
-        }
-        leaf_network<T, K>(lo);
-        leaf_network<T, K>(hi);
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-            v[j] = lo[j];
-            v[K + j] = hi[j];
-        }
-        lane_merge_halves<T, KPL>(v);
+        lane_sort<T, K, KPL>(v);
         wave_merge<T, KPL>(v, lane);
     }
     for (int L = kWave * KPL; L < span; L <<= 1) {

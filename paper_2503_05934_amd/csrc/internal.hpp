@@ -32,6 +32,7 @@ struct SortArgs {
     int leaf_k;           // keys per lane in the base case: 8 or 4
     int vmode;
     int merge_tile;       // 2048, 4096 or 8192
+    int block_tile;       // first-sweep run length: 1024K, 2048K or 4096K
     void* ws;
     size_t ws_bytes;
     hipStream_t stream;
@@ -58,6 +59,7 @@ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 constexpr int kMinMergeTile = 2048;
 constexpr int kDefaultMergeTile = 8192;
+constexpr int kDefaultBlockTileMult = 2048;  // first-sweep run = 2048 x leaf size
 
 // Workspace of the flat sort: ping-pong keys (+ values) and one merge-path
 // split per merge tile.

@@ -9,18 +9,17 @@
 namespace msn {
 
 // ----------------------------------------------------------- first sweep ---
-template <int DT, int K, bool STABLE, int VM>
-__global__ __launch_bounds__(kBlockThreads) void k_block_sort(const uint32_t* kin,
-                                                              const uint32_t* vin,
-                                                              uint32_t* kout, uint32_t* vout,
-                                                              int64_t n, int vec) {
+template <int DT, int K, bool STABLE, int VM, int SHAPE>
+__global__ __launch_bounds__((TileTraits<DT, K, STABLE, SHAPE>::kThreads)) void k_block_sort(
+    const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, int64_t n,
+    int vec) {
     extern __shared__ __align__(16) unsigned char smem[];
-    constexpr int kTile = TileTraits<DT, K, STABLE>::kTile;
+    constexpr int kTile = TileTraits<DT, K, STABLE, SHAPE>::kTile;
     const int64_t base = (int64_t)blockIdx.x * kTile;
     const int nv = (int)((n - base) < kTile ? (n - base) : kTile);
-    block_sort_tile<DT, K, STABLE, VM>(kin + base, VM == kVals ? vin + base : nullptr,
-                                       kout + base, VM != kNoVals ? vout + base : nullptr, nv,
-                                       (uint32_t)base, smem, vec != 0);
+    block_sort_tile<DT, K, STABLE, VM, SHAPE>(kin + base, VM == kVals ? vin + base : nullptr,
+                                             kout + base, VM != kNoVals ? vout + base : nullptr,
+                                             nv, (uint32_t)base, smem, vec != 0);
 }
 
 // ------------------------------------------------------- merge-path split ---
@@ -154,26 +153,53 @@ int ensure_lds(Kern kern, size_t bytes) {
     return set_dynamic_lds(reinterpret_cast<const void*>(kern), bytes);
 }
 
-template <int DT, int K, bool STABLE, int VM>
+template <int DT, int K, bool STABLE, int VM, int SHAPE = 0>
 int launch_block_sort(const SortArgs& a, uint32_t* kdst, uint32_t* vdst, int vec) {
-    using Tr = TileTraits<DT, K, STABLE>;
-    auto kern = &k_block_sort<DT, K, STABLE, VM>;
+    using Tr = TileTraits<DT, K, STABLE, SHAPE>;
+    auto kern = &k_block_sort<DT, K, STABLE, VM, SHAPE>;
     if (int rc = ensure_lds(kern, Tr::kLdsBytes)) return rc;
     const int64_t blocks = (a.n + Tr::kTile - 1) / Tr::kTile;
     {
         LaunchTimer timer("block_sort", a.n, a.stream);
-        hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kBlockThreads), Tr::kLdsBytes,
+        hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(Tr::kThreads), Tr::kLdsBytes,
                            a.stream, a.kin, a.vin, kdst, vdst, a.n, vec);
     }
     return (int)hipGetLastError();
+}
+
+// Tile shape of the first sweep: larger shapes only for integer keys-only
+// sorts, chosen by the requested first-run length (block_tile / 1024K).
+inline int block_shape(const SortArgs& a) {
+    if (a.vmode != kNoVals || a.dtype == kF32) return 0;
+    const int ratio = a.block_tile / (1024 * a.leaf_k);
+    return ratio >= 4 ? 2 : ratio == 2 ? 1 : 0;
 }
 
 template <int DT, int K>
 int dispatch_block_sort(const SortArgs& a, uint32_t* kdst, uint32_t* vdst, int vec) {
     if (a.vmode == kVals) return launch_block_sort<DT, K, true, kVals>(a, kdst, vdst, vec);
     if (a.vmode == kArg) return launch_block_sort<DT, K, true, kArg>(a, kdst, vdst, vec);
-    if constexpr (DT == kF32) return launch_block_sort<DT, K, true, kNoVals>(a, kdst, vdst, vec);
-    else return launch_block_sort<DT, K, false, kNoVals>(a, kdst, vdst, vec);
+    if constexpr (DT == kF32) {
+        return launch_block_sort<DT, K, true, kNoVals>(a, kdst, vdst, vec);
+    } else {
+        switch (block_shape(a)) {
+            case 1: return launch_block_sort<DT, K, false, kNoVals, 1>(a, kdst, vdst, vec);
+            case 2: return launch_block_sort<DT, K, false, kNoVals, 2>(a, kdst, vdst, vec);
+            default: return launch_block_sort<DT, K, false, kNoVals, 0>(a, kdst, vdst, vec);
+        }
+    }
+}
+
+// Run length after the first sweep (the tile of the chosen shape).
+inline int first_run_length(const SortArgs& a) {
+    const int shape = block_shape(a);
+    if (a.leaf_k == 8)
+        return shape == 2 ? TileTraits<kU32, 8, false, 2>::kTile
+             : shape == 1 ? TileTraits<kU32, 8, false, 1>::kTile
+                          : TileTraits<kU32, 8, false, 0>::kTile;
+    return shape == 2 ? TileTraits<kU32, 4, false, 2>::kTile
+         : shape == 1 ? TileTraits<kU32, 4, false, 1>::kTile
+                      : TileTraits<kU32, 4, false, 0>::kTile;
 }
 
 template <int DT, int KPT, bool VALS>
@@ -218,7 +244,7 @@ int dispatch_merge(const SortArgs& a, const uint32_t* ks, const uint32_t* vs, ui
 
 template <int DT>
 int run_sort(const SortArgs& a) {
-    const int tile = 2 * a.leaf_k * kBlockThreads;  // run length after the first sweep
+    const int tile = first_run_length(a);
     const int64_t runs = (a.n + tile - 1) / tile;
     int passes = 0;
     while (((int64_t)1 << passes) < runs) ++passes;

@@ -115,6 +115,18 @@ def test_merge_tiles_give_identical_bits(orc):
         assert np.array_equal(host(ko), rk) and np.array_equal(host(vo), rv), mt
 
 
+@pytest.mark.parametrize("leaf,k", [("6To8", 8), ("3To5", 4)])
+@pytest.mark.parametrize("dtype", ["u32", "i32"])
+def test_block_tiles_give_identical_bits(orc, dtype, leaf, k):
+    for n in (1, 4095, 8193, 16385, 32767, 32769, 65537, 300007):
+        x = make_keys(n, dtype, seed=11 + n)
+        ref = orc.sort(x, dtype=dtype)
+        for bt in (1024 * k, 2048 * k, 4096 * k):
+            say(f"sort_keys dtype={dtype} leaf={leaf} block_tile={bt} n={n}")
+            y = host(msn.sort(gpu(x), leaf=leaf, tuning={"block_tile": bt}))
+            assert np.array_equal(y, ref), (bt, n)
+
+
 def test_unaligned_views(orc):
     # offsets by one element: 4-byte aligned, not 16-byte aligned
     n = 50001
