@@ -35,10 +35,26 @@ struct TileTraits {
 // aligned.  kout may equal kin (and vout vin): each position is read and
 // written only by its owning thread, or read before a barrier that precedes
 // every write.
+// Records the chunk samples among a thread's outputs x[0..N) at tile
+// positions first.. (global position samp.base + first + j).  N divides the
+// chunk and tiles start on chunk boundaries, so only x[0] can open a chunk
+// and only x[N-1] can close one.
+template <int N>
+__device__ __forceinline__ void write_samples(const Samples& samp, int first, int nv,
+                                              const uint32_t (&x)[N]) {
+    static_assert(kSampleChunk % N == 0, "keys per lane must divide the sample chunk");
+    if (!samp.first) return;
+    const int64_t p = samp.base + first;
+    if ((p & (kSampleChunk - 1)) == 0 && first < nv) samp.first[p / kSampleChunk] = x[0];
+    if (((p + N - 1) & (kSampleChunk - 1)) == kSampleChunk - 1 && first + N - 1 < nv)
+        samp.last[(p + N - 1) / kSampleChunk] = x[N - 1];
+}
+
 template <int DT, int K, bool STABLE, int VM, int SHAPE = 0>
 __device__ __forceinline__ void block_sort_tile(const uint32_t* kin, const uint32_t* vin,
                                                 uint32_t* kout, uint32_t* vout, int nv,
-                                                uint32_t val_base, void* smem, bool vec) {
+                                                uint32_t val_base, void* smem, bool vec,
+                                                Samples samp = Samples{nullptr, nullptr, 0}) {
     using Tr = TileTraits<DT, K, STABLE, SHAPE>;
     using T = typename Tr::T;
     static_assert(STABLE || (DT != kF32 && VM == kNoVals), "float keys and pairs sort stably");
@@ -79,6 +95,7 @@ __device__ __forceinline__ void block_sort_tile(const uint32_t* kin, const uint3
     if constexpr (!STABLE) {
 #pragma unroll
         for (int j = 0; j < KPL; ++j) x[j] = unord_key<DT>(v[j]);
+        write_samples(samp, first, nv, x);
         if (vec && first + KPL <= nv) {
 #pragma unroll
             for (int q = 0; q < KPL / 4; ++q)
@@ -114,6 +131,7 @@ __device__ __forceinline__ void block_sort_tile(const uint32_t* kin, const uint3
             if constexpr (VM == kVals) y[j] = svals[t];
             else y[j] = val_base + t;
         }
+        write_samples(samp, first, nv, x);
         if (vec && first + KPL <= nv) {
 #pragma unroll
             for (int q = 0; q < KPL / 4; ++q) {

@@ -58,16 +58,26 @@ struct SegArgs {
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 constexpr int kMinMergeTile = 2048;
+// Chunk size of the key samples every sweep of a flat sort leaves behind
+// (first and last key of each chunk); merge-path splits search them first.
+constexpr int kSampleChunk = 256;
+
+struct Samples {
+    uint32_t* first;  // first key of chunk c (position c * kSampleChunk)
+    uint32_t* last;   // last key of chunk c (position c * kSampleChunk + kSampleChunk - 1)
+    int64_t base;     // global position of the tile being written
+};
 constexpr int kDefaultMergeTile = 8192;
 constexpr int kDefaultBlockTileMult = 2048;  // first-sweep run = 2048 x leaf size
 
-// Workspace of the flat sort: ping-pong keys (+ values) and one merge-path
-// split per merge tile.
+// Workspace of the flat sort: ping-pong keys (+ values), one merge-path split
+// per merge tile, and the two chunk-sample arrays.
 inline size_t sort_ws_bytes(int64_t n, bool vals) {
     const size_t nk = align_up((size_t)n * 4, 256);
     const size_t nv = vals ? nk : 0;
     const size_t tiles = (size_t)((n + kMinMergeTile - 1) / kMinMergeTile) + 1;
-    return nk + nv + align_up(tiles * 4, 256);
+    const size_t chunks = (size_t)((n + kSampleChunk - 1) / kSampleChunk);
+    return nk + nv + align_up(tiles * 4, 256) + 2 * align_up(chunks * 4, 256);
 }
 
 size_t seg_ws_bytes(int64_t n_total, int64_t num_segments, bool vals);

@@ -19,7 +19,9 @@ template <int DT, int KPT>
 __global__ __launch_bounds__(kMergeThreads) void k_merge_keys(const uint32_t* __restrict__ kin,
                                                               uint32_t* __restrict__ kout,
                                                               const int32_t* __restrict__ part,
-                                                              int64_t n, int64_t L, int vec) {
+                                                              int64_t n, int64_t L, int vec,
+                                                              uint32_t* __restrict__ samp_first,
+                                                              uint32_t* __restrict__ samp_last) {
     static_assert(DT == kU32 || DT == kI32, "integer keys only");
     using Key = std::conditional_t<DT == kI32, int32_t, uint32_t>;
     constexpr Key kMax = DT == kI32 ? (Key)0x7fffffff : (Key)0xffffffffu;
@@ -109,6 +111,18 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_keys(const uint32_t* __
             for (int k = 0; k < 4; ++k)
                 if (e + k < cnt) ko[e + k] = st[pe + k];
         }
+    }
+    // Chunk samples for the next pass's splits: the tile's first and last key
+    // of every chunk, written by the first wavefront as two contiguous runs.
+    constexpr int kChunks = MT / kSampleChunk;
+    static_assert(2 * kChunks <= kMergeThreads, "one thread per sample");
+    const int c = (int)threadIdx.x;
+    if (c < kChunks) {
+        const int e = c * kSampleChunk;
+        if (e < cnt) samp_first[g0 / kSampleChunk + c] = st[e + (e >> 4)];
+    } else if (c < 2 * kChunks) {
+        const int e = (c - kChunks) * kSampleChunk + kSampleChunk - 1;
+        if (e < cnt) samp_last[g0 / kSampleChunk + (c - kChunks)] = st[e + (e >> 4)];
     }
 }
 

@@ -12,23 +12,29 @@ namespace msn {
 template <int DT, int K, bool STABLE, int VM, int SHAPE>
 __global__ __launch_bounds__((TileTraits<DT, K, STABLE, SHAPE>::kThreads)) void k_block_sort(
     const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, int64_t n,
-    int vec) {
+    int vec, uint32_t* samp_first, uint32_t* samp_last) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int kTile = TileTraits<DT, K, STABLE, SHAPE>::kTile;
     const int64_t base = (int64_t)blockIdx.x * kTile;
     const int nv = (int)((n - base) < kTile ? (n - base) : kTile);
     block_sort_tile<DT, K, STABLE, VM, SHAPE>(kin + base, VM == kVals ? vin + base : nullptr,
                                              kout + base, VM != kNoVals ? vout + base : nullptr,
-                                             nv, (uint32_t)base, smem, vec != 0);
+                                             nv, (uint32_t)base, smem, vec != 0,
+                                             Samples{samp_first, samp_last, base});
 }
 
 // ------------------------------------------------------- merge-path split ---
 // For merge tile t of a pass that merges runs of length L: the number of
 // elements of the pair's left run among the tile's first output position.
 // One binary search per tile (Green, McColl, Bader 2012); stable (left run
-// wins ties).
+// wins ties).  The search first runs over chunk-aligned candidates, reading
+// the chunk samples the previous sweep wrote (A's chunk-first keys, B's
+// chunk-last keys: a few MiB, cache- and TLB-friendly), which narrows it to
+// one chunk; the last steps read the runs themselves.
 template <int DT>
 __global__ __launch_bounds__(256) void k_partition(const uint32_t* __restrict__ kin,
+                                                   const uint32_t* __restrict__ samp_first,
+                                                   const uint32_t* __restrict__ samp_last,
                                                    int32_t* __restrict__ part, int64_t n,
                                                    int64_t L, int mt, int ntiles) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -43,6 +49,26 @@ __global__ __launch_bounds__(256) void k_partition(const uint32_t* __restrict__ 
     const uint32_t* B = A + la;
     int64_t lo = d > lb ? d - lb : 0;
     int64_t hi = d < la ? d : la;
+    if (lb > 0 && lo < hi) {
+        // base, la (= L), d and every candidate are multiples of the chunk, so
+        // A[i] is a chunk's first key and B[d-1-i] a full chunk's last key.
+        constexpr int64_t G = kSampleChunk;
+        int64_t clo = (lo + G - 1) / G;
+        int64_t chi = (hi - 1) / G;
+        while (clo <= chi) {
+            const int64_t cm = (clo + chi) >> 1;
+            const int64_t i = cm * G;
+            const uint32_t a = samp_first[(base + i) / G];
+            const uint32_t b = samp_last[(base + la + d - i) / G - 1];
+            if (!(ord_key<DT>(b) < ord_key<DT>(a))) {
+                lo = i + 1;
+                clo = cm + 1;
+            } else {
+                hi = i;
+                chi = cm - 1;
+            }
+        }
+    }
     while (lo < hi) {
         const int64_t mid = (lo + hi) >> 1;
         if (!(ord_key<DT>(B[d - 1 - mid]) < ord_key<DT>(A[mid])))
@@ -65,7 +91,9 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge(const uint32_t* __restr
                                                          uint32_t* __restrict__ kout,
                                                          uint32_t* __restrict__ vout,
                                                          const int32_t* __restrict__ part,
-                                                         int64_t n, int64_t L, int vec) {
+                                                         int64_t n, int64_t L, int vec,
+                                                         uint32_t* __restrict__ samp_first,
+                                                         uint32_t* __restrict__ samp_last) {
     constexpr int MT = KPT * kMergeThreads;
     extern __shared__ __align__(16) unsigned char smem[];
     uint32_t* sk = reinterpret_cast<uint32_t*>(smem);
@@ -117,6 +145,10 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge(const uint32_t* __restr
     serial_merge<uint32_t, KPT, VALS>(sk, 0, na, na, nb, i, d - i, cnt - 1, o, src,
                                       OrdLess<DT>{});
     uint32_t* ko = kout + g0 + d;
+    // chunk samples (KPT divides the chunk, so a thread holds at most one of each)
+    if (((g0 + d) & (kSampleChunk - 1)) == 0) samp_first[(g0 + d) / kSampleChunk] = o[0];
+    if (((g0 + d + KPT - 1) & (kSampleChunk - 1)) == kSampleChunk - 1 && d + KPT <= cnt)
+        samp_last[(g0 + d + KPT - 1) / kSampleChunk] = o[KPT - 1];
     if (vec && d + KPT <= cnt) {
 #pragma unroll
         for (int q = 0; q < KPT / 4; ++q)
@@ -154,7 +186,8 @@ int ensure_lds(Kern kern, size_t bytes) {
 }
 
 template <int DT, int K, bool STABLE, int VM, int SHAPE = 0>
-int launch_block_sort(const SortArgs& a, uint32_t* kdst, uint32_t* vdst, int vec) {
+int launch_block_sort(const SortArgs& a, uint32_t* kdst, uint32_t* vdst, int vec,
+                      const Samples& sm) {
     using Tr = TileTraits<DT, K, STABLE, SHAPE>;
     auto kern = &k_block_sort<DT, K, STABLE, VM, SHAPE>;
     if (int rc = ensure_lds(kern, Tr::kLdsBytes)) return rc;
@@ -162,7 +195,7 @@ int launch_block_sort(const SortArgs& a, uint32_t* kdst, uint32_t* vdst, int vec
     {
         LaunchTimer timer("block_sort", a.n, a.stream);
         hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(Tr::kThreads), Tr::kLdsBytes,
-                           a.stream, a.kin, a.vin, kdst, vdst, a.n, vec);
+                           a.stream, a.kin, a.vin, kdst, vdst, a.n, vec, sm.first, sm.last);
     }
     return (int)hipGetLastError();
 }
@@ -176,16 +209,17 @@ inline int block_shape(const SortArgs& a) {
 }
 
 template <int DT, int K>
-int dispatch_block_sort(const SortArgs& a, uint32_t* kdst, uint32_t* vdst, int vec) {
-    if (a.vmode == kVals) return launch_block_sort<DT, K, true, kVals>(a, kdst, vdst, vec);
-    if (a.vmode == kArg) return launch_block_sort<DT, K, true, kArg>(a, kdst, vdst, vec);
+int dispatch_block_sort(const SortArgs& a, uint32_t* kdst, uint32_t* vdst, int vec,
+                        const Samples& sm) {
+    if (a.vmode == kVals) return launch_block_sort<DT, K, true, kVals>(a, kdst, vdst, vec, sm);
+    if (a.vmode == kArg) return launch_block_sort<DT, K, true, kArg>(a, kdst, vdst, vec, sm);
     if constexpr (DT == kF32) {
-        return launch_block_sort<DT, K, true, kNoVals>(a, kdst, vdst, vec);
+        return launch_block_sort<DT, K, true, kNoVals>(a, kdst, vdst, vec, sm);
     } else {
         switch (block_shape(a)) {
-            case 1: return launch_block_sort<DT, K, false, kNoVals, 1>(a, kdst, vdst, vec);
-            case 2: return launch_block_sort<DT, K, false, kNoVals, 2>(a, kdst, vdst, vec);
-            default: return launch_block_sort<DT, K, false, kNoVals, 0>(a, kdst, vdst, vec);
+            case 1: return launch_block_sort<DT, K, false, kNoVals, 1>(a, kdst, vdst, vec, sm);
+            case 2: return launch_block_sort<DT, K, false, kNoVals, 2>(a, kdst, vdst, vec, sm);
+            default: return launch_block_sort<DT, K, false, kNoVals, 0>(a, kdst, vdst, vec, sm);
         }
     }
 }
@@ -204,13 +238,13 @@ inline int first_run_length(const SortArgs& a) {
 
 template <int DT, int KPT, bool VALS>
 int launch_merge(const SortArgs& a, const uint32_t* ks, const uint32_t* vs, uint32_t* kd,
-                 uint32_t* vd, int32_t* part, int64_t L, int vec) {
+                 uint32_t* vd, int32_t* part, int64_t L, int vec, const Samples& sm) {
     constexpr int MT = KPT * kMergeThreads;
     const int ntiles = (int)((a.n + MT - 1) / MT);
     {
         LaunchTimer timer("partition", ntiles, a.stream);
         hipLaunchKernelGGL(k_partition<DT>, dim3((ntiles + 255) / 256), dim3(256), 0, a.stream,
-                           ks, part, a.n, L, MT, ntiles);
+                           ks, sm.first, sm.last, part, a.n, L, MT, ntiles);
     }
     if (int rc = (int)hipGetLastError()) return rc;
     if constexpr (!VALS && DT != kF32) {
@@ -220,25 +254,25 @@ int launch_merge(const SortArgs& a, const uint32_t* ks, const uint32_t* vs, uint
         if (int rc = ensure_lds(kern, lds)) return rc;
         LaunchTimer timer("merge", a.n, a.stream);
         hipLaunchKernelGGL(kern, dim3(ntiles), dim3(kMergeThreads), lds, a.stream, ks, kd, part,
-                           a.n, L, vec);
+                           a.n, L, vec, sm.first, sm.last);
     } else {
         auto kern = &k_merge<DT, KPT, VALS>;
         const size_t lds = (size_t)lds_words<uint32_t>(MT) * 4 * (VALS ? 2 : 1);
         if (int rc = ensure_lds(kern, lds)) return rc;
         LaunchTimer timer("merge", a.n, a.stream);
         hipLaunchKernelGGL(kern, dim3(ntiles), dim3(kMergeThreads), lds, a.stream, ks, vs, kd, vd,
-                           part, a.n, L, vec);
+                           part, a.n, L, vec, sm.first, sm.last);
     }
     return (int)hipGetLastError();
 }
 
 template <int DT, bool VALS>
 int dispatch_merge(const SortArgs& a, const uint32_t* ks, const uint32_t* vs, uint32_t* kd,
-                   uint32_t* vd, int32_t* part, int64_t L, int vec) {
+                   uint32_t* vd, int32_t* part, int64_t L, int vec, const Samples& sm) {
     switch (a.merge_tile) {
-        case 2048: return launch_merge<DT, 8, VALS>(a, ks, vs, kd, vd, part, L, vec);
-        case 8192: return launch_merge<DT, 32, VALS>(a, ks, vs, kd, vd, part, L, vec);
-        default: return launch_merge<DT, 16, VALS>(a, ks, vs, kd, vd, part, L, vec);
+        case 2048: return launch_merge<DT, 8, VALS>(a, ks, vs, kd, vd, part, L, vec, sm);
+        case 8192: return launch_merge<DT, 32, VALS>(a, ks, vs, kd, vd, part, L, vec, sm);
+        default: return launch_merge<DT, 16, VALS>(a, ks, vs, kd, vd, part, L, vec, sm);
     }
 }
 
@@ -255,6 +289,11 @@ int run_sort(const SortArgs& a) {
     uint32_t* wk = reinterpret_cast<uint32_t*>(ws);
     uint32_t* wv = vals ? reinterpret_cast<uint32_t*>(ws + nk) : nullptr;
     int32_t* part = reinterpret_cast<int32_t*>(ws + nk + (vals ? nk : 0));
+    const size_t ntile_max = (size_t)((a.n + kMinMergeTile - 1) / kMinMergeTile) + 1;
+    uint8_t* sbase = reinterpret_cast<uint8_t*>(part) + align_up(ntile_max * 4, 256);
+    const size_t nchunks = (size_t)((a.n + kSampleChunk - 1) / kSampleChunk);
+    Samples sm{reinterpret_cast<uint32_t*>(sbase),
+               reinterpret_cast<uint32_t*>(sbase + align_up(nchunks * 4, 256)), 0};
 
     // Ping-pong so that the last pass lands in the output.
     uint32_t* kb[2] = {a.kout, wk};
@@ -265,15 +304,16 @@ int run_sort(const SortArgs& a) {
                                (a.vmode != kVals || aligned(a.vin))));
 
     int cur = passes & 1;
-    int rc = a.leaf_k == 8 ? dispatch_block_sort<DT, 8>(a, kb[cur], vb[cur], vec)
-                           : dispatch_block_sort<DT, 4>(a, kb[cur], vb[cur], vec);
+    int rc = a.leaf_k == 8 ? dispatch_block_sort<DT, 8>(a, kb[cur], vb[cur], vec, sm)
+                           : dispatch_block_sort<DT, 4>(a, kb[cur], vb[cur], vec, sm);
     if (rc) return rc;
     for (int p = 0; p < passes; ++p) {
         const int64_t L = (int64_t)tile << p;
         const int nxt = cur ^ 1;
-        rc = vals ? dispatch_merge<DT, true>(a, kb[cur], vb[cur], kb[nxt], vb[nxt], part, L, vec)
+        rc = vals ? dispatch_merge<DT, true>(a, kb[cur], vb[cur], kb[nxt], vb[nxt], part, L, vec,
+                                             sm)
                   : dispatch_merge<DT, false>(a, kb[cur], nullptr, kb[nxt], nullptr, part, L,
-                                              vec);
+                                              vec, sm);
         if (rc) return rc;
         cur = nxt;
     }
