@@ -150,22 +150,32 @@ def bench_keys(args):
         steps = args.steps if dist == "random" else max(2, args.steps // 4)
         log(f"[bench] {dist}: warmup {args.warmup}, timing {steps} steps")
         if dist == "random":
-            _lib.timing_enable(64 * (steps + 1))
-            # warmup first, then reset the events so only timed steps count
+            # eager steps with HIP events around every launch (per-kernel times)
             for _ in range(args.warmup):
                 plan.run(x)
             torch.cuda.synchronize()
             _lib.timing_enable(64 * (steps + 1))
-            ms, wall = time_steps(lambda: plan.run(x), steps, 0)
+            ms_eager, wall = time_steps(lambda: plan.run(x), steps, 0)
             stats = _lib.timing_read()
             _lib.timing_disable()
         else:
-            ms, wall = time_steps(lambda: plan.run(x), steps, args.warmup)
+            ms_eager, wall = time_steps(lambda: plan.run(x), steps, args.warmup)
+        # the same sort captured once in a HIP graph and replayed (no launch gaps)
+        if args.eager:
+            ms = ms_eager
+        else:
+            gstream = torch.cuda.Stream()
+            gstream.wait_stream(torch.cuda.current_stream())
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph, stream=gstream):
+                plan.run(x)
+            ms, wall = time_steps(graph.replay, steps, args.warmup)
+            del graph
         ok = check_sorted_u32(plan.out, x)
         if not ok:
             raise SystemExit(f"[bench] output check failed for {dist}")
         results[dist] = {"gkeys_per_s": n / (ms / 1e3) / 1e9, "ms_per_step": ms, "steps": steps,
-                         "wall_s": wall}
+                         "wall_s": wall, "eager_ms_per_step": ms_eager}
         log(f"[bench] {dist}: {ms:.3f} ms/step, {results[dist]['gkeys_per_s']:.2f} Gkeys/s")
         if dist == "random":
             m = stats.get("merge")
@@ -206,7 +216,11 @@ def bench_keys(args):
         "hbm_schedule": {"bytes_per_key": sched,
                          "implied_gkeys_at_peak": HBM_PEAK_GBPS / sched,
                          "frac": head["gkeys_per_s"] / (HBM_PEAK_GBPS / sched)},
-        "by_distribution": {d: {"gkeys_per_s": r["gkeys_per_s"], "ms_per_step": r["ms_per_step"]}
+        "timing": "graph replay of one msn_sort_keys call per step" if not args.eager
+                  else "eager msn_sort_keys call per step",
+        "eager_ms_per_step": head["eager_ms_per_step"],
+        "by_distribution": {d: {"gkeys_per_s": r["gkeys_per_s"], "ms_per_step": r["ms_per_step"],
+                                "eager_ms_per_step": r["eager_ms_per_step"]}
                             for d, r in results.items()},
         "kernels_ms_per_step": results.get("random", {}).get("kernels_ms_per_step"),
     }
@@ -495,6 +509,8 @@ def main():
     ap.add_argument("--dists", default="random,sorted,nearly")
     ap.add_argument("--cpu-sample", type=int, default=1 << 26)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--eager", action="store_true",
+                    help="time eager calls instead of replays of a captured HIP graph")
     ap.add_argument("--segments", type=int, default=100_000)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--retune", action="store_true", help="ignore the autotuner cache")

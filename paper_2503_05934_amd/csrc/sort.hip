@@ -138,42 +138,58 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge(const uint32_t* __restr
     __syncthreads();
 
     const int d = threadIdx.x * KPT;
-    if (d >= cnt) return;
-    const int i = corank_lds(sk, 0, na, na, nb, d, OrdLess<DT>{});
-    uint32_t o[KPT];
-    int src[KPT];
-    serial_merge<uint32_t, KPT, VALS>(sk, 0, na, na, nb, i, d - i, cnt - 1, o, src,
-                                      OrdLess<DT>{});
-    uint32_t* ko = kout + g0 + d;
-    // chunk samples (KPT divides the chunk, so a thread holds at most one of each)
-    if (((g0 + d) & (kSampleChunk - 1)) == 0) samp_first[(g0 + d) / kSampleChunk] = o[0];
-    if (((g0 + d + KPT - 1) & (kSampleChunk - 1)) == kSampleChunk - 1 && d + KPT <= cnt)
-        samp_last[(g0 + d + KPT - 1) / kSampleChunk] = o[KPT - 1];
-    if (vec && d + KPT <= cnt) {
+    uint32_t o[KPT], y[KPT];
+    if (d < cnt) {
+        const int i = corank_lds(sk, 0, na, na, nb, d, OrdLess<DT>{});
+        int src[KPT];
+        serial_merge<uint32_t, KPT, VALS>(sk, 0, na, na, nb, i, d - i, cnt - 1, o, src,
+                                          OrdLess<DT>{});
+        if constexpr (VALS) {
 #pragma unroll
-        for (int q = 0; q < KPT / 4; ++q)
-            *reinterpret_cast<uint4*>(ko + 4 * q) =
-                make_uint4(o[4 * q], o[4 * q + 1], o[4 * q + 2], o[4 * q + 3]);
-    } else {
-#pragma unroll
-        for (int k = 0; k < KPT; ++k)
-            if (d + k < cnt) ko[k] = o[k];
+            for (int k = 0; k < KPT; ++k) y[k] = sv[lds_idx<uint32_t>(min(src[k], cnt - 1))];
+        }
     }
-    if constexpr (VALS) {
-        uint32_t y[KPT];
+    // Stage outputs in LDS (a spare word every 16) and store them as
+    // contiguous 16-byte chunks per lane, keys and payload alike.
+    constexpr int kStage = MT + MT / 16;
+    uint32_t* stk = reinterpret_cast<uint32_t*>(smem);
+    uint32_t* stv = stk + kStage;
+    __syncthreads();
+    if (d < cnt) {
 #pragma unroll
-        for (int k = 0; k < KPT; ++k) y[k] = sv[lds_idx<uint32_t>(min(src[k], cnt - 1))];
-        uint32_t* vo = vout + g0 + d;
-        if (vec && d + KPT <= cnt) {
+        for (int k = 0; k < KPT; ++k) {
+            stk[(d + k) + ((d + k) >> 4)] = o[k];
+            if constexpr (VALS) stv[(d + k) + ((d + k) >> 4)] = y[k];
+        }
+    }
+    __syncthreads();
 #pragma unroll
-            for (int q = 0; q < KPT / 4; ++q)
-                *reinterpret_cast<uint4*>(vo + 4 * q) =
-                    make_uint4(y[4 * q], y[4 * q + 1], y[4 * q + 2], y[4 * q + 3]);
+    for (int q = 0; q < KPT / 4; ++q) {
+        const int e = 4 * ((int)threadIdx.x + q * kMergeThreads);
+        const int pe = e + (e >> 4);
+        if (vec && e + 4 <= cnt) {
+            *reinterpret_cast<uint4*>(kout + g0 + e) =
+                make_uint4(stk[pe], stk[pe + 1], stk[pe + 2], stk[pe + 3]);
+            if constexpr (VALS)
+                *reinterpret_cast<uint4*>(vout + g0 + e) =
+                    make_uint4(stv[pe], stv[pe + 1], stv[pe + 2], stv[pe + 3]);
         } else {
 #pragma unroll
-            for (int k = 0; k < KPT; ++k)
-                if (d + k < cnt) vo[k] = y[k];
+            for (int k = 0; k < 4; ++k)
+                if (e + k < cnt) {
+                    kout[g0 + e + k] = stk[pe + k];
+                    if constexpr (VALS) vout[g0 + e + k] = stv[pe + k];
+                }
         }
+    }
+    constexpr int kChunks = MT / kSampleChunk;
+    const int c = (int)threadIdx.x;
+    if (c < kChunks) {
+        const int e = c * kSampleChunk;
+        if (e < cnt) samp_first[g0 / kSampleChunk + c] = stk[e + (e >> 4)];
+    } else if (c < 2 * kChunks) {
+        const int e = (c - kChunks) * kSampleChunk + kSampleChunk - 1;
+        if (e < cnt) samp_last[g0 / kSampleChunk + (c - kChunks)] = stk[e + (e >> 4)];
     }
 }
 
@@ -257,7 +273,8 @@ int launch_merge(const SortArgs& a, const uint32_t* ks, const uint32_t* vs, uint
                            a.n, L, vec, sm.first, sm.last);
     } else {
         auto kern = &k_merge<DT, KPT, VALS>;
-        const size_t lds = (size_t)lds_words<uint32_t>(MT) * 4 * (VALS ? 2 : 1);
+        const size_t lds = (size_t)std::max(lds_words<uint32_t>(MT), MT + MT / 16) * 4 *
+                           (VALS ? 2 : 1);
         if (int rc = ensure_lds(kern, lds)) return rc;
         LaunchTimer timer("merge", a.n, a.stream);
         hipLaunchKernelGGL(kern, dim3(ntiles), dim3(kMergeThreads), lds, a.stream, ks, vs, kd, vd,
