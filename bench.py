@@ -136,7 +136,8 @@ def bench_keys(args):
     n = args.n
     leaf = args.leaf
     tuning = {k: v for k, v in (("merge_tile", args.merge_tile),
-                                ("block_tile", args.block_tile)) if v}
+                                ("block_tile", args.block_tile),
+                                ("merge_ways", args.merge_ways)) if v}
     plan = msn.SortPlan(n, torch.uint32, dev, leaf=leaf, tuning=tuning or None)
     results = {}
     roof = None
@@ -178,15 +179,20 @@ def bench_keys(args):
                          "wall_s": wall, "eager_ms_per_step": ms_eager}
         log(f"[bench] {dist}: {ms:.3f} ms/step, {results[dist]['gkeys_per_s']:.2f} Gkeys/s")
         if dist == "random":
-            m = stats.get("merge")
+            # the dominant merge kernel: four-way passes if the plan used them
+            mkind = max((k for k in ("merge", "merge4") if k in stats),
+                        key=lambda k: stats[k]["total_ms"], default=None)
+            m = stats.get(mkind) if mkind else None
             if m:
                 avg_s = m["avg_ms"] / 1e3
                 bytes_per_launch = 8.0 * n
                 achieved = bytes_per_launch / avg_s / 1e9
-                traffic = load_traffic("k_merge_keys_2p28_u32_traffic.md")
+                traffic = load_traffic("k_merge_keys_2p28_u32_traffic.md") \
+                    if mkind == "merge" else None
                 roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS,
                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
-                        "kernel": "k_merge (global merge-path pass)",
+                        "kernel": ("k_merge4 (four-way merge pass)" if mkind == "merge4"
+                                   else "k_merge_keys (binary merge-path pass)"),
                         "avg_launch_ms": m["avg_ms"], "launches": m["launches"],
                         "algorithmic_bytes_per_launch": bytes_per_launch}
             results[dist]["kernels_ms_per_step"] = {
@@ -506,6 +512,7 @@ def main():
     ap.add_argument("--leaf", default="6To8", choices=["6To8", "3To5"])
     ap.add_argument("--merge-tile", type=int, default=0)
     ap.add_argument("--block-tile", type=int, default=0)
+    ap.add_argument("--merge-ways", type=int, default=0)
     ap.add_argument("--dists", default="random,sorted,nearly")
     ap.add_argument("--cpu-sample", type=int, default=1 << 26)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")

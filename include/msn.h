@@ -87,6 +87,9 @@ extern "C" {
  *                   2048 x leaf size).  Only integer keys-only sorts use runs
  *                   above 1024 x leaf size; other sorts accept the value and
  *                   keep 1024 x leaf size.
+ *   merge_ways      fan-in of the global merge passes: 2 or 4 (default 4).
+ *                   Four-way passes serve integer keys-only sorts; the
+ *                   others always merge pairs of runs.
  */
 typedef struct {
     int32_t merge_tile;
@@ -95,7 +98,8 @@ typedef struct {
     int32_t seg_block_max;
     int32_t seg_grid;
     int32_t block_tile;
-    int32_t reserved[2];
+    int32_t merge_ways;
+    int32_t reserved;
 } msn_tuning;
 
 /*

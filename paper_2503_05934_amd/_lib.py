@@ -41,7 +41,8 @@ class Tuning(ctypes.Structure):
         ("seg_block_max", ctypes.c_int32),
         ("seg_grid", ctypes.c_int32),
         ("block_tile", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 2),
+        ("merge_ways", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:

@@ -93,6 +93,14 @@ int merge_tile_of(const msn_tuning* t, int* out) {
     return MSN_OK;
 }
 
+// Merge fan-in of the global passes: 2 or 4 (default 4).
+int merge_ways_of(const msn_tuning* t, int* out) {
+    const int w = t && t->merge_ways ? t->merge_ways : 4;
+    if (w != 2 && w != 4) return MSN_ERR_CONFIG;
+    *out = w;
+    return MSN_OK;
+}
+
 // First-sweep run length: 1024, 2048 or 4096 x the leaf size (default 2048 K).
 int block_tile_of(const msn_tuning* t, int k, int* out) {
     int bt = t && t->block_tile ? t->block_tile : msn::kDefaultBlockTileMult * k;
@@ -107,9 +115,10 @@ int sort_common(const void* keys_in, const uint32_t* vals_in, void* keys_out, ui
     if (!valid_dtype(dtype)) return MSN_ERR_DTYPE;
     const int k = leaf_keys(leaf);
     if (!k) return MSN_ERR_CONFIG;
-    int mt = 0, bt = 0;
+    int mt = 0, bt = 0, mw = 0;
     if (int rc = merge_tile_of(tuning, &mt)) return rc;
     if (int rc = block_tile_of(tuning, k, &bt)) return rc;
+    if (int rc = merge_ways_of(tuning, &mw)) return rc;
     if (n < 0 || n > kMaxN) return MSN_ERR_SIZE;
     if (n == 0) return MSN_OK;
     if (!keys_in || !keys_out) return MSN_ERR_NULL;
@@ -124,7 +133,7 @@ int sort_common(const void* keys_in, const uint32_t* vals_in, void* keys_out, ui
     const size_t need = msn::sort_ws_bytes(n, vmode != msn::kNoVals);
     if (!ws || ws_bytes < need) return MSN_ERR_WORKSPACE;
     msn::SortArgs a{static_cast<const uint32_t*>(keys_in), vals_in,
-                    static_cast<uint32_t*>(keys_out), vals_out, n, dtype, k, vmode, mt, bt, ws,
+                    static_cast<uint32_t*>(keys_out), vals_out, n, dtype, k, vmode, mt, bt, mw, ws,
                     ws_bytes, static_cast<hipStream_t>(stream)};
     return msn::launch_sort(a);
 }

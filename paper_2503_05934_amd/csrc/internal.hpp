@@ -33,6 +33,7 @@ struct SortArgs {
     int vmode;
     int merge_tile;       // 2048, 4096 or 8192
     int block_tile;       // first-sweep run length: 1024K, 2048K or 4096K
+    int merge_ways;       // 2 or 4 (four-way passes: integer keys-only sorts)
     void* ws;
     size_t ws_bytes;
     hipStream_t stream;
@@ -70,14 +71,37 @@ struct Samples {
 constexpr int kDefaultMergeTile = 8192;
 constexpr int kDefaultBlockTileMult = 2048;  // first-sweep run = 2048 x leaf size
 
+// Four-way passes: samples merged per group of four runs cut output tiles at
+// every kM4SamplesPerTile-th sample.
+constexpr int kM4SamplesPerTile = 27;
+
+// Upper bound on the tile boundaries of any four-way pass (runs of at least
+// 4096 keys): chunks / 27 + 2 per group + slack.
+inline size_t m4_max_bounds(int64_t n) {
+    const size_t chunks = (size_t)((n + kSampleChunk - 1) / kSampleChunk);
+    return chunks / kM4SamplesPerTile + (size_t)(n / 8192) + 8;
+}
+
+// Workspace of the four-way passes: merged sample keys and chunk indices,
+// their ping-pong copies, an index array, the sample-merge splits and the
+// boundary table (four splits per boundary).
+inline size_t m4_ws_bytes(int64_t n) {
+    const size_t chunks = (size_t)((n + kSampleChunk - 1) / kSampleChunk);
+    const size_t a = align_up(chunks * 4, 256);
+    const size_t parts = align_up((chunks / kMinMergeTile + 2) * 4, 256);
+    return 5 * a + parts + align_up(m4_max_bounds(n) * 16, 256);
+}
+
 // Workspace of the flat sort: ping-pong keys (+ values), one merge-path split
-// per merge tile, and the two chunk-sample arrays.
+// per merge tile, the two chunk-sample arrays, and (keys-only) the four-way
+// pass buffers.
 inline size_t sort_ws_bytes(int64_t n, bool vals) {
     const size_t nk = align_up((size_t)n * 4, 256);
     const size_t nv = vals ? nk : 0;
     const size_t tiles = (size_t)((n + kMinMergeTile - 1) / kMinMergeTile) + 1;
     const size_t chunks = (size_t)((n + kSampleChunk - 1) / kSampleChunk);
-    return nk + nv + align_up(tiles * 4, 256) + 2 * align_up(chunks * 4, 256);
+    return nk + nv + align_up(tiles * 4, 256) + 2 * align_up(chunks * 4, 256) +
+           (vals ? 0 : m4_ws_bytes(n));
 }
 
 size_t seg_ws_bytes(int64_t n_total, int64_t num_segments, bool vals);

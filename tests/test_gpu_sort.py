@@ -127,6 +127,54 @@ def test_block_tiles_give_identical_bits(orc, dtype, leaf, k):
             assert np.array_equal(y, ref), (bt, n)
 
 
+def _tricky_keys(n, kind, dtype, seed):
+    rng = np.random.default_rng(seed)
+    np_t = np.uint32 if dtype == "u32" else np.int32
+    if kind == "random":
+        return make_keys(n, dtype, seed)
+    if kind == "few":        # four distinct values: every sample ties
+        x = rng.integers(0, 4, n)
+    elif kind == "equal":
+        x = np.full(n, 3)
+    elif kind == "sorted":
+        x = np.sort(rng.integers(0, 1 << 20, n))
+    elif kind == "reversed":
+        x = np.sort(rng.integers(0, 1 << 20, n))[::-1]
+    else:                    # extremes of the type mixed with ties
+        lo, hi = (0, 2**32 - 1) if dtype == "u32" else (-2**31, 2**31 - 1)
+        x = rng.choice(np.array([lo, hi, 0, 1, hi - 1], dtype=np.int64), n)
+    return np.ascontiguousarray(x.astype(np.int64).astype(np_t) if dtype == "i32"
+                                else x.astype(np.uint64).astype(np_t))
+
+
+@pytest.mark.parametrize("leaf", ["6To8", "3To5"])
+@pytest.mark.parametrize("dtype", ["u32", "i32"])
+def test_four_way_passes_match_oracle_and_binary(orc, dtype, leaf):
+    """Four-way passes (sampled splitters) against the oracle and against
+    binary passes, on tie-heavy, sorted, reversed and extreme inputs, with
+    groups that end in one, two or three runs."""
+    t = 2048 * (8 if leaf == "6To8" else 4)   # default first-sweep run length
+    runs_list = [3, 4, 5, 6, 7, 9, 17, 64 + 3]
+    kinds = ["random", "few", "equal", "sorted", "reversed", "extremes"]
+    for i, runs in enumerate(runs_list):
+        n = runs * t - (i % 3) * 97
+        for kind in kinds:
+            x = _tricky_keys(n, kind, dtype, seed=100 * i + len(kind))
+            ref = orc.sort(x, dtype=dtype)
+            say(f"four-way dtype={dtype} leaf={leaf} n={n} kind={kind}")
+            y4 = host(msn.sort(gpu(x), leaf=leaf, tuning={"merge_ways": 4}))
+            assert np.array_equal(y4, ref), (n, kind, "4-way")
+            y2 = host(msn.sort(gpu(x), leaf=leaf, tuning={"merge_ways": 2}))
+            assert np.array_equal(y2, ref), (n, kind, "2-way")
+    for bt_mult in (1024, 2048, 4096):
+        k = 8 if leaf == "6To8" else 4
+        n = 23 * bt_mult * k + 1234
+        x = _tricky_keys(n, "few", dtype, seed=bt_mult)
+        say(f"four-way block_tile={bt_mult * k} n={n}")
+        y = host(msn.sort(gpu(x), leaf=leaf, tuning={"block_tile": bt_mult * k}))
+        assert np.array_equal(y, orc.sort(x, dtype=dtype)), bt_mult
+
+
 def test_unaligned_views(orc):
     # offsets by one element: 4-byte aligned, not 16-byte aligned
     n = 50001
