@@ -137,7 +137,8 @@ def bench_keys(args):
     leaf = args.leaf
     tuning = {k: v for k, v in (("merge_tile", args.merge_tile),
                                 ("block_tile", args.block_tile),
-                                ("merge_ways", args.merge_ways)) if v}
+                                ("merge_ways", args.merge_ways),
+                                ("merge4_kpt", args.merge4_kpt)) if v}
     plan = msn.SortPlan(n, torch.uint32, dev, leaf=leaf, tuning=tuning or None)
     results = {}
     roof = None
@@ -513,6 +514,8 @@ def main():
     ap.add_argument("--merge-tile", type=int, default=0)
     ap.add_argument("--block-tile", type=int, default=0)
     ap.add_argument("--merge-ways", type=int, default=0)
+    ap.add_argument("--merge4-kpt", type=int, default=0,
+                    help="keys per thread of the four-way merge kernel (16 or 32)")
     ap.add_argument("--dists", default="random,sorted,nearly")
     ap.add_argument("--cpu-sample", type=int, default=1 << 26)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")

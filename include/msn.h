@@ -90,6 +90,8 @@ extern "C" {
  *   merge_ways      fan-in of the global merge passes: 2 or 4 (default 4).
  *                   Four-way passes serve integer keys-only sorts; the
  *                   others always merge pairs of runs.
+ *   merge4_kpt      keys per thread of the four-way merge kernel: 16 (512
+ *                   threads per tile) or 32 (256 threads); default 16.
  */
 typedef struct {
     int32_t merge_tile;
@@ -99,7 +101,7 @@ typedef struct {
     int32_t seg_grid;
     int32_t block_tile;
     int32_t merge_ways;
-    int32_t reserved;
+    int32_t merge4_kpt;
 } msn_tuning;
 
 /*

@@ -42,11 +42,11 @@ class Tuning(ctypes.Structure):
         ("seg_grid", ctypes.c_int32),
         ("block_tile", ctypes.c_int32),
         ("merge_ways", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("merge4_kpt", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 def make_tuning(params: dict | None) -> Tuning | None:

@@ -101,6 +101,14 @@ int merge_ways_of(const msn_tuning* t, int* out) {
     return MSN_OK;
 }
 
+// Keys per thread of the four-way merge kernel: 16 or 32 (default 16).
+int merge4_kpt_of(const msn_tuning* t, int* out) {
+    const int v = t && t->merge4_kpt ? t->merge4_kpt : 16;
+    if (v != 16 && v != 32) return MSN_ERR_CONFIG;
+    *out = v;
+    return MSN_OK;
+}
+
 // First-sweep run length: 1024, 2048 or 4096 x the leaf size (default 2048 K).
 int block_tile_of(const msn_tuning* t, int k, int* out) {
     int bt = t && t->block_tile ? t->block_tile : msn::kDefaultBlockTileMult * k;
@@ -115,8 +123,9 @@ int sort_common(const void* keys_in, const uint32_t* vals_in, void* keys_out, ui
     if (!valid_dtype(dtype)) return MSN_ERR_DTYPE;
     const int k = leaf_keys(leaf);
     if (!k) return MSN_ERR_CONFIG;
-    int mt = 0, bt = 0, mw = 0;
+    int mt = 0, bt = 0, mw = 0, m4k = 0;
     if (int rc = merge_tile_of(tuning, &mt)) return rc;
+    if (int rc = merge4_kpt_of(tuning, &m4k)) return rc;
     if (int rc = block_tile_of(tuning, k, &bt)) return rc;
     if (int rc = merge_ways_of(tuning, &mw)) return rc;
     if (n < 0 || n > kMaxN) return MSN_ERR_SIZE;
@@ -133,7 +142,7 @@ int sort_common(const void* keys_in, const uint32_t* vals_in, void* keys_out, ui
     const size_t need = msn::sort_ws_bytes(n, vmode != msn::kNoVals);
     if (!ws || ws_bytes < need) return MSN_ERR_WORKSPACE;
     msn::SortArgs a{static_cast<const uint32_t*>(keys_in), vals_in,
-                    static_cast<uint32_t*>(keys_out), vals_out, n, dtype, k, vmode, mt, bt, mw, ws,
+                    static_cast<uint32_t*>(keys_out), vals_out, n, dtype, k, vmode, mt, bt, mw, m4k, ws,
                     ws_bytes, static_cast<hipStream_t>(stream)};
     return msn::launch_sort(a);
 }

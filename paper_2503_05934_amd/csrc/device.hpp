@@ -198,7 +198,10 @@ __device__ __forceinline__ void wave_merge(T (&v)[K], int lane) {
 // so that the strided accesses of merge path do not pile onto few banks.
 template <typename T>
 __device__ __forceinline__ int lds_idx(int i) {
-    return sizeof(T) == 8 ? i + (i >> 4) : i + (i >> 5);
+    // indices are never negative: unsigned shifts let the compiler fold the
+    // scaling into one shift-add
+    const unsigned u = (unsigned)i;
+    return (int)(sizeof(T) == 8 ? u + (u >> 4) : u + (u >> 5));
 }
 template <typename T>
 __host__ __device__ constexpr int lds_words(int n) {

@@ -34,6 +34,7 @@ struct SortArgs {
     int merge_tile;       // 2048, 4096 or 8192
     int block_tile;       // first-sweep run length: 1024K, 2048K or 4096K
     int merge_ways;       // 2 or 4 (four-way passes: integer keys-only sorts)
+    int merge4_kpt;       // keys per thread of the four-way merge: 16 or 32
     void* ws;
     size_t ws_bytes;
     hipStream_t stream;

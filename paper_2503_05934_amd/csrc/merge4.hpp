@@ -27,12 +27,18 @@
 
 namespace msn {
 
-constexpr int kM4Threads = 512;
-constexpr int kM4KPT = 16;
 constexpr int kM4MaxTile = (kM4SamplesPerTile + 4) * kSampleChunk - 4;
-static_assert(kM4MaxTile <= kM4Threads * kM4KPT, "a tile fits one workgroup");
-// level 1 needs ceil(nx/KPT) + ceil(ny/KPT) <= kMaxTile/KPT + 2 threads
-static_assert(kM4MaxTile / kM4KPT + 2 <= kM4Threads, "level-1 threads fit");
+constexpr int kM4Gap = 64;  // slice spacing in LDS (>= KPT sentinels, lane-aligned)
+// LDS keys: the slices with their gaps, or X and Y with theirs (Y starts at a
+// multiple of 32 at least KPT <= 32 past X), plus a dummy slot.
+__host__ __device__ constexpr int m4_buf_keys() { return kM4MaxTile + 4 * kM4Gap + 8; }
+// Level 1 needs ceil(nx/KPT) + ceil(ny/KPT) <= kM4MaxTile/KPT + 2 threads.
+// LDS words: the padded buffer, or the staged output (a spare word every 16).
+__host__ __device__ constexpr int m4_lds_words(int threads, int kpt) {
+    return lds_words<uint32_t>(m4_buf_keys()) + 16 > threads * kpt + threads * kpt / 16 + 16
+               ? lds_words<uint32_t>(m4_buf_keys()) + 16
+               : threads * kpt + threads * kpt / 16 + 16;
+}
 
 // Geometry of one four-way pass (host-computed, passed by value).
 struct M4Geom {
@@ -154,23 +160,84 @@ __global__ __launch_bounds__(256) void k_m4_split(const uint32_t* __restrict__ i
     bnd[row * 4 + r] = (int32_t)split;
 }
 
+// Byte offset of padded LDS slot i (one spare word every 32, as lds_idx):
+// 4 * (i + i / 32) in one shift and one shift-add.
+__device__ __forceinline__ uint32_t m4_off(uint32_t i) {
+    uint32_t r;
+    asm("v_add_lshl_u32 %0, %1, %2, 2" : "=v"(r) : "v"(i), "v"(i >> 5));
+    return r;
+}
+
+template <typename Key>
+__device__ __forceinline__ Key m4_ld(const unsigned char* sm, uint32_t i) {
+    return *reinterpret_cast<const Key*>(sm + m4_off(i));
+}
+
+// Merge path co-rank in padded LDS (A at a0, B at b0): keys of A among the
+// first d outputs, A first on ties.
+template <typename Key>
+__device__ __forceinline__ int m4_corank(const unsigned char* sm, int a0, int la, int b0, int lb,
+                                         int d) {
+    int lo = d > lb ? d - lb : 0;
+    int hi = d < la ? d : la;
+    const int kb = b0 + d - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (!(m4_ld<Key>(sm, kb - mid) < m4_ld<Key>(sm, a0 + mid)))
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// KPT outputs of the merge of two sentinel-closed LDS runs from positions
+// pa, pb.  The state is the head x of the run that gave the last output (next
+// key at pc) and the head y of the other run (next key at po).  Equal keys
+// may come from either run: the values are those of the stable merge, which
+// is all a keys-only sort keeps.
+template <typename Key, int KPT>
+__device__ __forceinline__ void m4_serial(const unsigned char* sm, uint32_t pa, uint32_t pb,
+                                          Key (&out)[KPT]) {
+    Key x = m4_ld<Key>(sm, pa);
+    Key y = m4_ld<Key>(sm, pb);
+    uint32_t pc = pa + 1, po = pb + 1;
+#pragma unroll
+    for (int k = 0; k < KPT; ++k) {
+        const bool keep = x <= y;
+        out[k] = keep ? x : y;
+        const Key hi = keep ? y : x;
+        const uint32_t p = keep ? pc : po;
+        po = keep ? po : pc;
+        pc = p + 1;
+        x = m4_ld<Key>(sm, p);
+        y = hi;
+    }
+}
+
 // Merges one tile: the four run slices between two boundaries, in one LDS
 // buffer that holds, in turn, the four slices, the two level-1 results, and
 // the staged output (level results pass through registers between barriers).
-template <int DT>
-__global__ __launch_bounds__(kM4Threads) void k_merge4(const uint32_t* __restrict__ in,
-                                                       uint32_t* __restrict__ out,
-                                                       const int32_t* __restrict__ bnd,
-                                                       M4Geom g4,
-                                                       uint32_t* __restrict__ samp_first,
-                                                       uint32_t* __restrict__ samp_last) {
+// Slice r sits at tile position p_r + r * kM4Gap (a multiple of 64 apart),
+// so a wavefront's 64 consecutive keys that lie in one slice are read from
+// one scalar base and written to LDS at one scalar offset.
+template <int DT, int THREADS, int KPT>
+__global__ __launch_bounds__(THREADS) void k_merge4(const uint32_t* __restrict__ in,
+                                                    uint32_t* __restrict__ out,
+                                                    const int32_t* __restrict__ bnd, M4Geom g4,
+                                                    uint32_t* __restrict__ samp_first,
+                                                    uint32_t* __restrict__ samp_last) {
     static_assert(DT == kU32 || DT == kI32, "integer keys only");
+    static_assert(kM4MaxTile <= THREADS * KPT && kM4MaxTile / KPT + 2 <= THREADS, "tile fits");
+    static_assert(KPT == 16 || KPT == 32, "outputs of a thread stay in one padded 32-block");
     using Key = std::conditional_t<DT == kI32, int32_t, uint32_t>;
     constexpr Key kMax = DT == kI32 ? (Key)0x7fffffff : (Key)0xffffffffu;
-    constexpr int KPT = kM4KPT;
-    constexpr int kBuf = kM4MaxTile + 4 * KPT + 8;  // keys + sentinels, unpadded
-    extern __shared__ __align__(16) unsigned char smem[];
-    Key* b = reinterpret_cast<Key*>(smem);
+    constexpr int kBuf = m4_buf_keys();
+    constexpr uint32_t kDummy = kBuf - 1;
+    // static LDS: its base is a compile-time constant the address math folds
+    __shared__ __align__(16) uint32_t lds[m4_lds_words(THREADS, KPT)];
+    unsigned char* smem = reinterpret_cast<unsigned char*>(lds);
+    Key* b = reinterpret_cast<Key*>(lds);
 
     const int64_t t = blockIdx.x;
     int64_t g, j;
@@ -192,89 +259,118 @@ __global__ __launch_bounds__(kM4Threads) void k_merge4(const uint32_t* __restric
         ostart += lo[r];
     }
     const int p1 = c[0], p2 = p1 + c[1], p3 = p2 + c[2], cnt = p3 + c[3];
-    const int o1 = c[0] + KPT, o2 = o1 + c[1] + KPT, o3 = o2 + c[2] + KPT;  // slice offsets
     const int tid = threadIdx.x;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const uint32_t lane = (uint32_t)tid & 63u;
+    const uint32_t lane4 = lane * 4u;
+    const uint32_t plane = 4u * (lane + (lane >> 5));  // padded byte offset in a 64-block
 
-    // load the four slices (every load issued before the first LDS write).
-    // Tile element x of slice r sits at group offset x + sh[r] (32-bit: a
-    // group spans 4L <= 2^31 keys).
+    // ---- load the four slices (all loads issued before the first LDS write).
+    // Wave w loads tile keys [w * 64 KPT, (w + 1) * 64 KPT).  A chunk inside
+    // one slice reads from one scalar base at constant offsets; a chunk that
+    // crosses a slice boundary (or the tile end) picks the slice per lane.
     {
+        const int pst[4] = {0, p1, p2, p3};
+        auto slice_of = [&](int x) {
+            return (x >= p1 ? 1 : 0) + (x >= p2 ? 1 : 0) + (x >= p3 ? 1 : 0);
+        };
+        // tile key x of slice r is group key x + sh_r
         const uint32_t* gin = in + gb;
-        const uint32_t L32 = (uint32_t)g4.L;
-        const uint32_t sh[4] = {(uint32_t)lo[0], L32 + lo[1] - p1, 2 * L32 + lo[2] - p2,
-                                3 * L32 + lo[3] - p3};
+        const int64_t L = g4.L;
+        const int64_t sh0 = lo[0], sh1 = L + lo[1] - p1, sh2 = 2 * L + lo[2] - p2,
+                      sh3 = 3 * L + lo[3] - p3;
+        const int X0 = wv * 64 * KPT;
+        const int r0 = slice_of(X0), r1 = slice_of(X0 + 64 * KPT - 1);
         Key rk[KPT];
-        int pos[KPT];
+        if (X0 + 64 * KPT <= cnt && r0 == r1) {
+            const int64_t sh = r0 == 0 ? sh0 : r0 == 1 ? sh1 : r0 == 2 ? sh2 : sh3;
+            const char* sp = reinterpret_cast<const char*>(gin + X0 + sh) + lane4;
 #pragma unroll
-        for (int q = 0; q < KPT; ++q) {
-            const int x = tid + q * kM4Threads;
-            const int xc = min(x, cnt - 1);
-            const int r = (xc >= p1 ? 1 : 0) + (xc >= p2 ? 1 : 0) + (xc >= p3 ? 1 : 0);
-            const uint32_t s = r == 0 ? sh[0] : r == 1 ? sh[1] : r == 2 ? sh[2] : sh[3];
-            rk[q] = (Key)gin[(uint32_t)xc + s];
-            pos[q] = x < cnt ? x + r * KPT : kBuf - 1;
+            for (int q = 0; q < KPT; ++q) rk[q] = *reinterpret_cast<const Key*>(sp + 256 * q);
+            const uint32_t base = (uint32_t)(X0 + r0 * kM4Gap);  // a multiple of 64
+            unsigned char* dp = smem + plane + 4u * (base + (base >> 5));
+#pragma unroll
+            for (int q = 0; q < KPT; ++q) *reinterpret_cast<Key*>(dp + 264 * q) = rk[q];
+        } else if (X0 < cnt) {
+#pragma unroll
+            for (int q = 0; q < KPT; ++q) {
+                const int x = X0 + 64 * q + (int)lane;
+                const int xc = min(x, cnt - 1);
+                int64_t sh = sh0;
+                sh = xc >= p1 ? sh1 : sh;
+                sh = xc >= p2 ? sh2 : sh;
+                sh = xc >= p3 ? sh3 : sh;
+                rk[q] = (Key)gin[xc + sh];
+            }
+#pragma unroll
+            for (int q = 0; q < KPT; ++q) {
+                const int x = X0 + 64 * q + (int)lane;
+                const uint32_t pos = x < cnt ? (uint32_t)(x + slice_of(x) * kM4Gap) : kDummy;
+                *reinterpret_cast<Key*>(smem + m4_off(pos)) = rk[q];
+            }
         }
-#pragma unroll
-        for (int q = 0; q < KPT; ++q) b[lds_idx<Key>(pos[q])] = rk[q];
         if (tid < KPT) {
-            b[lds_idx<Key>(c[0] + tid)] = kMax;
-            b[lds_idx<Key>(o1 + c[1] + tid)] = kMax;
-            b[lds_idx<Key>(o2 + c[2] + tid)] = kMax;
-            b[lds_idx<Key>(o3 + c[3] + tid)] = kMax;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) b[lds_idx<Key>(pst[r] + r * kM4Gap + c[r] + tid)] = kMax;
         }
     }
     __syncthreads();
 
-    // level 1: X = merge(s0, s1), Y = merge(s2, s3); then b = [X | max.. | Y | max..]
+    // ---- level 1: X = merge(s0, s1) at 0, Y = merge(s2, s3) at ybase
     const int nx = p2, ny = cnt - p2;
+    const int ybase = (nx + KPT + 31) & ~31;
     const int tx = (nx + KPT - 1) / KPT, ty = (ny + KPT - 1) / KPT;
     {
-        // one code path for both halves: per-thread run parameters
         Key o[KPT];
         const bool in_x = tid < tx;
         const bool active = tid < tx + ty;
         const int d = in_x ? tid * KPT : (tid - tx) * KPT;
-        const int sa = in_x ? 0 : o2, la = in_x ? c[0] : c[2];
-        const int sb = in_x ? o1 : o3, lb = in_x ? c[1] : c[3];
-        const int base2 = in_x ? 0 : nx + KPT;
-        const int lim = active ? (in_x ? nx : ny) : 0;
+        const int sa = in_x ? 0 : p2 + 2 * kM4Gap, la = in_x ? c[0] : c[2];
+        const int sb = in_x ? p1 + kM4Gap : p3 + 3 * kM4Gap, lb = in_x ? c[1] : c[3];
+        const int base2 = (in_x ? 0 : ybase) + d;  // a multiple of KPT
         if (active) {
-            const int i = corank_lds(b, sa, la, sb, lb, d, PlainLess{});
-            serial_merge_closed<Key, KPT>(b, sa + i, sb + d - i, o);
+            const int i = m4_corank<Key>(smem, sa, la, sb, lb, d);
+            m4_serial<Key, KPT>(smem, (uint32_t)(sa + i), (uint32_t)(sb + d - i), o);
         }
         __syncthreads();
+        // outputs past the end of X (Y) are key maxima: the sentinels
+        if (active) {
+            Key* dst = b + (base2 + (base2 >> 5));
 #pragma unroll
-        for (int k = 0; k < KPT; ++k) {
-            const int pos = d + k < lim ? base2 + d + k : kBuf - 1;
-            b[lds_idx<Key>(pos)] = o[k];
+            for (int k = 0; k < KPT; ++k) dst[k] = o[k];
         }
         if (tid < KPT) {
             b[lds_idx<Key>(nx + tid)] = kMax;
-            b[lds_idx<Key>(nx + KPT + ny + tid)] = kMax;
+            b[lds_idx<Key>(ybase + ny + tid)] = kMax;
         }
     }
     __syncthreads();
 
-    // level 2: merge(X, Y)
+    // ---- level 2: merge(X, Y)
     const int d = tid * KPT;
     Key o[KPT];
     if (d < cnt) {
-        const int i = corank_lds(b, 0, nx, nx + KPT, ny, d, PlainLess{});
-        serial_merge_closed<Key, KPT>(b, i, nx + KPT + d - i, o);
+        const int i = m4_corank<Key>(smem, 0, nx, ybase, ny, d);
+        m4_serial<Key, KPT>(smem, (uint32_t)i, (uint32_t)(ybase + d - i), o);
     }
     // stage (a spare word every 16) and store lane-contiguous words
     uint32_t* st = reinterpret_cast<uint32_t*>(smem);
     __syncthreads();
     if (d < cnt) {
+        uint32_t* sd = st + (d + (d >> 4));
 #pragma unroll
-        for (int k = 0; k < KPT; ++k) st[(d + k) + ((d + k) >> 4)] = (uint32_t)o[k];
+        for (int k = 0; k < KPT; ++k) sd[k + (k >> 4)] = (uint32_t)o[k];
     }
     __syncthreads();
-    uint32_t* dst = out + ostart;
+    char* dst = reinterpret_cast<char*>(out + ostart);
+    uint32_t v[KPT];
+    const uint32_t* sr = st + (tid + (tid >> 4));
+#pragma unroll
+    for (int q = 0; q < KPT; ++q) v[q] = sr[q * (THREADS + THREADS / 16)];
 #pragma unroll
     for (int q = 0; q < KPT; ++q) {
-        const int e = tid + q * kM4Threads;
-        if (e < cnt) dst[e] = st[e + (e >> 4)];
+        const int e = tid + q * THREADS;
+        if (e < cnt) *reinterpret_cast<uint32_t*>(dst + 4u * (uint32_t)e) = v[q];
     }
     // chunk samples of the output for the next pass
     constexpr int G = kSampleChunk;
@@ -289,11 +385,5 @@ __global__ __launch_bounds__(kM4Threads) void k_merge4(const uint32_t* __restric
     }
 }
 
-inline size_t m4_lds_bytes() {
-    constexpr int kBuf = kM4MaxTile + 4 * kM4KPT + 8;
-    const size_t one = (size_t)(lds_words<uint32_t>(kBuf) + 16) * 4;
-    const size_t stage = (size_t)(kM4Threads * kM4KPT + kM4Threads * kM4KPT / 16 + 16) * 4;
-    return one > stage ? one : stage;
-}
 
 }  // namespace msn

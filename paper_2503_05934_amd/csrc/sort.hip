@@ -344,6 +344,17 @@ int sample_merge_pass(const SortArgs& a, const uint32_t* ks, const uint32_t* vs,
     return (int)hipGetLastError();
 }
 
+template <int DT, int THREADS, int KPT>
+int launch_merge4(const SortArgs& a, const uint32_t* in, uint32_t* out, const M4Geom& g4,
+                  const Samples& sm, const M4Work& w) {
+    {
+        LaunchTimer timer("merge4", a.n, a.stream);
+        hipLaunchKernelGGL((k_merge4<DT, THREADS, KPT>), dim3((unsigned)m4_tiles(g4)),
+                           dim3(THREADS), 0, a.stream, in, out, w.bnd, g4, sm.first, sm.last);
+    }
+    return (int)hipGetLastError();
+}
+
 // One four-way pass: runs of L in `in` -> runs of 4L in `out`.
 template <int DT>
 int run_merge4(const SortArgs& a, const uint32_t* in, uint32_t* out, int64_t L, const Samples& sm,
@@ -381,15 +392,8 @@ int run_merge4(const SortArgs& a, const uint32_t* in, uint32_t* out, int64_t L, 
                            a.stream, in, sm.first, w.mk, w.mv, w.bnd, g4, nb);
     }
     if (int rc = (int)hipGetLastError()) return rc;
-    auto kern = &k_merge4<DT>;
-    const size_t lds = m4_lds_bytes();
-    if (int rc = ensure_lds(kern, lds)) return rc;
-    {
-        LaunchTimer timer("merge4", a.n, a.stream);
-        hipLaunchKernelGGL(kern, dim3((unsigned)m4_tiles(g4)), dim3(kM4Threads), lds, a.stream,
-                           in, out, w.bnd, g4, sm.first, sm.last);
-    }
-    return (int)hipGetLastError();
+    return a.merge4_kpt == 32 ? launch_merge4<DT, 256, 32>(a, in, out, g4, sm, w)
+                              : launch_merge4<DT, 512, 16>(a, in, out, g4, sm, w);
 }
 
 template <int DT>

@@ -164,6 +164,8 @@ def test_four_way_passes_match_oracle_and_binary(orc, dtype, leaf):
             say(f"four-way dtype={dtype} leaf={leaf} n={n} kind={kind}")
             y4 = host(msn.sort(gpu(x), leaf=leaf, tuning={"merge_ways": 4}))
             assert np.array_equal(y4, ref), (n, kind, "4-way")
+            y4w = host(msn.sort(gpu(x), leaf=leaf, tuning={"merge_ways": 4, "merge4_kpt": 32}))
+            assert np.array_equal(y4w, ref), (n, kind, "4-way, 32 keys per thread")
             y2 = host(msn.sort(gpu(x), leaf=leaf, tuning={"merge_ways": 2}))
             assert np.array_equal(y2, ref), (n, kind, "2-way")
     for bt_mult in (1024, 2048, 4096):
