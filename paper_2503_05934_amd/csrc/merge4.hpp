@@ -28,6 +28,10 @@
 namespace msn {
 
 constexpr int kM4MaxTile = (kM4SamplesPerTile + 4) * kSampleChunk - 4;
+// Word 3 of a raw (unswizzled, stride 0) buffer descriptor on CDNA: 32-bit
+// data format; accesses at byte offsets >= num_records are dropped (stores)
+// or return zero (loads).
+constexpr int kRawBufferWord3 = 0x00020000;
 constexpr int kM4Gap = 64;  // slice spacing in LDS (>= KPT sentinels, lane-aligned)
 // LDS keys: the slices with their gaps, or X and Y with theirs (Y starts at a
 // multiple of 32 at least KPT <= 32 past X), plus a dummy slot.
@@ -40,6 +44,25 @@ __host__ __device__ constexpr int m4_lds_words(int threads, int kpt) {
                : threads * kpt + threads * kpt / 16 + 16;
 }
 
+// Division by a launch-invariant divisor with a multiply-high and shifts
+// (Granlund and Montgomery 1994, unsigned case): for 32-bit n and d >= 1,
+// q = (t + ((n - t) >> s1)) >> s2 with t = mulhi(n, mul).
+struct M4Div {
+    uint32_t mul, s1, s2;
+};
+
+inline M4Div m4_div(uint32_t d) {
+    uint32_t l = 0;
+    while ((1ull << l) < d) ++l;
+    const uint64_t m = ((1ull << 32) * ((1ull << l) - d)) / d + 1;
+    return {(uint32_t)m, l ? 1u : 0u, l ? l - 1 : 0u};
+}
+
+__device__ __forceinline__ uint32_t m4_udiv(uint32_t n, M4Div v) {
+    const uint32_t t = __umulhi(n, v.mul);
+    return (t + ((n - t) >> v.s1)) >> v.s2;
+}
+
 // Geometry of one four-way pass (host-computed, passed by value).
 struct M4Geom {
     int64_t n;
@@ -47,6 +70,7 @@ struct M4Geom {
     int64_t full_groups;  // groups of four full runs
     int tiles_full;       // tiles per full group
     int tiles_tail;       // tiles of the last, partial group (0 if none)
+    M4Div by_tiles;       // division by tiles_full
 };
 
 __host__ __device__ inline int64_t m4_ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -63,8 +87,9 @@ __host__ __device__ inline int64_t m4_group_samples(const M4Geom& g4, int64_t g)
 }
 
 inline M4Geom m4_geometry(int64_t n, int64_t L) {
-    M4Geom g4{n, L, n / (4 * L), 0, 0};
+    M4Geom g4{n, L, n / (4 * L), 0, 0, {}};
     g4.tiles_full = (int)m4_ceil_div(4 * L / kSampleChunk, kM4SamplesPerTile);
+    g4.by_tiles = m4_div((uint32_t)g4.tiles_full);
     if (n - g4.full_groups * 4 * L > 0)
         g4.tiles_tail = (int)m4_ceil_div(m4_group_samples(g4, g4.full_groups), kM4SamplesPerTile);
     return g4;
@@ -239,14 +264,13 @@ __global__ __launch_bounds__(THREADS) void k_merge4(const uint32_t* __restrict__
     unsigned char* smem = reinterpret_cast<unsigned char*>(lds);
     Key* b = reinterpret_cast<Key*>(lds);
 
-    const int64_t t = blockIdx.x;
+    // tile -> (group, tile of the group); grids stay below 2^31 tiles
+    const uint32_t t = blockIdx.x;
     int64_t g, j;
-    if (t < g4.full_groups * g4.tiles_full) {
-        g = t / g4.tiles_full;
-        j = t % g4.tiles_full;
-    } else {
-        g = g4.full_groups;
-        j = t - g4.full_groups * g4.tiles_full;
+    {
+        const uint32_t q = m4_udiv(t, g4.by_tiles);
+        g = q < (uint64_t)g4.full_groups ? q : g4.full_groups;
+        j = (int64_t)t - g * g4.tiles_full;
     }
     const int64_t row = m4_bound_row(g4, g, j);
     const int64_t gb = g * 4 * g4.L;
@@ -292,22 +316,22 @@ __global__ __launch_bounds__(THREADS) void k_merge4(const uint32_t* __restrict__
 #pragma unroll
             for (int q = 0; q < KPT; ++q) *reinterpret_cast<Key*>(dp + 264 * q) = rk[q];
         } else if (X0 < cnt) {
+            // group offsets of slice starts fit 32 bits: a group spans 4L < 2^32 keys
+            const uint32_t s0 = (uint32_t)sh0, s1 = (uint32_t)sh1, s2 = (uint32_t)sh2,
+                           s3 = (uint32_t)sh3;
+            uint32_t pos[KPT];
 #pragma unroll
             for (int q = 0; q < KPT; ++q) {
                 const int x = X0 + 64 * q + (int)lane;
                 const int xc = min(x, cnt - 1);
-                int64_t sh = sh0;
-                sh = xc >= p1 ? sh1 : sh;
-                sh = xc >= p2 ? sh2 : sh;
-                sh = xc >= p3 ? sh3 : sh;
-                rk[q] = (Key)gin[xc + sh];
+                const bool c1 = xc >= p1, c2 = xc >= p2, c3 = xc >= p3;
+                const uint32_t s = c3 ? s3 : c2 ? s2 : c1 ? s1 : s0;
+                const uint32_t gap = c3 ? 3 * kM4Gap : c2 ? 2 * kM4Gap : c1 ? kM4Gap : 0;
+                rk[q] = (Key)gin[(uint32_t)xc + s];
+                pos[q] = x < cnt ? (uint32_t)x + gap : kDummy;
             }
 #pragma unroll
-            for (int q = 0; q < KPT; ++q) {
-                const int x = X0 + 64 * q + (int)lane;
-                const uint32_t pos = x < cnt ? (uint32_t)(x + slice_of(x) * kM4Gap) : kDummy;
-                *reinterpret_cast<Key*>(smem + m4_off(pos)) = rk[q];
-            }
+            for (int q = 0; q < KPT; ++q) *reinterpret_cast<Key*>(smem + m4_off(pos[q])) = rk[q];
         }
         if (tid < KPT) {
 #pragma unroll
@@ -362,16 +386,17 @@ __global__ __launch_bounds__(THREADS) void k_merge4(const uint32_t* __restrict__
         for (int k = 0; k < KPT; ++k) sd[k + (k >> 4)] = (uint32_t)o[k];
     }
     __syncthreads();
-    char* dst = reinterpret_cast<char*>(out + ostart);
     uint32_t v[KPT];
     const uint32_t* sr = st + (tid + (tid >> 4));
 #pragma unroll
     for (int q = 0; q < KPT; ++q) v[q] = sr[q * (THREADS + THREADS / 16)];
+    // raw buffer stores: the descriptor's byte bound (cnt keys) drops the
+    // stores past the tile end, so the rows need no per-lane guard
+    const __amdgpu_buffer_rsrc_t ro =
+        __builtin_amdgcn_make_buffer_rsrc(out + ostart, 0, cnt * 4, kRawBufferWord3);
 #pragma unroll
-    for (int q = 0; q < KPT; ++q) {
-        const int e = tid + q * THREADS;
-        if (e < cnt) *reinterpret_cast<uint32_t*>(dst + 4u * (uint32_t)e) = v[q];
-    }
+    for (int q = 0; q < KPT; ++q)
+        __builtin_amdgcn_raw_buffer_store_b32(v[q], ro, (tid + q * THREADS) * 4, 0, 0);
     // chunk samples of the output for the next pass
     constexpr int G = kSampleChunk;
     const int f0 = (int)((G - (ostart % G)) % G);             // first chunk start in the tile
