@@ -83,15 +83,9 @@ inline size_t m4_max_bounds(int64_t n) {
     return chunks / kM4SamplesPerTile + (size_t)(n / 8192) + 8;
 }
 
-// Workspace of the four-way passes: merged sample keys and chunk indices,
-// their ping-pong copies, an index array, the sample-merge splits and the
-// boundary table (four splits per boundary).
-inline size_t m4_ws_bytes(int64_t n) {
-    const size_t chunks = (size_t)((n + kSampleChunk - 1) / kSampleChunk);
-    const size_t a = align_up(chunks * 4, 256);
-    const size_t parts = align_up((chunks / kMinMergeTile + 2) * 4, 256);
-    return 5 * a + parts + align_up(m4_max_bounds(n) * 16, 256);
-}
+// Workspace of the four-way passes: the boundary table (four splits per
+// tile boundary).
+inline size_t m4_ws_bytes(int64_t n) { return align_up(m4_max_bounds(n) * 16, 256); }
 
 // Workspace of the flat sort: ping-pong keys (+ values), one merge-path split
 // per merge tile, the two chunk-sample arrays, and (keys-only) the four-way

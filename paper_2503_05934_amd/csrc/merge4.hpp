@@ -5,13 +5,13 @@
 // Output tiles are cut at sampled splitters rather than at fixed output
 // positions, so no tile needs a four-sequence co-rank search:
 //   1. the chunk samples of the input (the first key of every 256-key chunk,
-//      left by the previous sweep) are runs of L/256 sorted keys; two binary
-//      merge passes over them (payload = chunk index) put each group's samples
-//      in total order (key, run, position);
-//   2. every kM4SamplesPerTile-th merged sample is a tile boundary; k_m4_split
-//      finds, for each of the four runs, how many of its keys precede it
-//      (its own run: its position; earlier runs: keys <= it; later runs:
-//      keys < it), searching the run's chunk samples first;
+//      left by the previous sweep) are runs of L/256 sorted keys; k_m4_bounds
+//      ranks every sample in its group's total order (key, run, position) by
+//      binary searches of the other runs' samples;
+//   2. every kM4SamplesPerTile-th sample in that order is a tile boundary; its
+//      thread finds, for each of the four runs, how many of the run's keys
+//      precede it (its own run: its position; earlier runs: keys <= it; later
+//      runs: keys < it) by a search inside one chunk;
 //   3. k_merge4 merges a tile's four slices in LDS, two binary levels, and
 //      writes them at the output position the splits imply.
 // Between consecutive boundaries a run contributes a contiguous slice that
@@ -108,81 +108,95 @@ __device__ __forceinline__ int64_t m4_bound_row(const M4Geom& g4, int64_t g, int
     return g * (g4.tiles_full + 1) + j;
 }
 
-__global__ void k_iota(uint32_t* out, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = (uint32_t)i;
-}
-
-// Splits of every tile boundary: one thread per (boundary, run).
-// mkeys/mpay: each group's samples in total order, payload = global chunk
-// index.  bnd[row * 4 + r] = keys of run r before the boundary.
+// Tile boundaries of one four-way pass, one thread per input chunk sample.
+// A sample's rank in its group's total order (key, run, position) is its
+// index in its own run plus, for each other run, how many of that run's
+// samples precede it (earlier runs win ties).  Samples whose rank is a
+// positive multiple of kM4SamplesPerTile are the tile boundaries; their
+// thread turns each run's sample count into a key count by a search inside
+// one chunk and writes the boundary row: bnd[row * 4 + r] = keys of run r
+// before the boundary.  The group's first sample in that order writes the
+// group's rows 0 and `tiles`.  Chunks per run: 1 << lg_cl.
 template <int DT>
-__global__ __launch_bounds__(256) void k_m4_split(const uint32_t* __restrict__ in,
-                                                  const uint32_t* __restrict__ samp_first,
-                                                  const uint32_t* __restrict__ mkeys,
-                                                  const uint32_t* __restrict__ mpay,
-                                                  int32_t* __restrict__ bnd, M4Geom g4,
-                                                  int64_t nbounds) {
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= nbounds * 4) return;
-    const int64_t row = gid >> 2;
-    const int r = (int)(gid & 3);
-    int64_t g, j, tiles;
-    if (row < g4.full_groups * (g4.tiles_full + 1)) {
-        g = row / (g4.tiles_full + 1);
-        j = row % (g4.tiles_full + 1);
-        tiles = g4.tiles_full;
-    } else {
-        g = g4.full_groups;
-        j = row - g4.full_groups * (g4.tiles_full + 1);
-        tiles = g4.tiles_tail;
-    }
+__global__ __launch_bounds__(256) void k_m4_bounds(const uint32_t* __restrict__ in,
+                                                   const uint32_t* __restrict__ samp_first,
+                                                   int32_t* __restrict__ bnd, M4Geom g4,
+                                                   int lg_cl, int64_t nck) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nck) return;
     constexpr int64_t G = kSampleChunk;
+    const int64_t g = c >> (lg_cl + 2);
+    const int r = (int)((c >> lg_cl) & 3);
+    const int64_t ic = c & ((1ll << lg_cl) - 1);
     const int64_t gb = g * 4 * g4.L;
-    const int64_t rb = gb + r * g4.L;
-    const int64_t len = rb >= g4.n ? 0 : (g4.n - rb < g4.L ? g4.n - rb : g4.L);
-    int64_t split;
-    if (j == 0) {
-        split = 0;
-    } else if (j == tiles) {
-        split = len;
-    } else {
-        const int64_t idx = gb / G + j * kM4SamplesPerTile;
-        const uint32_t v = mkeys[idx];
-        const int64_t pos = (int64_t)mpay[idx] * G;          // the splitter's position
-        const int rs = (int)((pos - gb) / g4.L);
-        if (r == rs) {
-            split = pos - rb;
-        } else {
-            // keys of run r ordered before the splitter: earlier runs win ties
-            const bool le = r < rs;
-            const uint32_t ov = ord_key<DT>(v);
-            auto before = [&](uint32_t x) {
-                const uint32_t ox = ord_key<DT>(x);
-                return le ? ox <= ov : ox < ov;
-            };
-            // chunks whose first key is before the splitter: a prefix of run r
-            const int64_t nck = m4_ceil_div(len, G);
-            int64_t lo = 0, hi = nck;
-            while (lo < hi) {
-                const int64_t mid = (lo + hi) >> 1;
-                if (before(samp_first[rb / G + mid])) lo = mid + 1; else hi = mid;
-            }
-            if (lo == 0) {
-                split = 0;
-            } else {
-                // the count lies in [(lo-1)*G + 1, min(lo*G, len)]
-                int64_t a = (lo - 1) * G + 1;
-                int64_t b = lo * G < len ? lo * G : len;
-                while (a < b) {
-                    const int64_t mid = (a + b) >> 1;   // is key mid (0-based) before?
-                    if (before(in[rb + mid])) a = mid + 1; else b = mid;
-                }
-                split = a;
+    int64_t len[4], cnt[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int64_t rb = gb + k * g4.L;
+        len[k] = rb >= g4.n ? 0 : (g4.n - rb < g4.L ? g4.n - rb : g4.L);
+    }
+    const uint32_t ov = ord_key<DT>(samp_first[c]);
+    // samples of run k before this one: a prefix of run k, found by a
+    // binary search; the three searches advance in lockstep
+    int64_t lo[4], hi[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        lo[k] = 0;
+        hi[k] = k == r ? 0 : m4_ceil_div(len[k], G);
+    }
+    for (int it = 0; it <= lg_cl; ++it) {
+        uint32_t x[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            x[k] = lo[k] < hi[k] ? samp_first[(gb + k * g4.L) / G + ((lo[k] + hi[k]) >> 1)] : 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (lo[k] < hi[k]) {
+                const int64_t mid = (lo[k] + hi[k]) >> 1;
+                const uint32_t ox = ord_key<DT>(x[k]);
+                if (k < r ? ox <= ov : ox < ov) lo[k] = mid + 1; else hi[k] = mid;
             }
         }
     }
-    bnd[row * 4 + r] = (int32_t)split;
+    int64_t rank = ic;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        cnt[k] = k == r ? ic : lo[k];
+        if (k != r) rank += lo[k];
+    }
+    const int64_t tiles = g < g4.full_groups ? g4.tiles_full : g4.tiles_tail;
+    int32_t* row0 = bnd + m4_bound_row(g4, g, 0) * 4;
+    if (rank == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            row0[k] = 0;
+            row0[tiles * 4 + k] = (int32_t)len[k];
+        }
+        return;
+    }
+    if (rank % kM4SamplesPerTile != 0) return;
+    int32_t* rowj = row0 + (rank / kM4SamplesPerTile) * 4;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        int64_t split;
+        if (k == r) {
+            split = ic * G;
+        } else if (cnt[k] == 0) {
+            split = 0;
+        } else {
+            // the key count lies in [(cnt-1) G + 1, min(cnt G, len)]
+            const int64_t rb = gb + k * g4.L;
+            int64_t a = (cnt[k] - 1) * G + 1;
+            int64_t b = cnt[k] * G < len[k] ? cnt[k] * G : len[k];
+            while (a < b) {
+                const int64_t mid = (a + b) >> 1;  // is key mid (0-based) before?
+                const uint32_t ox = ord_key<DT>(in[rb + mid]);
+                if (k < r ? ox <= ov : ox < ov) a = mid + 1; else b = mid;
+            }
+            split = a;
+        }
+        rowj[k] = (int32_t)split;
+    }
 }
 
 // Byte offset of padded LDS slot i (one spare word every 32, as lds_idx):

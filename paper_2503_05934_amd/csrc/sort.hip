@@ -195,21 +195,6 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge(const uint32_t* __restr
     }
 }
 
-// Puts each group's chunk samples (four sorted runs, per_group samples in
-// all) in total order with one stable block sort per group; payload = global
-// chunk index.  For groups of at most one block tile of samples.
-template <int DT>
-__global__ __launch_bounds__(kBlockThreads) void k_sample_group_sort(const uint32_t* samp,
-                                                                     uint32_t* mk, uint32_t* mv,
-                                                                     int64_t nck,
-                                                                     int64_t per_group) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int64_t base = (int64_t)blockIdx.x * per_group;
-    const int nv = (int)(nck - base < per_group ? nck - base : per_group);
-    block_sort_tile<DT, 8, true, kArg>(samp + base, nullptr, mk + base, mv + base, nv,
-                                       (uint32_t)base, smem, false);
-}
-
 // ------------------------------------------------------------------ host ---
 namespace {
 
@@ -310,90 +295,35 @@ int dispatch_merge(const SortArgs& a, const uint32_t* ks, const uint32_t* vs, ui
     }
 }
 
-// Four-way pass buffers (inside the workspace, after the chunk samples).
-struct M4Work {
-    uint32_t* mk;    // merged sample keys
-    uint32_t* mv;    // their chunk indices
-    uint32_t* tk;    // after the first binary sample merge
-    uint32_t* tv;
-    uint32_t* pay;   // chunk indices in order
-    int32_t* part2;  // sample-merge splits
-    int32_t* bnd;    // four splits per tile boundary
-};
-
-// One binary merge pass over a small array (no samples kept, own timer label).
-template <int DT>
-int sample_merge_pass(const SortArgs& a, const uint32_t* ks, const uint32_t* vs, uint32_t* kd,
-                      uint32_t* vd, int32_t* part, int64_t n, int64_t L) {
-    constexpr int KPT = 8, MT = KPT * kMergeThreads;
-    const int ntiles = (int)((n + MT - 1) / MT);
-    {
-        LaunchTimer timer("sample_merge", n, a.stream);
-        hipLaunchKernelGGL(k_partition<DT>, dim3((ntiles + 255) / 256), dim3(256), 0, a.stream,
-                           ks, nullptr, nullptr, part, n, L, MT, ntiles);
-    }
-    if (int rc = (int)hipGetLastError()) return rc;
-    auto kern = &k_merge<DT, KPT, true>;
-    const size_t lds = (size_t)std::max(lds_words<uint32_t>(MT), MT + MT / 16) * 4 * 2;
-    if (int rc = ensure_lds(kern, lds)) return rc;
-    {
-        LaunchTimer timer("sample_merge", n, a.stream);
-        hipLaunchKernelGGL(kern, dim3(ntiles), dim3(kMergeThreads), lds, a.stream, ks, vs, kd, vd,
-                           part, n, L, 1, nullptr, nullptr);
-    }
-    return (int)hipGetLastError();
-}
-
 template <int DT, int THREADS, int KPT>
 int launch_merge4(const SortArgs& a, const uint32_t* in, uint32_t* out, const M4Geom& g4,
-                  const Samples& sm, const M4Work& w) {
+                  const int32_t* bnd, const Samples& sm) {
     {
         LaunchTimer timer("merge4", a.n, a.stream);
         hipLaunchKernelGGL((k_merge4<DT, THREADS, KPT>), dim3((unsigned)m4_tiles(g4)),
-                           dim3(THREADS), 0, a.stream, in, out, w.bnd, g4, sm.first, sm.last);
+                           dim3(THREADS), 0, a.stream, in, out, bnd, g4, sm.first, sm.last);
     }
     return (int)hipGetLastError();
 }
 
-// One four-way pass: runs of L in `in` -> runs of 4L in `out`.
+// One four-way pass: runs of L in `in` -> runs of 4L in `out`.  L is a
+// power of two (the first-sweep run length times a power of four).
 template <int DT>
 int run_merge4(const SortArgs& a, const uint32_t* in, uint32_t* out, int64_t L, const Samples& sm,
-               const M4Work& w) {
+               int32_t* bnd) {
     const M4Geom g4 = m4_geometry(a.n, L);
     const int64_t nck = (a.n + kSampleChunk - 1) / kSampleChunk;
-    const int64_t per_group = 4 * L / kSampleChunk;
-    using SortTr = TileTraits<DT, 8, true>;
-    if (per_group <= SortTr::kTile) {
-        auto kern = &k_sample_group_sort<DT>;
-        if (int rc = ensure_lds(kern, SortTr::kLdsBytes)) return rc;
-        const int64_t groups = (nck + per_group - 1) / per_group;
-        LaunchTimer timer("sample_sort", nck, a.stream);
-        hipLaunchKernelGGL(kern, dim3((unsigned)groups), dim3(kBlockThreads), SortTr::kLdsBytes,
-                           a.stream, sm.first, w.mk, w.mv, nck, per_group);
-    } else {
-        {
-            LaunchTimer timer("sample_merge", nck, a.stream);
-            hipLaunchKernelGGL(k_iota, dim3((unsigned)((nck + 255) / 256)), dim3(256), 0, a.stream,
-                               w.pay, nck);
-        }
-        if (int rc = (int)hipGetLastError()) return rc;
-        if (int rc = sample_merge_pass<DT>(a, sm.first, w.pay, w.tk, w.tv, w.part2, nck,
-                                           L / kSampleChunk))
-            return rc;
-        if (int rc = sample_merge_pass<DT>(a, w.tk, w.tv, w.mk, w.mv, w.part2, nck,
-                                           2 * L / kSampleChunk))
-            return rc;
-    }
-    if (int rc = (int)hipGetLastError()) return rc;
-    const int64_t nb = m4_bounds(g4);
+    int lg_cl = 0;
+    while ((int64_t)kSampleChunk << lg_cl < L) ++lg_cl;
+    if (((int64_t)kSampleChunk << lg_cl) != L) return (int)hipErrorInvalidValue;
     {
-        LaunchTimer timer("m4_split", nb, a.stream);
-        hipLaunchKernelGGL(k_m4_split<DT>, dim3((unsigned)((nb * 4 + 255) / 256)), dim3(256), 0,
-                           a.stream, in, sm.first, w.mk, w.mv, w.bnd, g4, nb);
+        LaunchTimer timer("m4_bounds", nck, a.stream);
+        hipLaunchKernelGGL(k_m4_bounds<DT>, dim3((unsigned)((nck + 255) / 256)), dim3(256), 0,
+                           a.stream, in, sm.first, bnd, g4, lg_cl, nck);
     }
     if (int rc = (int)hipGetLastError()) return rc;
-    return a.merge4_kpt == 32 ? launch_merge4<DT, 256, 32>(a, in, out, g4, sm, w)
-                              : launch_merge4<DT, 512, 16>(a, in, out, g4, sm, w);
+    return a.merge4_kpt == 32 ? launch_merge4<DT, 256, 32>(a, in, out, g4, bnd, sm)
+                              : launch_merge4<DT, 512, 16>(a, in, out, g4, bnd, sm);
 }
 
 template <int DT>
@@ -422,18 +352,8 @@ int run_sort(const SortArgs& a) {
     const size_t nchunks = (size_t)((a.n + kSampleChunk - 1) / kSampleChunk);
     const size_t ca = align_up(nchunks * 4, 256);
     Samples sm{reinterpret_cast<uint32_t*>(sbase), reinterpret_cast<uint32_t*>(sbase + ca), 0};
-    M4Work m4w{};
-    if (!vals) {
-        uint8_t* m = sbase + 2 * ca;
-        m4w.mk = reinterpret_cast<uint32_t*>(m);
-        m4w.mv = reinterpret_cast<uint32_t*>(m + ca);
-        m4w.tk = reinterpret_cast<uint32_t*>(m + 2 * ca);
-        m4w.tv = reinterpret_cast<uint32_t*>(m + 3 * ca);
-        m4w.pay = reinterpret_cast<uint32_t*>(m + 4 * ca);
-        m4w.part2 = reinterpret_cast<int32_t*>(m + 5 * ca);
-        m4w.bnd = reinterpret_cast<int32_t*>(
-            m + 5 * ca + align_up((nchunks / kMinMergeTile + 2) * 4, 256));
-    }
+    // boundary table of the four-way passes (keys-only sorts)
+    int32_t* bnd = vals ? nullptr : reinterpret_cast<int32_t*>(sbase + 2 * ca);
 
     // Ping-pong so that the last pass lands in the output.
     uint32_t* kb[2] = {a.kout, wk};
@@ -451,7 +371,7 @@ int run_sort(const SortArgs& a) {
     for (int p = 0; p < passes; ++p) {
         const int nxt = cur ^ 1;
         if (ways[p] == 4) {
-            if constexpr (DT != kF32) rc = run_merge4<DT>(a, kb[cur], kb[nxt], L, sm, m4w);
+            if constexpr (DT != kF32) rc = run_merge4<DT>(a, kb[cur], kb[nxt], L, sm, bnd);
         } else {
             rc = vals ? dispatch_merge<DT, true>(a, kb[cur], vb[cur], kb[nxt], vb[nxt], part, L,
                                                  vec, sm)
