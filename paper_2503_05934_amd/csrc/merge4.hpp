@@ -108,95 +108,341 @@ __device__ __forceinline__ int64_t m4_bound_row(const M4Geom& g4, int64_t g, int
     return g * (g4.tiles_full + 1) + j;
 }
 
-// Tile boundaries of one four-way pass, one thread per input chunk sample.
-// A sample's rank in its group's total order (key, run, position) is its
-// index in its own run plus, for each other run, how many of that run's
-// samples precede it (earlier runs win ties).  Samples whose rank is a
-// positive multiple of kM4SamplesPerTile are the tile boundaries; their
-// thread turns each run's sample count into a key count by a search inside
-// one chunk and writes the boundary row: bnd[row * 4 + r] = keys of run r
-// before the boundary.  The group's first sample in that order writes the
-// group's rows 0 and `tiles`.  Chunks per run: 1 << lg_cl.
+// Tile boundaries of one four-way pass.  A chunk sample's rank in its
+// group's total order (key, run, position) is its index in its own run plus,
+// for each other run, how many of that run's samples precede it (earlier runs
+// win ties).  Samples whose rank is a positive multiple of kM4SamplesPerTile
+// are the tile boundaries; their thread turns each run's sample count into a
+// key count by a search inside one chunk and writes the boundary row:
+// bnd[row * 4 + r] = keys of run r before the boundary.  The group's first
+// sample in that order writes the group's rows 0 and `tiles`.
+struct M4Group {
+    int64_t gb;       // first key of the group
+    int64_t len[4];   // run lengths (short or empty runs at the array end)
+    int64_t smp[4];   // chunk samples per run
+    int64_t tiles;    // tiles of the group
+};
+
+__device__ __forceinline__ M4Group m4_group(const M4Geom& g4, int64_t g) {
+    M4Group q;
+    q.gb = g * 4 * g4.L;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int64_t rb = q.gb + k * g4.L;
+        q.len[k] = rb >= g4.n ? 0 : (g4.n - rb < g4.L ? g4.n - rb : g4.L);
+        q.smp[k] = m4_ceil_div(q.len[k], kSampleChunk);
+    }
+    q.tiles = g < g4.full_groups ? g4.tiles_full : g4.tiles_tail;
+    return q;
+}
+
+// a[k] for a run index known only at run time, without local-memory indexing
+__device__ __forceinline__ int64_t m4_sel(const int64_t (&a)[4], int k) {
+    return k == 0 ? a[0] : k == 1 ? a[1] : k == 2 ? a[2] : a[3];
+}
+
+// Is a key (order-mapped) of run k ordered before the sample ov of run r?
+__device__ __forceinline__ bool m4_before(uint32_t ox, uint32_t ov, int k, int r) {
+    return k < r ? ox <= ov : ox < ov;
+}
+
+// Keys of run `run` (len keys) before the sample, given that `cnt` of the
+// run's chunk samples precede it: the count lies in [(cnt-1) G + 1,
+// min(cnt G, len)].  Two rounds of 16 independent loads: first the last key
+// of each 16-key block, then the keys of the block holding the transition.
 template <int DT>
-__global__ __launch_bounds__(256) void k_m4_bounds(const uint32_t* __restrict__ in,
-                                                   const uint32_t* __restrict__ samp_first,
-                                                   int32_t* __restrict__ bnd, M4Geom g4,
-                                                   int lg_cl, int64_t nck) {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= nck) return;
+__device__ int64_t m4_key_count(const uint32_t* __restrict__ run, int64_t len, int64_t cnt,
+                                uint32_t ov, int k, int r) {
     constexpr int64_t G = kSampleChunk;
-    const int64_t g = c >> (lg_cl + 2);
-    const int r = (int)((c >> lg_cl) & 3);
-    const int64_t ic = c & ((1ll << lg_cl) - 1);
-    const int64_t gb = g * 4 * g4.L;
-    int64_t len[4], cnt[4];
+    if (cnt == 0) return 0;
+    const int64_t A = (cnt - 1) * G + 1;
+    const int64_t B = cnt * G < len ? cnt * G : len;
+    // indices are clamped to B - 1 (>= A - 1, a valid key) so that the 16
+    // loads of a round issue together; results past B are masked off
+    uint32_t x[16];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int64_t rb = gb + k * g4.L;
-        len[k] = rb >= g4.n ? 0 : (g4.n - rb < g4.L ? g4.n - rb : g4.L);
+    for (int m = 0; m < 16; ++m) {
+        const int64_t idx = A + 16 * m + 15;
+        x[m] = run[idx < B ? idx : B - 1];
     }
-    const uint32_t ov = ord_key<DT>(samp_first[c]);
-    // samples of run k before this one: a prefix of run k, found by a
-    // binary search; the three searches advance in lockstep
-    int64_t lo[4], hi[4];
+    int full = 0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        lo[k] = 0;
-        hi[k] = k == r ? 0 : m4_ceil_div(len[k], G);
+    for (int m = 0; m < 16; ++m)
+        full += (int)((A + 16 * m + 15 < B) & m4_before(ord_key<DT>(x[m]), ov, k, r));
+    const int64_t a = A + 16 * full;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) x[u] = run[a + u < B ? a + u : B - 1];
+    int part = 0;
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+        part += (int)((a + u < B) & m4_before(ord_key<DT>(x[u]), ov, k, r));
+    return a + part;
+}
+
+// Number of entries of the sorted (order-mapped) LDS array s[0, n) ordered
+// before ov under the tie rule of runs k and r.
+__device__ __forceinline__ int m4_lds_count(const uint32_t* s, int n, uint32_t ov, int k, int r) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (m4_before(s[mid], ov, k, r)) lo = mid + 1; else hi = mid;
     }
-    for (int it = 0; it <= lg_cl; ++it) {
-        uint32_t x[4];
+    return lo;
+}
+
+// Three such counts at once, over s_j[0, m_j) with every m_j < 2^(lgmax+1):
+// binary lifting with one step size for all three, so their LDS reads are
+// in flight together.  k_j: the run of array j; r: the run of ov.  Each
+// array has a readable word before it (s_j[-1]).  An entry x is before ov
+// when x < ov + (k_j < r), compared in 64 bits.
+__device__ __forceinline__ void m4_lds_count3(const uint32_t* (&s)[3], const int (&m)[3],
+                                              const int (&k)[3], uint32_t ov, int r, int lgmax,
+                                              int (&c)[3]) {
+    int p[3] = {0, 0, 0};
+    uint64_t thr[3];
+    const uint32_t* base[3];
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-            x[k] = lo[k] < hi[k] ? samp_first[(gb + k * g4.L) / G + ((lo[k] + hi[k]) >> 1)] : 0;
+    for (int j = 0; j < 3; ++j) {
+        thr[j] = (uint64_t)ov + (k[j] < r ? 1u : 0u);
+        base[j] = s[j] - 1;
+    }
+    for (int b = 1 << lgmax; b > 0; b >>= 1) {
+        uint32_t x[3];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            if (lo[k] < hi[k]) {
-                const int64_t mid = (lo[k] + hi[k]) >> 1;
-                const uint32_t ox = ord_key<DT>(x[k]);
-                if (k < r ? ox <= ov : ox < ov) lo[k] = mid + 1; else hi[k] = mid;
-            }
+        for (int j = 0; j < 3; ++j) x[j] = base[j][min(p[j] + b, m[j])];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const int q = p[j] + b;
+            p[j] = (q <= m[j]) & ((uint64_t)x[j] < thr[j]) ? q : p[j];
         }
     }
-    int64_t rank = ic;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        cnt[k] = k == r ? ic : lo[k];
-        if (k != r) rank += lo[k];
-    }
-    const int64_t tiles = g < g4.full_groups ? g4.tiles_full : g4.tiles_tail;
-    int32_t* row0 = bnd + m4_bound_row(g4, g, 0) * 4;
+    for (int j = 0; j < 3; ++j) c[j] = p[j];
+}
+
+// Both boundary kernels rank kM4BoundsBlock samples per workgroup in LDS,
+// collect the boundary samples in an LDS list, and then refine all
+// (boundary, run) pairs at once, one per thread.
+constexpr int kM4BoundsBlock = 1024;
+constexpr int kM4MaxCuts = 64;  // boundaries per workgroup: 1024 / 27 + one per group
+constexpr int kM4SmallRun = 256;  // runs of at most this many chunks: small kernel
+
+struct M4Cut {
+    int64_t g, ic, rank;
+    int64_t cnt[4];
+    uint32_t ov;
+    int r;
+};
+
+// Key count of run k before boundary sample c, written to its row.
+template <int DT>
+__device__ __forceinline__ void m4_split_one(const uint32_t* __restrict__ in,
+                                             int32_t* __restrict__ bnd, const M4Geom& g4,
+                                             const M4Cut& c, int k) {
+    const M4Group q = m4_group(g4, c.g);
+    const int64_t split =
+        k == c.r ? c.ic * kSampleChunk
+                 : m4_key_count<DT>(in + q.gb + k * g4.L, m4_sel(q.len, k), m4_sel(c.cnt, k),
+                                    c.ov, k, c.r);
+    // ranks stay below 2^23 (n < 2^31 keys): 32-bit division
+    bnd[(m4_bound_row(g4, c.g, 0) + (uint32_t)c.rank / kM4SamplesPerTile) * 4 + k] = (int32_t)split;
+}
+
+// Records a ranked sample: the group's first sample writes rows 0 and
+// `tiles` at once; boundary samples go to the list (or, past its capacity,
+// are refined on the spot).
+template <int DT>
+__device__ __forceinline__ void m4_note(const uint32_t* __restrict__ in,
+                                        int32_t* __restrict__ bnd, const M4Geom& g4, int64_t g,
+                                        const M4Group& q, int r, int64_t ic, uint32_t ov,
+                                        int64_t rank, const int64_t (&cnt)[4], M4Cut* cuts,
+                                        int* ncut) {
     if (rank == 0) {
+        int32_t* row0 = bnd + m4_bound_row(g4, g, 0) * 4;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             row0[k] = 0;
-            row0[tiles * 4 + k] = (int32_t)len[k];
+            row0[q.tiles * 4 + k] = (int32_t)q.len[k];
         }
-        return;
-    }
-    if (rank % kM4SamplesPerTile != 0) return;
-    int32_t* rowj = row0 + (rank / kM4SamplesPerTile) * 4;
+    } else if ((uint32_t)rank % kM4SamplesPerTile == 0) {
+        M4Cut c;
+        c.g = g;
+        c.ic = ic;
+        c.rank = rank;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        int64_t split;
-        if (k == r) {
-            split = ic * G;
-        } else if (cnt[k] == 0) {
-            split = 0;
+        for (int k = 0; k < 4; ++k) c.cnt[k] = cnt[k];
+        c.ov = ov;
+        c.r = r;
+        const int e = atomicAdd(ncut, 1);
+        if (e < kM4MaxCuts) {
+            cuts[e] = c;
         } else {
-            // the key count lies in [(cnt-1) G + 1, min(cnt G, len)]
-            const int64_t rb = gb + k * g4.L;
-            int64_t a = (cnt[k] - 1) * G + 1;
-            int64_t b = cnt[k] * G < len[k] ? cnt[k] * G : len[k];
-            while (a < b) {
-                const int64_t mid = (a + b) >> 1;  // is key mid (0-based) before?
-                const uint32_t ox = ord_key<DT>(in[rb + mid]);
-                if (k < r ? ox <= ov : ox < ov) a = mid + 1; else b = mid;
-            }
-            split = a;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) m4_split_one<DT>(in, bnd, g4, c, k);
         }
-        rowj[k] = (int32_t)split;
     }
+}
+
+// The listed (boundary, run) pairs, one per thread.
+template <int DT>
+__device__ __forceinline__ void m4_refine(const uint32_t* __restrict__ in,
+                                          int32_t* __restrict__ bnd, const M4Geom& g4,
+                                          const M4Cut* cuts, int ncut) {
+    const int e = threadIdx.x >> 2, k = threadIdx.x & 3;
+    if (e < ncut && e < kM4MaxCuts) m4_split_one<DT>(in, bnd, g4, cuts[e], k);
+}
+
+// Groups of at most kM4SmallRun chunks per run: each workgroup ranks the
+// samples of kM4BoundsBlock / (4 CL) whole groups against each other in LDS.
+template <int DT>
+__global__ __launch_bounds__(256) void k_m4_bounds_small(const uint32_t* __restrict__ in,
+                                                         const uint32_t* __restrict__ samp_first,
+                                                         int32_t* __restrict__ bnd, M4Geom g4,
+                                                         int lg_cl, int64_t nck) {
+    __shared__ uint32_t smp_g[1 + kM4BoundsBlock];  // a guard word, then the samples
+    __shared__ M4Cut cuts[kM4MaxCuts];
+    __shared__ int ncut;
+    uint32_t* smp = smp_g + 1;
+    const int CL = 1 << lg_cl, GS = 4 * CL;
+    const int gpw = kM4BoundsBlock / GS;
+    const int64_t c0 = (int64_t)blockIdx.x * kM4BoundsBlock;
+    const int nh = (int)(nck - c0 < kM4BoundsBlock ? nck - c0 : kM4BoundsBlock);
+    if (threadIdx.x == 0) ncut = 0;
+    for (int i = threadIdx.x; i < nh; i += blockDim.x) smp[i] = ord_key<DT>(samp_first[c0 + i]);
+    __syncthreads();
+    for (int i = threadIdx.x; i < nh; i += blockDim.x) {
+        const int gl = i / GS, j = i - gl * GS;
+        const int64_t g = (int64_t)blockIdx.x * gpw + gl;
+        const M4Group q = m4_group(g4, g);
+        const int r = j >> lg_cl;
+        const int64_t ic = j & (CL - 1);
+        const uint32_t ov = smp[i];
+        const uint32_t* gs = smp + gl * GS;  // the group's runs: k CL apart
+        const int o[3] = {r == 0 ? 1 : 0, r <= 1 ? 2 : 1, r <= 2 ? 3 : 2};  // the other runs
+        const uint32_t* sa[3] = {gs + o[0] * CL, gs + o[1] * CL, gs + o[2] * CL};
+        const int ma[3] = {(int)m4_sel(q.smp, o[0]), (int)m4_sel(q.smp, o[1]),
+                           (int)m4_sel(q.smp, o[2])};
+        int cj[3];
+        m4_lds_count3(sa, ma, o, ov, r, lg_cl, cj);
+        int64_t cnt[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            cnt[k] = k == r ? ic : k == o[0] ? cj[0] : k == o[1] ? cj[1] : cj[2];
+        const int64_t rank = ic + cj[0] + cj[1] + cj[2];
+        m4_note<DT>(in, bnd, g4, g, q, r, ic, ov, rank, cnt, cuts, &ncut);
+    }
+    __syncthreads();
+    m4_refine<DT>(in, bnd, g4, cuts, ncut);
+}
+
+// Larger groups: each workgroup ranks min(kM4BoundsBlock, CL) consecutive
+// samples of one run (CL, the run's chunk count, is a power of two).  For
+// each other run, every cs-th sample (cs = 256, or more for runs of over
+// 2^19 chunks, so that at most kM4Window are taken) is staged in LDS, which
+// brackets the block's counts to within cs-sample steps; the bracket (up to
+// kM4Window samples) is staged next and every count is finished in LDS.
+// Wider brackets (skewed inputs) are searched in global memory.
+constexpr int kM4Window = 2048;
+static_assert(kM4Window < (2 << 11), "window counts use 12 lifting steps");
+
+template <int DT>
+__global__ __launch_bounds__(256) void k_m4_bounds_large(const uint32_t* __restrict__ in,
+                                                         const uint32_t* __restrict__ samp_first,
+                                                         int32_t* __restrict__ bnd, M4Geom g4,
+                                                         int lg_cl, int64_t nck) {
+    __shared__ uint32_t vs[kM4BoundsBlock];
+    __shared__ uint32_t stage_g[3][1 + kM4Window];  // guard word + coarse samples / window
+    __shared__ M4Cut cuts[kM4MaxCuts];
+    __shared__ int64_t brk[6];
+    __shared__ int ncut;
+    const int tid = threadIdx.x;
+    const int bs = lg_cl < 10 ? 1 << lg_cl : kM4BoundsBlock;
+    const int lg_cs = lg_cl > 19 ? lg_cl - 11 : 8;  // coarse stride: at most 2^11 per run
+    const int64_t cs = 1ll << lg_cs;
+    const int64_t c0 = (int64_t)blockIdx.x * bs;
+    const int64_t g = c0 >> (lg_cl + 2);
+    const int r = (int)((c0 >> lg_cl) & 3);
+    const int64_t ic0 = c0 & ((1ll << lg_cl) - 1);
+    const M4Group q = m4_group(g4, g);
+    const int nh = (int)(nck - c0 < bs ? nck - c0 : bs);
+    const int o[3] = {r == 0 ? 1 : 0, r <= 1 ? 2 : 1, r <= 2 ? 3 : 2};  // the other runs
+    int64_t nsm[3];
+    const uint32_t* rs[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        nsm[j] = m4_sel(q.smp, o[j]);
+        rs[j] = samp_first + (q.gb + o[j] * g4.L) / kSampleChunk;
+    }
+    if (tid == 0) ncut = 0;
+    for (int i = tid; i < nh; i += 256) vs[i] = ord_key<DT>(samp_first[c0 + i]);
+    // every cs-th sample of each other run
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const int nc = (int)m4_ceil_div(nsm[j], cs);
+        for (int i = tid; i < nc; i += 256) (stage_g[j] + 1)[i] = ord_key<DT>(rs[j][(int64_t)i << lg_cs]);
+    }
+    __syncthreads();
+    // brackets: with c coarse samples before v, the count lies in
+    // [(c - 1) cs + 1, min(c cs, n)] (or is 0 when c == 0)
+    if (tid < 6) {
+        const int j = tid >> 1;
+        const uint32_t ov = vs[(tid & 1) ? nh - 1 : 0];
+        const int nc = (int)m4_ceil_div(nsm[j], cs);
+        const int64_t c = m4_lds_count((stage_g[j] + 1), nc, ov, o[j], r);
+        brk[tid] = (tid & 1) ? (c * cs < nsm[j] ? c * cs : nsm[j])
+                             : (c == 0 ? 0 : (c - 1) * cs + 1);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const int64_t lo = brk[2 * j], hi = brk[2 * j + 1];
+        if (hi - lo <= kM4Window)
+            for (int i = tid; i < hi - lo; i += 256) (stage_g[j] + 1)[i] = ord_key<DT>(rs[j][lo + i]);
+    }
+    __syncthreads();
+    const bool narrow = brk[1] - brk[0] <= kM4Window && brk[3] - brk[2] <= kM4Window &&
+                        brk[5] - brk[4] <= kM4Window;
+    for (int i = tid; i < nh; i += 256) {
+        const uint32_t ov = vs[i];
+        const int64_t ic = ic0 + i;
+        int64_t cj[3];
+        int64_t rank = ic;
+        if (narrow) {  // all three brackets staged: counts in lockstep
+            const uint32_t* sa[3];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) sa[j] = stage_g[j] + 1;
+            const int ma[3] = {(int)(brk[1] - brk[0]), (int)(brk[3] - brk[2]),
+                               (int)(brk[5] - brk[4])};
+            int c3[3];
+            m4_lds_count3(sa, ma, o, ov, r, 11, c3);
+#pragma unroll
+            for (int j = 0; j < 3; ++j) cj[j] = brk[2 * j] + c3[j];
+            rank += cj[0] + cj[1] + cj[2];
+        } else {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const int64_t lo = brk[2 * j], hi = brk[2 * j + 1];
+            if (hi - lo <= kM4Window) {
+                cj[j] = lo + m4_lds_count((stage_g[j] + 1), (int)(hi - lo), ov, o[j], r);
+            } else {
+                int64_t a = lo, b = hi;
+                while (a < b) {
+                    const int64_t mid = (a + b) >> 1;
+                    if (m4_before(ord_key<DT>(rs[j][mid]), ov, o[j], r)) a = mid + 1; else b = mid;
+                }
+                cj[j] = a;
+            }
+            rank += cj[j];
+        }
+        }
+        int64_t cnt[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            cnt[k] = k == r ? ic : k == o[0] ? cj[0] : k == o[1] ? cj[1] : cj[2];
+        m4_note<DT>(in, bnd, g4, g, q, r, ic, ov, rank, cnt, cuts, &ncut);
+    }
+    __syncthreads();
+    m4_refine<DT>(in, bnd, g4, cuts, ncut);
 }
 
 // Byte offset of padded LDS slot i (one spare word every 32, as lds_idx):

@@ -318,8 +318,15 @@ int run_merge4(const SortArgs& a, const uint32_t* in, uint32_t* out, int64_t L, 
     if (((int64_t)kSampleChunk << lg_cl) != L) return (int)hipErrorInvalidValue;
     {
         LaunchTimer timer("m4_bounds", nck, a.stream);
-        hipLaunchKernelGGL(k_m4_bounds<DT>, dim3((unsigned)((nck + 255) / 256)), dim3(256), 0,
-                           a.stream, in, sm.first, bnd, g4, lg_cl, nck);
+        if ((1 << lg_cl) <= kM4SmallRun) {
+            hipLaunchKernelGGL(k_m4_bounds_small<DT>,
+                               dim3((unsigned)((nck + kM4BoundsBlock - 1) / kM4BoundsBlock)),
+                               dim3(256), 0, a.stream, in, sm.first, bnd, g4, lg_cl, nck);
+        } else {
+            const int64_t bs = std::min<int64_t>(kM4BoundsBlock, (int64_t)1 << lg_cl);
+            hipLaunchKernelGGL(k_m4_bounds_large<DT>, dim3((unsigned)((nck + bs - 1) / bs)),
+                               dim3(256), 0, a.stream, in, sm.first, bnd, g4, lg_cl, nck);
+        }
     }
     if (int rc = (int)hipGetLastError()) return rc;
     return a.merge4_kpt == 32 ? launch_merge4<DT, 256, 32>(a, in, out, g4, bnd, sm)

@@ -136,6 +136,9 @@ def _tricky_keys(n, kind, dtype, seed):
         x = rng.integers(0, 4, n)
     elif kind == "equal":
         x = np.full(n, 3)
+    elif kind == "clustered":  # half uniform, half inside a narrow band
+        x = np.where(rng.random(n) < 0.5, rng.integers(0, 1 << 31, n),
+                     (1 << 30) + rng.integers(0, 1000, n))
     elif kind == "sorted":
         x = np.sort(rng.integers(0, 1 << 20, n))
     elif kind == "reversed":
@@ -168,6 +171,13 @@ def test_four_way_passes_match_oracle_and_binary(orc, dtype, leaf):
             assert np.array_equal(y4w, ref), (n, kind, "4-way, 32 keys per thread")
             y2 = host(msn.sort(gpu(x), leaf=leaf, tuning={"merge_ways": 2}))
             assert np.array_equal(y2, ref), (n, kind, "2-way")
+    # runs of 2^20 keys and more: boundary brackets wider than the LDS window
+    for kind in ("clustered", "random"):
+        n = 5 * (1 << 20) + 777
+        x = _tricky_keys(n, kind, dtype, seed=11)
+        say(f"four-way large groups dtype={dtype} leaf={leaf} n={n} kind={kind}")
+        y4 = host(msn.sort(gpu(x), leaf=leaf, tuning={"merge_ways": 4}))
+        assert np.array_equal(y4, orc.sort(x, dtype=dtype)), (n, kind)
     for bt_mult in (1024, 2048, 4096):
         k = 8 if leaf == "6To8" else 4
         n = 23 * bt_mult * k + 1234
