@@ -32,7 +32,8 @@ constexpr int kM4MaxTile = (kM4SamplesPerTile + 4) * kSampleChunk - 4;
 // data format; accesses at byte offsets >= num_records are dropped (stores)
 // or return zero (loads).
 constexpr int kRawBufferWord3 = 0x00020000;
-constexpr int kM4Gap = 64;  // slice spacing in LDS (>= KPT sentinels, lane-aligned)
+constexpr int kM4Gap = 64;  // slice spacing in LDS (> kM4Sent sentinels, lane-aligned)
+constexpr int kM4Sent = 32;  // outputs per thread of the merge levels = sentinels per run
 // LDS keys: the slices with their gaps, or X and Y with theirs (Y starts at a
 // multiple of 32 at least KPT <= 32 past X), plus a dummy slot.
 __host__ __device__ constexpr int m4_buf_keys() { return kM4MaxTile + 4 * kM4Gap + 8; }
@@ -513,7 +514,7 @@ __global__ __launch_bounds__(THREADS) void k_merge4(const uint32_t* __restrict__
                                                     uint32_t* __restrict__ samp_first,
                                                     uint32_t* __restrict__ samp_last) {
     static_assert(DT == kU32 || DT == kI32, "integer keys only");
-    static_assert(kM4MaxTile <= THREADS * KPT && kM4MaxTile / KPT + 2 <= THREADS, "tile fits");
+    static_assert(kM4MaxTile <= THREADS * KPT, "tile fits");
     static_assert(KPT == 16 || KPT == 32, "outputs of a thread stay in one padded 32-block");
     using Key = std::conditional_t<DT == kI32, int32_t, uint32_t>;
     constexpr Key kMax = DT == kI32 ? (Key)0x7fffffff : (Key)0xffffffffu;
@@ -575,6 +576,23 @@ __global__ __launch_bounds__(THREADS) void k_merge4(const uint32_t* __restrict__
             unsigned char* dp = smem + plane + 4u * (base + (base >> 5));
 #pragma unroll
             for (int q = 0; q < KPT; ++q) *reinterpret_cast<Key*>(dp + 264 * q) = rk[q];
+        } else if (X0 + 64 * KPT <= cnt && r1 == r0 + 1) {
+            // one boundary P (chunk offset) inside: slice r0 before it, r1 from it
+            const int P = (r1 == 1 ? p1 : r1 == 2 ? p2 : p3) - X0;
+            const int64_t sa = r0 == 0 ? sh0 : r0 == 1 ? sh1 : sh2;
+            const int64_t sb = r1 == 1 ? sh1 : r1 == 2 ? sh2 : sh3;
+            const uint32_t S0 = (uint32_t)(X0 + sa), S1 = (uint32_t)(X0 + sb);  // < 4L < 2^32
+            const uint32_t G0 = (uint32_t)(X0 + r0 * kM4Gap), G1 = G0 + kM4Gap;
+#pragma unroll
+            for (int q = 0; q < KPT; ++q) {
+                const int e = 64 * q + (int)lane;
+                rk[q] = (Key)gin[(uint32_t)e + (e >= P ? S1 : S0)];
+            }
+#pragma unroll
+            for (int q = 0; q < KPT; ++q) {
+                const int e = 64 * q + (int)lane;
+                *reinterpret_cast<Key*>(smem + m4_off((uint32_t)e + (e >= P ? G1 : G0))) = rk[q];
+            }
         } else if (X0 < cnt) {
             // group offsets of slice starts fit 32 bits: a group spans 4L < 2^32 keys
             const uint32_t s0 = (uint32_t)sh0, s1 = (uint32_t)sh1, s2 = (uint32_t)sh2,
@@ -593,37 +611,43 @@ __global__ __launch_bounds__(THREADS) void k_merge4(const uint32_t* __restrict__
 #pragma unroll
             for (int q = 0; q < KPT; ++q) *reinterpret_cast<Key*>(smem + m4_off(pos[q])) = rk[q];
         }
-        if (tid < KPT) {
+        // kM4Sent copies of the maximum close every slice (the merge levels
+        // take up to kM4Sent outputs per thread)
+        if (tid < kM4Sent) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) b[lds_idx<Key>(pst[r] + r * kM4Gap + c[r] + tid)] = kMax;
         }
     }
     __syncthreads();
 
-    // ---- level 1: X = merge(s0, s1) at 0, Y = merge(s2, s3) at ybase
+    // ---- level 1: X = merge(s0, s1) at 0, Y = merge(s2, s3) at ybase.  Both
+    // merge levels give MK = 32 outputs to each of the first tiles/32 threads
+    // (one co-rank search per 32 outputs); the others wait at the barriers.
+    constexpr int MK = kM4Sent;
+    static_assert(kM4MaxTile / MK + 2 <= THREADS && kM4Gap > MK, "merge shape");
     const int nx = p2, ny = cnt - p2;
-    const int ybase = (nx + KPT + 31) & ~31;
-    const int tx = (nx + KPT - 1) / KPT, ty = (ny + KPT - 1) / KPT;
+    const int ybase = (nx + MK + 31) & ~31;
+    const int tx = (nx + MK - 1) / MK, ty = (ny + MK - 1) / MK;
     {
-        Key o[KPT];
+        Key o[MK];
         const bool in_x = tid < tx;
         const bool active = tid < tx + ty;
-        const int d = in_x ? tid * KPT : (tid - tx) * KPT;
+        const int d = in_x ? tid * MK : (tid - tx) * MK;
         const int sa = in_x ? 0 : p2 + 2 * kM4Gap, la = in_x ? c[0] : c[2];
         const int sb = in_x ? p1 + kM4Gap : p3 + 3 * kM4Gap, lb = in_x ? c[1] : c[3];
-        const int base2 = (in_x ? 0 : ybase) + d;  // a multiple of KPT
+        const int base2 = (in_x ? 0 : ybase) + d;  // a multiple of 32
         if (active) {
             const int i = m4_corank<Key>(smem, sa, la, sb, lb, d);
-            m4_serial<Key, KPT>(smem, (uint32_t)(sa + i), (uint32_t)(sb + d - i), o);
+            m4_serial<Key, MK>(smem, (uint32_t)(sa + i), (uint32_t)(sb + d - i), o);
         }
         __syncthreads();
         // outputs past the end of X (Y) are key maxima: the sentinels
         if (active) {
             Key* dst = b + (base2 + (base2 >> 5));
 #pragma unroll
-            for (int k = 0; k < KPT; ++k) dst[k] = o[k];
+            for (int k = 0; k < MK; ++k) dst[k] = o[k];
         }
-        if (tid < KPT) {
+        if (tid < MK) {
             b[lds_idx<Key>(nx + tid)] = kMax;
             b[lds_idx<Key>(ybase + ny + tid)] = kMax;
         }
@@ -631,11 +655,11 @@ __global__ __launch_bounds__(THREADS) void k_merge4(const uint32_t* __restrict__
     __syncthreads();
 
     // ---- level 2: merge(X, Y)
-    const int d = tid * KPT;
-    Key o[KPT];
+    const int d = tid * MK;
+    Key o[MK];
     if (d < cnt) {
         const int i = m4_corank<Key>(smem, 0, nx, ybase, ny, d);
-        m4_serial<Key, KPT>(smem, (uint32_t)i, (uint32_t)(ybase + d - i), o);
+        m4_serial<Key, MK>(smem, (uint32_t)i, (uint32_t)(ybase + d - i), o);
     }
     // stage (a spare word every 16) and store lane-contiguous words
     uint32_t* st = reinterpret_cast<uint32_t*>(smem);
@@ -643,7 +667,7 @@ __global__ __launch_bounds__(THREADS) void k_merge4(const uint32_t* __restrict__
     if (d < cnt) {
         uint32_t* sd = st + (d + (d >> 4));
 #pragma unroll
-        for (int k = 0; k < KPT; ++k) sd[k + (k >> 4)] = (uint32_t)o[k];
+        for (int k = 0; k < MK; ++k) sd[k + (k >> 4)] = (uint32_t)o[k];
     }
     __syncthreads();
     uint32_t v[KPT];
