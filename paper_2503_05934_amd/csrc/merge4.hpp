@@ -38,11 +38,11 @@ constexpr int kM4Sent = 32;  // outputs per thread of the merge levels = sentine
 // multiple of 32 at least KPT <= 32 past X), plus a dummy slot.
 __host__ __device__ constexpr int m4_buf_keys() { return kM4MaxTile + 4 * kM4Gap + 8; }
 // Level 1 needs ceil(nx/KPT) + ceil(ny/KPT) <= kM4MaxTile/KPT + 2 threads.
-// LDS words: the padded buffer, or the staged output (a spare word every 16).
+// LDS words: the padded buffer, or the staged output (a spare word every 32).
 __host__ __device__ constexpr int m4_lds_words(int threads, int kpt) {
-    return lds_words<uint32_t>(m4_buf_keys()) + 16 > threads * kpt + threads * kpt / 16 + 16
+    return lds_words<uint32_t>(m4_buf_keys()) + 16 > threads * kpt + threads * kpt / 32 + 16
                ? lds_words<uint32_t>(m4_buf_keys()) + 16
-               : threads * kpt + threads * kpt / 16 + 16;
+               : threads * kpt + threads * kpt / 32 + 16;
 }
 
 // Division by a launch-invariant divisor with a multiply-high and shifts
@@ -661,19 +661,20 @@ __global__ __launch_bounds__(THREADS) void k_merge4(const uint32_t* __restrict__
         const int i = m4_corank<Key>(smem, 0, nx, ybase, ny, d);
         m4_serial<Key, MK>(smem, (uint32_t)i, (uint32_t)(ybase + d - i), o);
     }
-    // stage (a spare word every 16) and store lane-contiguous words
+    // stage (a spare word every 32: a thread's 32 outputs start on distinct
+    // banks) and store lane-contiguous words
     uint32_t* st = reinterpret_cast<uint32_t*>(smem);
     __syncthreads();
     if (d < cnt) {
-        uint32_t* sd = st + (d + (d >> 4));
+        uint32_t* sd = st + (d + (d >> 5));
 #pragma unroll
-        for (int k = 0; k < MK; ++k) sd[k + (k >> 4)] = (uint32_t)o[k];
+        for (int k = 0; k < MK; ++k) sd[k] = (uint32_t)o[k];
     }
     __syncthreads();
     uint32_t v[KPT];
-    const uint32_t* sr = st + (tid + (tid >> 4));
+    const uint32_t* sr = st + (tid + (tid >> 5));
 #pragma unroll
-    for (int q = 0; q < KPT; ++q) v[q] = sr[q * (THREADS + THREADS / 16)];
+    for (int q = 0; q < KPT; ++q) v[q] = sr[q * (THREADS + THREADS / 32)];
     // raw buffer stores: the descriptor's byte bound (cnt keys) drops the
     // stores past the tile end, so the rows need no per-lane guard
     const __amdgpu_buffer_rsrc_t ro =
@@ -687,10 +688,10 @@ __global__ __launch_bounds__(THREADS) void k_merge4(const uint32_t* __restrict__
     const int l0 = (int)((2 * G - 1 - (ostart % G)) % G);     // first chunk end in the tile
     if (tid < 32) {
         const int e = f0 + tid * G;
-        if (e < cnt) samp_first[(ostart + e) / G] = st[e + (e >> 4)];
+        if (e < cnt) samp_first[(ostart + e) / G] = st[e + (e >> 5)];
     } else if (tid < 64) {
         const int e = l0 + (tid - 32) * G;
-        if (e < cnt) samp_last[(ostart + e) / G] = st[e + (e >> 4)];
+        if (e < cnt) samp_last[(ostart + e) / G] = st[e + (e >> 5)];
     }
 }
 
