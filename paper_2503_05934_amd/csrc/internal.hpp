@@ -77,7 +77,7 @@ constexpr int kDefaultBlockTileMult = 2048;  // first-sweep run = 2048 x leaf si
 constexpr int kM4SamplesPerTile = 27;
 
 // Upper bound on the tile boundaries of any four-way pass (runs of at least
-// 4096 keys): chunks / 27 + 2 per group + slack.
+// 4096 keys): chunks / kM4SamplesPerTile + 2 per group + slack.
 inline size_t m4_max_bounds(int64_t n) {
     const size_t chunks = (size_t)((n + kSampleChunk - 1) / kSampleChunk);
     return chunks / kM4SamplesPerTile + (size_t)(n / 8192) + 8;

@@ -38,11 +38,16 @@ constexpr int kM4Sent = 32;  // outputs per thread of the merge levels = sentine
 // multiple of 32 at least KPT <= 32 past X), plus a dummy slot.
 __host__ __device__ constexpr int m4_buf_keys() { return kM4MaxTile + 4 * kM4Gap + 8; }
 // Level 1 needs ceil(nx/KPT) + ceil(ny/KPT) <= kM4MaxTile/KPT + 2 threads.
+// Rows of `threads` outputs that a tile can fill.
+__host__ __device__ constexpr int m4_rows(int threads) {
+    return (kM4MaxTile + threads - 1) / threads;
+}
 // LDS words: the padded buffer, or the staged output (a spare word every 32).
-__host__ __device__ constexpr int m4_lds_words(int threads, int kpt) {
-    return lds_words<uint32_t>(m4_buf_keys()) + 16 > threads * kpt + threads * kpt / 32 + 16
+__host__ __device__ constexpr int m4_lds_words(int threads) {
+    return lds_words<uint32_t>(m4_buf_keys()) + 16 >
+                   m4_rows(threads) * threads + m4_rows(threads) * threads / 32 + 16
                ? lds_words<uint32_t>(m4_buf_keys()) + 16
-               : threads * kpt + threads * kpt / 32 + 16;
+               : m4_rows(threads) * threads + m4_rows(threads) * threads / 32 + 16;
 }
 
 // Division by a launch-invariant divisor with a multiply-high and shifts
@@ -521,7 +526,7 @@ __global__ __launch_bounds__(THREADS) void k_merge4(const uint32_t* __restrict__
     constexpr int kBuf = m4_buf_keys();
     constexpr uint32_t kDummy = kBuf - 1;
     // static LDS: its base is a compile-time constant the address math folds
-    __shared__ __align__(16) uint32_t lds[m4_lds_words(THREADS, KPT)];
+    __shared__ __align__(16) uint32_t lds[m4_lds_words(THREADS)];
     unsigned char* smem = reinterpret_cast<unsigned char*>(lds);
     Key* b = reinterpret_cast<Key*>(lds);
 
@@ -577,21 +582,61 @@ __global__ __launch_bounds__(THREADS) void k_merge4(const uint32_t* __restrict__
 #pragma unroll
             for (int q = 0; q < KPT; ++q) *reinterpret_cast<Key*>(dp + 264 * q) = rk[q];
         } else if (X0 + 64 * KPT <= cnt && r1 == r0 + 1) {
-            // one boundary P (chunk offset) inside: slice r0 before it, r1 from it
-            const int P = (r1 == 1 ? p1 : r1 == 2 ? p2 : p3) - X0;
+            // one boundary P (chunk offset) inside: slice r0 before it, r1 from
+            // it.  Windows of 64 keys wholly on one side read one scalar base
+            // at constant offsets; only window P / 64 picks per lane.
+            const int P = __builtin_amdgcn_readfirstlane((r1 == 1 ? p1 : r1 == 2 ? p2 : p3) - X0);
+            const int qb = P >> 6;
             const int64_t sa = r0 == 0 ? sh0 : r0 == 1 ? sh1 : sh2;
             const int64_t sb = r1 == 1 ? sh1 : r1 == 2 ? sh2 : sh3;
-            const uint32_t S0 = (uint32_t)(X0 + sa), S1 = (uint32_t)(X0 + sb);  // < 4L < 2^32
-            const uint32_t G0 = (uint32_t)(X0 + r0 * kM4Gap), G1 = G0 + kM4Gap;
+            const char* spa = reinterpret_cast<const char*>(gin + X0 + sa) + lane4;
+            const char* spb = reinterpret_cast<const char*>(gin + X0 + sb) + lane4;
+#pragma unroll
+            for (int q = 0; q < KPT; ++q) {
+                if (q < qb) {
+                    rk[q] = *reinterpret_cast<const Key*>(spa + 256 * q);
+                } else if (q > qb) {
+                    rk[q] = *reinterpret_cast<const Key*>(spb + 256 * q);
+                } else {
+                    const int e = 64 * q + (int)lane;
+                    rk[q] = *reinterpret_cast<const Key*>((e >= P ? spb : spa) + 256 * q);
+                }
+            }
+            const uint32_t ga = (uint32_t)(X0 + r0 * kM4Gap);  // multiples of 64
+            const uint32_t gb2 = ga + kM4Gap;
+            unsigned char* dpa = smem + plane + 4u * (ga + (ga >> 5));
+            unsigned char* dpb = smem + plane + 4u * (gb2 + (gb2 >> 5));
 #pragma unroll
             for (int q = 0; q < KPT; ++q) {
                 const int e = 64 * q + (int)lane;
-                rk[q] = (Key)gin[(uint32_t)e + (e >= P ? S1 : S0)];
+                unsigned char* dp = q < qb ? dpa : q > qb ? dpb : (e >= P ? dpb : dpa);
+                *reinterpret_cast<Key*>(dp + 264 * q) = rk[q];
+            }
+        } else if (X0 < cnt && r0 == slice_of(cnt - 1)) {
+            // the tile's last chunk, inside one slice: full windows read one
+            // scalar base; the window holding the tile end checks each lane
+            const int E = __builtin_amdgcn_readfirstlane(cnt - X0);  // 1 .. 64 KPT - 1
+            const int qe = E >> 6;
+            const int64_t sh = r0 == 0 ? sh0 : r0 == 1 ? sh1 : r0 == 2 ? sh2 : sh3;
+            const char* sp = reinterpret_cast<const char*>(gin + X0 + sh) + lane4;
+            const uint32_t base = (uint32_t)(X0 + r0 * kM4Gap);  // a multiple of 64
+            unsigned char* dp = smem + plane + 4u * (base + (base >> 5));
+#pragma unroll
+            for (int q = 0; q < KPT; ++q) {
+                if (q < qe) {
+                    rk[q] = *reinterpret_cast<const Key*>(sp + 256 * q);
+                } else if (q == qe) {
+                    const int e = min(64 * q + (int)lane, E - 1);
+                    rk[q] = *reinterpret_cast<const Key*>(sp - lane4 + 4 * e);
+                }
             }
 #pragma unroll
             for (int q = 0; q < KPT; ++q) {
-                const int e = 64 * q + (int)lane;
-                *reinterpret_cast<Key*>(smem + m4_off((uint32_t)e + (e >= P ? G1 : G0))) = rk[q];
+                if (q < qe) {
+                    *reinterpret_cast<Key*>(dp + 264 * q) = rk[q];
+                } else if (q == qe && 64 * q + (int)lane < E) {
+                    *reinterpret_cast<Key*>(dp + 264 * q) = rk[q];
+                }
             }
         } else if (X0 < cnt) {
             // group offsets of slice starts fit 32 bits: a group spans 4L < 2^32 keys
@@ -671,16 +716,17 @@ __global__ __launch_bounds__(THREADS) void k_merge4(const uint32_t* __restrict__
         for (int k = 0; k < MK; ++k) sd[k] = (uint32_t)o[k];
     }
     __syncthreads();
-    uint32_t v[KPT];
+    constexpr int QR = m4_rows(THREADS);
+    uint32_t v[QR];
     const uint32_t* sr = st + (tid + (tid >> 5));
 #pragma unroll
-    for (int q = 0; q < KPT; ++q) v[q] = sr[q * (THREADS + THREADS / 32)];
+    for (int q = 0; q < QR; ++q) v[q] = sr[q * (THREADS + THREADS / 32)];
     // raw buffer stores: the descriptor's byte bound (cnt keys) drops the
     // stores past the tile end, so the rows need no per-lane guard
     const __amdgpu_buffer_rsrc_t ro =
         __builtin_amdgcn_make_buffer_rsrc(out + ostart, 0, cnt * 4, kRawBufferWord3);
 #pragma unroll
-    for (int q = 0; q < KPT; ++q)
+    for (int q = 0; q < QR; ++q)
         __builtin_amdgcn_raw_buffer_store_b32(v[q], ro, (tid + q * THREADS) * 4, 0, 0);
     // chunk samples of the output for the next pass
     constexpr int G = kSampleChunk;
