@@ -207,6 +207,21 @@ template <typename T>
 __host__ __device__ constexpr int lds_words(int n) {
     return sizeof(T) == 8 ? n + (n >> 4) + 1 : n + (n >> 5) + 1;
 }
+// Byte offset of padded slot i, sizeof(T) * lds_idx<T>(i), in one shift and
+// one shift-add.
+template <typename T>
+__device__ __forceinline__ uint32_t lds_off(uint32_t i) {
+    uint32_t r;
+    if constexpr (sizeof(T) == 8)
+        asm("v_add_lshl_u32 %0, %1, %2, 3" : "=v"(r) : "v"(i), "v"(i >> 4));
+    else
+        asm("v_add_lshl_u32 %0, %1, %2, 2" : "=v"(r) : "v"(i), "v"(i >> 5));
+    return r;
+}
+template <typename T>
+__device__ __forceinline__ T lds_load(const T* s, uint32_t i) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const unsigned char*>(s) + lds_off<T>(i));
+}
 
 // Merge path (Green, McColl, Bader 2012): number of elements of A among the
 // first d outputs of the stable merge of A (la keys) and B (lb keys), both
@@ -216,9 +231,10 @@ __device__ __forceinline__ int corank_lds(const T* s, int a0, int la, int b0, in
                                           Less less) {
     int lo = d > lb ? d - lb : 0;
     int hi = d < la ? d : la;
+    const int kb = b0 + d - 1;
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
-        if (!less(s[lds_idx<T>(b0 + d - 1 - mid)], s[lds_idx<T>(a0 + mid)]))
+        if (!less(lds_load(s, (uint32_t)(kb - mid)), lds_load(s, (uint32_t)(a0 + mid))))
             lo = mid + 1;
         else
             hi = mid;
@@ -273,21 +289,43 @@ __device__ __forceinline__ constexpr T key_max() {
 // least N copies of key_max(): no bounds checks are needed, because a used-up
 // run offers the maximum, which is taken only when the other run's key is the
 // maximum too (the same value; composite keys never reach it).  pa, pb:
-// (unpadded) positions of the next key of each run.
+// (unpadded) positions of the next key of each run.  The state is the head x
+// of the run that gave the last output (its next key at pc) and the head y of
+// the other run (next key at po).  Equal keys may come from either run, which
+// yields the values of the stable merge: all a key-only merge keeps
+// (composite keys are unique).
 template <typename T, int N>
 __device__ __forceinline__ void serial_merge_closed(const T* s, int pa, int pb, T (&out)[N]) {
-    const int sum0 = pa + pb;  // grows by one per output
-    T a = s[lds_idx<T>(pa)];
-    T b = s[lds_idx<T>(pb)];
+    if constexpr (sizeof(T) == 4) {
+        T x = lds_load(s, (uint32_t)pa);
+        T y = lds_load(s, (uint32_t)pb);
+        uint32_t pc = (uint32_t)pa + 1, po = (uint32_t)pb + 1;
 #pragma unroll
-    for (int k = 0; k < N; ++k) {
-        const bool take_a = !(b < a);
-        out[k] = take_a ? a : b;
-        pa += take_a ? 1 : 0;
-        const int p = take_a ? pa : sum0 + k + 1 - pa;
-        const T x = s[lds_idx<T>(p)];
-        a = take_a ? x : a;
-        b = take_a ? b : x;
+        for (int k = 0; k < N; ++k) {
+            const bool keep = !(y < x);
+            out[k] = keep ? x : y;
+            const T hi = keep ? y : x;
+            const uint32_t p = keep ? pc : po;
+            po = keep ? po : pc;
+            pc = p + 1;
+            x = lds_load(s, p);
+            y = hi;
+        }
+    } else {
+        // 64-bit composites: track both runs' positions (fewer live registers)
+        const int sum0 = pa + pb;  // grows by one per output
+        T a = s[lds_idx<T>(pa)];
+        T b = s[lds_idx<T>(pb)];
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            const bool take_a = !(b < a);
+            out[k] = take_a ? a : b;
+            pa += take_a ? 1 : 0;
+            const int p = take_a ? pa : sum0 + k + 1 - pa;
+            const T x = s[lds_idx<T>(p)];
+            a = take_a ? x : a;
+            b = take_a ? b : x;
+        }
     }
 }
 

@@ -11,10 +11,13 @@ namespace msn {
 
 // ----------------------------------------------------------- first sweep ---
 template <int DT, int K, bool STABLE, int VM, int SHAPE>
-__global__ __launch_bounds__((TileTraits<DT, K, STABLE, SHAPE>::kThreads)) void k_block_sort(
+__global__ __launch_bounds__((TileTraits<DT, K, STABLE, SHAPE>::kThreads),
+                             (TileTraits<DT, K, STABLE, SHAPE>::kWavesPerSimd)) void k_block_sort(
     const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, int64_t n,
     int vec, uint32_t* samp_first, uint32_t* samp_last) {
-    extern __shared__ __align__(16) unsigned char smem[];
+    // static LDS (gfx950 allows up to 160 KiB): its base is a compile-time
+    // constant that the padded-slot address math folds away
+    __shared__ __align__(16) unsigned char smem[TileTraits<DT, K, STABLE, SHAPE>::kLdsBytes];
     constexpr int kTile = TileTraits<DT, K, STABLE, SHAPE>::kTile;
     const int64_t base = (int64_t)blockIdx.x * kTile;
     const int nv = (int)((n - base) < kTile ? (n - base) : kTile);
@@ -208,12 +211,11 @@ int launch_block_sort(const SortArgs& a, uint32_t* kdst, uint32_t* vdst, int vec
                       const Samples& sm) {
     using Tr = TileTraits<DT, K, STABLE, SHAPE>;
     auto kern = &k_block_sort<DT, K, STABLE, VM, SHAPE>;
-    if (int rc = ensure_lds(kern, Tr::kLdsBytes)) return rc;
     const int64_t blocks = (a.n + Tr::kTile - 1) / Tr::kTile;
     {
         LaunchTimer timer("block_sort", a.n, a.stream);
-        hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(Tr::kThreads), Tr::kLdsBytes,
-                           a.stream, a.kin, a.vin, kdst, vdst, a.n, vec, sm.first, sm.last);
+        hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(Tr::kThreads), 0, a.stream, a.kin,
+                           a.vin, kdst, vdst, a.n, vec, sm.first, sm.last);
     }
     return (int)hipGetLastError();
 }
