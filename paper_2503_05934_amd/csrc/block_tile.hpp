@@ -22,8 +22,14 @@ struct TileTraits {
     static constexpr int kThreads = SHAPE == 0 ? kBlockThreads : 2 * kBlockThreads;
     static constexpr int kKPL = SHAPE == 2 ? 2 * keys_per_lane<K>() : keys_per_lane<K>();
     static constexpr int kTile = kKPL * kThreads;
+    // keys-only tiles of 16 keys per lane can merge in LDS at 32 outputs per
+    // thread (block_sort_regs2); LDS is sized for either layout
+    static constexpr bool kWideOk = !STABLE && kKPL == 16;
     static constexpr size_t kLdsBytes =
-        (size_t)block_lds_words<T, kKPL>(kTile) * sizeof(T);
+        (size_t)(kWideOk && block_lds_words2<T, kKPL, 2 * kKPL>(kTile) >
+                                block_lds_words<T, kKPL>(kTile)
+                     ? block_lds_words2<T, kKPL, 2 * kKPL>(kTile)
+                     : block_lds_words<T, kKPL>(kTile)) * sizeof(T);
     static_assert(!STABLE || kLdsBytes >= (size_t)2 * kTile * 4, "staging must fit");
     // waves per SIMD that the LDS footprint allows (160 KiB per compute unit,
     // 4 SIMDs): the register budget the compiler is held to
@@ -55,7 +61,9 @@ __device__ __forceinline__ void write_samples(const Samples& samp, int first, in
         samp.last[(p + N - 1) / kSampleChunk] = x[N - 1];
 }
 
-template <int DT, int K, bool STABLE, int VM, int SHAPE = 0>
+// WIDE (keys-only tiles of 16 keys per lane): LDS merge levels at 32 outputs
+// per thread; fewer co-rank searches for more live registers.
+template <int DT, int K, bool STABLE, int VM, int SHAPE = 0, bool WIDE = false>
 __device__ __forceinline__ void block_sort_tile(const uint32_t* kin, const uint32_t* vin,
                                                 uint32_t* kout, uint32_t* vout, int nv,
                                                 uint32_t val_base, void* smem, bool vec,
@@ -95,9 +103,29 @@ __device__ __forceinline__ void block_sort_tile(const uint32_t* kin, const uint3
     }
 
     const int span = span_for(nv, kWave * KPL);
-    block_sort_regs<T, K, KPL>(v, s, span);
-
-    if constexpr (!STABLE) {
+    if constexpr (WIDE && Tr::kWideOk) {
+        constexpr int MK = 2 * KPL;
+        T o[MK];
+        block_sort_regs2<T, K, KPL, MK>(v, o, s, span);
+        const int first2 = tid * MK;
+        if (first2 < span) {
+            uint32_t y[MK];
+#pragma unroll
+            for (int j = 0; j < MK; ++j) y[j] = unord_key<DT>(o[j]);
+            write_samples(samp, first2, nv, y);
+            if (vec && first2 + MK <= nv) {
+#pragma unroll
+                for (int q = 0; q < MK / 4; ++q)
+                    *reinterpret_cast<uint4*>(kout + first2 + 4 * q) =
+                        make_uint4(y[4 * q], y[4 * q + 1], y[4 * q + 2], y[4 * q + 3]);
+            } else {
+#pragma unroll
+                for (int j = 0; j < MK; ++j)
+                    if (first2 + j < nv) kout[first2 + j] = y[j];
+            }
+        }
+    } else if constexpr (!STABLE) {
+        block_sort_regs<T, K, KPL>(v, s, span);
 #pragma unroll
         for (int j = 0; j < KPL; ++j) x[j] = unord_key<DT>(v[j]);
         write_samples(samp, first, nv, x);
@@ -112,6 +140,7 @@ __device__ __forceinline__ void block_sort_tile(const uint32_t* kin, const uint3
                 if (first + j < nv) kout[first + j] = x[j];
         }
     } else {
+        block_sort_regs<T, K, KPL>(v, s, span);
         // Stage what must be gathered by position (float bits, payload).
         uint32_t* sbits = reinterpret_cast<uint32_t*>(smem);
         uint32_t* svals = sbits + Tr::kTile;

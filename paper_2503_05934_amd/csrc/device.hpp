@@ -426,6 +426,74 @@ __device__ __forceinline__ void block_sort_regs(T (&v)[KPL], T* s, int span) {
     }
 }
 
+// LDS words block_sort_regs2 needs: as block_lds_words with MK sentinels per run.
+template <typename T, int KPL, int MK>
+__host__ __device__ constexpr int block_lds_words2(int n) {
+    return lds_words<T>(n + (n / (kWave * KPL)) * MK + MK);
+}
+
+// As block_sort_regs, with the LDS merge levels run by the first half of the
+// threads at MK = 2 KPL outputs each (one co-rank search per MK outputs): on
+// return thread t < threads/2 holds outputs t*MK .. t*MK+MK-1 of the sorted
+// span in o[].  s is LDS of block_lds_words2<T, KPL, MK>(tile keys) words.
+template <typename T, int K, int KPL, int MK>
+__device__ __forceinline__ void block_sort_regs2(T (&v)[KPL], T (&o)[MK], T* s, int span) {
+    static_assert(MK == 2 * KPL, "two lanes' keys per merger");
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    int L = kWave * KPL;  // wavefront runs
+    if (tid * KPL < span) {
+        lane_sort<T, K, KPL>(v);
+        wave_merge<T, KPL>(v, lane);
+        // run r occupies [r*(L+MK), r*(L+MK)+L), then MK sentinels
+        const int e = tid * KPL;
+        const int run = e / L;
+        const int pos = e + run * MK;
+#pragma unroll
+        for (int j = 0; j < KPL; ++j) s[lds_idx<T>(pos + j)] = v[j];
+        if ((e % L) == L - KPL) {
+#pragma unroll
+            for (int j = 0; j < MK; ++j) s[lds_idx<T>(pos + KPL + j)] = key_max<T>();
+        }
+    }
+    __syncthreads();
+    const int e = tid * MK;
+    const bool merger = e < span;
+    if (L >= span) {  // one wavefront run: regroup it, MK keys per thread
+        if (merger) {
+#pragma unroll
+            for (int j = 0; j < MK; ++j) o[j] = lds_load(s, (uint32_t)(e + j));
+        }
+        __syncthreads();
+        return;
+    }
+    for (;;) {
+        if (merger) {
+            const int run = e / L;
+            const int ra = run & ~1;
+            const int a0 = ra * (L + MK);
+            const int b0 = a0 + L + MK;
+            const int d = e - ra * L;
+            const int i = corank_lds(s, a0, L, b0, L, d, PlainLess{});
+            serial_merge_closed<T, MK>(s, a0 + i, b0 + d - i, o);
+        }
+        L <<= 1;
+        __syncthreads();
+        if (L >= span) break;
+        if (merger) {
+            const int run = e / L;
+            const int pos = e + run * MK;  // a multiple of MK: one padded block
+#pragma unroll
+            for (int j = 0; j < MK; ++j) s[lds_idx<T>(pos + j)] = o[j];
+            if ((e % L) == L - MK) {
+#pragma unroll
+                for (int j = 0; j < MK; ++j) s[lds_idx<T>(pos + MK + j)] = key_max<T>();
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // Smallest power of two >= max(n, lo).
 __device__ __forceinline__ int span_for(int n, int lo) {
     int s = lo;

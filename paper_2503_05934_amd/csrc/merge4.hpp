@@ -451,11 +451,18 @@ __global__ __launch_bounds__(256) void k_m4_bounds_large(const uint32_t* __restr
     m4_refine<DT>(in, bnd, g4, cuts, ncut);
 }
 
-// Byte offset of padded LDS slot i (one spare word every 32, as lds_idx):
-// 4 * (i + i / 32) in one shift and one shift-add.
+// LDS slots of the merge kernel: one spare word every 2^kM4PadShift, so that
+// the merge-path threads (whose runs start about 16 keys apart) begin on
+// distinct banks.
+constexpr int kM4PadShift = 5;
+__host__ __device__ constexpr uint32_t m4_idx(uint32_t i) { return i + (i >> kM4PadShift); }
+constexpr int kWin = 4 * (int)m4_idx(64);  // bytes between windows of 64 keys (64-aligned)
+static_assert(kM4PadShift == 5 || kM4PadShift == 6, "padding: every 32 or 64 words");
+
+// Byte offset of padded slot i, 4 * m4_idx(i), in one shift and one shift-add.
 __device__ __forceinline__ uint32_t m4_off(uint32_t i) {
     uint32_t r;
-    asm("v_add_lshl_u32 %0, %1, %2, 2" : "=v"(r) : "v"(i), "v"(i >> 5));
+    asm("v_add_lshl_u32 %0, %1, %2, 2" : "=v"(r) : "v"(i), "v"(i >> kM4PadShift));
     return r;
 }
 
@@ -553,7 +560,7 @@ __global__ __launch_bounds__(THREADS) void k_merge4(const uint32_t* __restrict__
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const uint32_t lane = (uint32_t)tid & 63u;
     const uint32_t lane4 = lane * 4u;
-    const uint32_t plane = 4u * (lane + (lane >> 5));  // padded byte offset in a 64-block
+    const uint32_t plane = 4u * m4_idx(lane);  // padded byte offset in a 64-key window
 
     // ---- load the four slices (all loads issued before the first LDS write).
     // Wave w loads tile keys [w * 64 KPT, (w + 1) * 64 KPT).  A chunk inside
@@ -578,9 +585,9 @@ __global__ __launch_bounds__(THREADS) void k_merge4(const uint32_t* __restrict__
 #pragma unroll
             for (int q = 0; q < KPT; ++q) rk[q] = *reinterpret_cast<const Key*>(sp + 256 * q);
             const uint32_t base = (uint32_t)(X0 + r0 * kM4Gap);  // a multiple of 64
-            unsigned char* dp = smem + plane + 4u * (base + (base >> 5));
+            unsigned char* dp = smem + plane + 4u * m4_idx(base);
 #pragma unroll
-            for (int q = 0; q < KPT; ++q) *reinterpret_cast<Key*>(dp + 264 * q) = rk[q];
+            for (int q = 0; q < KPT; ++q) *reinterpret_cast<Key*>(dp + kWin * q) = rk[q];
         } else if (X0 + 64 * KPT <= cnt && r1 == r0 + 1) {
             // one boundary P (chunk offset) inside: slice r0 before it, r1 from
             // it.  Windows of 64 keys wholly on one side read one scalar base
@@ -604,13 +611,13 @@ __global__ __launch_bounds__(THREADS) void k_merge4(const uint32_t* __restrict__
             }
             const uint32_t ga = (uint32_t)(X0 + r0 * kM4Gap);  // multiples of 64
             const uint32_t gb2 = ga + kM4Gap;
-            unsigned char* dpa = smem + plane + 4u * (ga + (ga >> 5));
-            unsigned char* dpb = smem + plane + 4u * (gb2 + (gb2 >> 5));
+            unsigned char* dpa = smem + plane + 4u * m4_idx(ga);
+            unsigned char* dpb = smem + plane + 4u * m4_idx(gb2);
 #pragma unroll
             for (int q = 0; q < KPT; ++q) {
                 const int e = 64 * q + (int)lane;
                 unsigned char* dp = q < qb ? dpa : q > qb ? dpb : (e >= P ? dpb : dpa);
-                *reinterpret_cast<Key*>(dp + 264 * q) = rk[q];
+                *reinterpret_cast<Key*>(dp + kWin * q) = rk[q];
             }
         } else if (X0 < cnt && r0 == slice_of(cnt - 1)) {
             // the tile's last chunk, inside one slice: full windows read one
@@ -620,7 +627,7 @@ __global__ __launch_bounds__(THREADS) void k_merge4(const uint32_t* __restrict__
             const int64_t sh = r0 == 0 ? sh0 : r0 == 1 ? sh1 : r0 == 2 ? sh2 : sh3;
             const char* sp = reinterpret_cast<const char*>(gin + X0 + sh) + lane4;
             const uint32_t base = (uint32_t)(X0 + r0 * kM4Gap);  // a multiple of 64
-            unsigned char* dp = smem + plane + 4u * (base + (base >> 5));
+            unsigned char* dp = smem + plane + 4u * m4_idx(base);
 #pragma unroll
             for (int q = 0; q < KPT; ++q) {
                 if (q < qe) {
@@ -633,9 +640,9 @@ __global__ __launch_bounds__(THREADS) void k_merge4(const uint32_t* __restrict__
 #pragma unroll
             for (int q = 0; q < KPT; ++q) {
                 if (q < qe) {
-                    *reinterpret_cast<Key*>(dp + 264 * q) = rk[q];
+                    *reinterpret_cast<Key*>(dp + kWin * q) = rk[q];
                 } else if (q == qe && 64 * q + (int)lane < E) {
-                    *reinterpret_cast<Key*>(dp + 264 * q) = rk[q];
+                    *reinterpret_cast<Key*>(dp + kWin * q) = rk[q];
                 }
             }
         } else if (X0 < cnt) {
@@ -660,7 +667,7 @@ __global__ __launch_bounds__(THREADS) void k_merge4(const uint32_t* __restrict__
         // take up to kM4Sent outputs per thread)
         if (tid < kM4Sent) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) b[lds_idx<Key>(pst[r] + r * kM4Gap + c[r] + tid)] = kMax;
+            for (int r = 0; r < 4; ++r) b[m4_idx(pst[r] + r * kM4Gap + c[r] + tid)] = kMax;
         }
     }
     __syncthreads();
@@ -688,13 +695,13 @@ __global__ __launch_bounds__(THREADS) void k_merge4(const uint32_t* __restrict__
         __syncthreads();
         // outputs past the end of X (Y) are key maxima: the sentinels
         if (active) {
-            Key* dst = b + (base2 + (base2 >> 5));
+            Key* dst = b + m4_idx(base2);
 #pragma unroll
             for (int k = 0; k < MK; ++k) dst[k] = o[k];
         }
         if (tid < MK) {
-            b[lds_idx<Key>(nx + tid)] = kMax;
-            b[lds_idx<Key>(ybase + ny + tid)] = kMax;
+            b[m4_idx(nx + tid)] = kMax;
+            b[m4_idx(ybase + ny + tid)] = kMax;
         }
     }
     __syncthreads();
