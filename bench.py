@@ -43,12 +43,20 @@ def reference_schedule_bytes(n: int, width: int) -> int:
     return 2 * width * (1 + passes)
 
 
-def load_traffic(kernel_file: str):
-    """Per-launch HBM bytes of the keys-only merge kernel from the committed
-    rocprofv3 PMC summary, if it was taken on the current kernel source
-    (merge_keys.hpp + device.hpp); None otherwise."""
+def kernel_source_hash(kernel_header: str) -> str:
+    """First 16 hex digits of sha256(kernel header + device.hpp + internal.hpp)."""
     import hashlib
 
+    csrc = os.path.join(ROOT, "paper_2503_05934_amd", "csrc")
+    data = b"".join(open(os.path.join(csrc, f), "rb").read()
+                    for f in (kernel_header, "device.hpp", "internal.hpp"))
+    return hashlib.sha256(data).hexdigest()[:16]
+
+
+def load_traffic(kernel_file: str, kernel_header: str):
+    """Per-launch HBM bytes of a merge kernel from the committed rocprofv3 PMC
+    summary, if it was taken on the current kernel source (the kernel's header
+    + device.hpp + internal.hpp); None otherwise."""
     path = os.path.join(ROOT, "profiles", kernel_file)
     if not os.path.exists(path):
         return None
@@ -57,10 +65,7 @@ def load_traffic(kernel_file: str):
         if ":" in line and line.startswith("- "):
             k, v = line[2:].split(":", 1)
             fields[k.strip()] = v.strip()
-    src = os.path.join(ROOT, "paper_2503_05934_amd", "csrc", "merge_keys.hpp")
-    dev = os.path.join(ROOT, "paper_2503_05934_amd", "csrc", "device.hpp")
-    h = hashlib.sha256(open(src, "rb").read() + open(dev, "rb").read()).hexdigest()[:16]
-    if fields.get("source_sha256_16") != h:
+    if fields.get("source_sha256_16") != kernel_source_hash(kernel_header):
         return None
     try:
         return float(fields["hbm_bytes_per_launch"])
@@ -188,8 +193,9 @@ def bench_keys(args):
                 avg_s = m["avg_ms"] / 1e3
                 bytes_per_launch = 8.0 * n
                 achieved = bytes_per_launch / avg_s / 1e9
-                traffic = load_traffic("k_merge_keys_2p28_u32_traffic.md") \
-                    if mkind == "merge" else None
+                traffic = (load_traffic("k_merge4_2p28_u32_traffic.md", "merge4.hpp")
+                           if mkind == "merge4" else
+                           load_traffic("k_merge_keys_2p28_u32_traffic.md", "merge_keys.hpp"))
                 roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS,
                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
                         "kernel": ("k_merge4 (four-way merge pass)" if mkind == "merge4"
