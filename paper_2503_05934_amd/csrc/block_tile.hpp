@@ -32,10 +32,10 @@ struct TileTraits {
                      : block_lds_words<T, kKPL>(kTile)) * sizeof(T);
     static_assert(!STABLE || kLdsBytes >= (size_t)2 * kTile * 4, "staging must fit");
     // waves per SIMD that the LDS footprint allows (160 KiB per compute unit,
-    // 4 SIMDs): the register budget the compiler is held to
-    static constexpr int kWavesPerSimd =
-        (int)((163840 / kLdsBytes) * (kThreads / kWave) / 4) > 0
-            ? (int)((163840 / kLdsBytes) * (kThreads / kWave) / 4) : 1;
+    // 4 SIMDs, at most 8 waves per SIMD): the register budget the compiler is
+    // held to
+    static constexpr int kLdsWaves = (int)((163840 / kLdsBytes) * (kThreads / kWave) / 4);
+    static constexpr int kWavesPerSimd = kLdsWaves < 1 ? 1 : kLdsWaves > 8 ? 8 : kLdsWaves;
 };
 
 // Sorts kin[0..nv) into kout[0..nv) (nv <= 2K*512).  STABLE sorts

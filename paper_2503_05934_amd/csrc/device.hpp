@@ -57,6 +57,28 @@ __device__ __forceinline__ uint32_t kmax(uint32_t a, uint32_t b) { return a < b 
 __device__ __forceinline__ uint64_t kmin(uint64_t a, uint64_t b) { return a < b ? a : b; }
 __device__ __forceinline__ uint64_t kmax(uint64_t a, uint64_t b) { return a < b ? b : a; }
 
+// Half of a compare-exchange between lanes: the lane whose all-ones `upper`
+// mask is set keeps the larger of (mine, theirs), the other the smaller.  For
+// 32-bit keys that is the median of (mine, theirs, upper): 0 never exceeds
+// the smaller and all-ones never falls below the larger, so one v_med3_u32
+// replaces a min, a max and a select.
+__device__ __forceinline__ uint32_t keep(uint32_t mine, uint32_t theirs, uint32_t upper) {
+    return kmax(kmin(mine, theirs), kmin(kmax(mine, theirs), upper));
+}
+__device__ __forceinline__ uint64_t keep(uint64_t mine, uint64_t theirs, uint32_t upper) {
+    // one 64-bit compare: the lower lane keeps mine when it is the smaller,
+    // the upper lane when it is not
+    return ((mine < theirs) != (upper != 0u)) ? mine : theirs;
+}
+
+// floor(log2(x)) for x >= 1.
+__host__ __device__ constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x >> 1); }
+
+// All-ones when bit `bit` of lane is set, else 0.
+__device__ __forceinline__ uint32_t lane_bit_mask(int lane, int bit) {
+    return 0u - (((uint32_t)lane >> bit) & 1u);
+}
+
 template <typename T>
 __device__ __forceinline__ void cx(T& a, T& b) {
     const T lo = kmin(a, b);
@@ -150,15 +172,15 @@ __device__ __forceinline__ void wave_merge_level(T (&v)[K], int lane) {
         T o[K];
 #pragma unroll
         for (int j = 0; j < K; ++j) o[j] = xor_lane<2 * G - 1>(v[K - 1 - j]);
-        const bool upper = (lane & G) != 0;
+        const uint32_t upper = lane_bit_mask(lane, ilog2(G));
 #pragma unroll
-        for (int j = 0; j < K; ++j) v[j] = upper ? kmax(v[j], o[j]) : kmin(v[j], o[j]);
+        for (int j = 0; j < K; ++j) v[j] = keep(v[j], o[j], upper);
     }
     if constexpr (G >= 2) {
         // cross-lane half-cleaners, lane distance G/2 ... 1
 #pragma unroll
         for (int m = G / 2; m >= 1; m >>= 1) {
-            const bool upper = (lane & m) != 0;
+            const uint32_t upper = lane_bit_mask(lane, ilog2(m));
 #pragma unroll
             for (int j = 0; j < K; ++j) {
                 T o;
@@ -169,7 +191,7 @@ __device__ __forceinline__ void wave_merge_level(T (&v)[K], int lane) {
                     case 8: o = xor_lane<8>(v[j]); break;
                     default: o = xor_lane<16>(v[j]); break;
                 }
-                v[j] = upper ? kmax(v[j], o) : kmin(v[j], o);
+                v[j] = keep(v[j], o, upper);
             }
         }
     }

@@ -219,7 +219,7 @@ __device__ __forceinline__ void m4_lds_count3(const uint32_t* (&s)[3], const int
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
             const int q = p[j] + b;
-            p[j] = (q <= m[j]) & ((uint64_t)x[j] < thr[j]) ? q : p[j];
+            p[j] = ((q <= m[j]) & ((uint64_t)x[j] < thr[j])) ? q : p[j];
         }
     }
 #pragma unroll
