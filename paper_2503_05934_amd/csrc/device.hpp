@@ -51,6 +51,24 @@ __device__ __forceinline__ uint32_t unord_key(uint32_t o) {
     return o;
 }
 
+// ------------------------------------------------------ streaming access ---
+// Global loads and stores with the nontemporal hint, for the binary merge of
+// key-value pairs: each 64-lane load row and 16-byte-per-lane store row there
+// covers whole cache lines, every key and value is read once and written once
+// per pass, and the hint raises its sustained rate (about 4% per pass on
+// 2^28 pairs).  Sweeps whose lanes each read or write a strided 64-byte
+// stretch in several instructions lose by it: the line leaves the cache
+// between them.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint32_t ld1_stream(const uint32_t* p) {
+    return __builtin_nontemporal_load(p);
+}
+__device__ __forceinline__ void st4_stream(uint32_t* p, uint32_t a, uint32_t b, uint32_t c,
+                                           uint32_t d) {
+    const u32x4 w = {a, b, c, d};
+    __builtin_nontemporal_store(w, reinterpret_cast<u32x4*>(p));
+}
+
 // ------------------------------------------------------ compare-exchange ---
 __device__ __forceinline__ uint32_t kmin(uint32_t a, uint32_t b) { return a < b ? a : b; }
 __device__ __forceinline__ uint32_t kmax(uint32_t a, uint32_t b) { return a < b ? b : a; }

@@ -127,8 +127,8 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge(const uint32_t* __restr
         for (int q = 0; q < KPT; ++q) {
             const int x = min((int)threadIdx.x + q * kMergeThreads, cnt - 1);
             const int64_t src = x < na ? base + i0 + x : base + la + j0 + (x - na);
-            rk[q] = kin[src];
-            if constexpr (VALS) rv[q] = vin[src];
+            rk[q] = ld1_stream(kin + src);
+            if constexpr (VALS) rv[q] = ld1_stream(vin + src);
         }
 #pragma unroll
         for (int q = 0; q < KPT; ++q) {
@@ -172,11 +172,9 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge(const uint32_t* __restr
         const int e = 4 * ((int)threadIdx.x + q * kMergeThreads);
         const int pe = e + (e >> 4);
         if (vec && e + 4 <= cnt) {
-            *reinterpret_cast<uint4*>(kout + g0 + e) =
-                make_uint4(stk[pe], stk[pe + 1], stk[pe + 2], stk[pe + 3]);
+            st4_stream(kout + g0 + e, stk[pe], stk[pe + 1], stk[pe + 2], stk[pe + 3]);
             if constexpr (VALS)
-                *reinterpret_cast<uint4*>(vout + g0 + e) =
-                    make_uint4(stv[pe], stv[pe + 1], stv[pe + 2], stv[pe + 3]);
+                st4_stream(vout + g0 + e, stv[pe], stv[pe + 1], stv[pe + 2], stv[pe + 3]);
         } else {
 #pragma unroll
             for (int k = 0; k < 4; ++k)
