@@ -88,8 +88,8 @@ extern "C" {
  *                   above 1024 x leaf size; other sorts accept the value and
  *                   keep 1024 x leaf size.
  *   merge_ways      fan-in of the global merge passes: 2 or 4 (default 4).
- *                   Four-way passes serve integer keys-only sorts; the
- *                   others always merge pairs of runs.
+ *                   Four-way passes serve integer keys, with or without
+ *                   values; float keys always merge pairs of runs.
  *   merge4_kpt      keys per thread of the four-way merge kernel: 16 (512
  *                   threads per tile) or 32 (256 threads); default 16.
  */

@@ -33,7 +33,7 @@ struct SortArgs {
     int vmode;
     int merge_tile;       // 2048, 4096 or 8192
     int block_tile;       // first-sweep run length: 1024K, 2048K or 4096K
-    int merge_ways;       // 2 or 4 (four-way passes: integer keys-only sorts)
+    int merge_ways;       // 2 or 4 (four-way passes: integer keys)
     int merge4_kpt;       // keys per thread of the four-way merge: 16 or 32
     void* ws;
     size_t ws_bytes;
@@ -88,15 +88,14 @@ inline size_t m4_max_bounds(int64_t n) {
 inline size_t m4_ws_bytes(int64_t n) { return align_up(m4_max_bounds(n) * 16, 256); }
 
 // Workspace of the flat sort: ping-pong keys (+ values), one merge-path split
-// per merge tile, the two chunk-sample arrays, and (keys-only) the four-way
-// pass buffers.
+// per merge tile, the two chunk-sample arrays, and the four-way passes'
+// boundary table.
 inline size_t sort_ws_bytes(int64_t n, bool vals) {
     const size_t nk = align_up((size_t)n * 4, 256);
     const size_t nv = vals ? nk : 0;
     const size_t tiles = (size_t)((n + kMinMergeTile - 1) / kMinMergeTile) + 1;
     const size_t chunks = (size_t)((n + kSampleChunk - 1) / kSampleChunk);
-    return nk + nv + align_up(tiles * 4, 256) + 2 * align_up(chunks * 4, 256) +
-           (vals ? 0 : m4_ws_bytes(n));
+    return nk + nv + align_up(tiles * 4, 256) + 2 * align_up(chunks * 4, 256) + m4_ws_bytes(n);
 }
 
 size_t seg_ws_bytes(int64_t n_total, int64_t num_segments, bool vals);

@@ -749,4 +749,190 @@ __global__ __launch_bounds__(THREADS) void k_merge4(const uint32_t* __restrict__
 }
 
 
+
+// ---------------------------------------------------------------- pairs ---
+// Four-way pass over key-value pairs (integer keys, stable).  The tiles and
+// their splits are those of the keys (the boundary kernels above, whose order
+// (key, run, position) is the stable order).  In LDS every key travels as the
+// 64-bit composite (order-mapped key, tile position): tile positions grow
+// with the run and with the position inside it, so plain composite order is
+// the stable order and the merge levels need no tie rule.  Values stay in
+// registers until the merge is done; then they are written to LDS by tile
+// position, gathered through the positions the composites carry, staged with
+// the keys and stored as rows.  MK = 16 outputs per thread of each level.
+constexpr int kM4pSent = 16;
+// Staged keys: every output a thread holds (up to MK - 1 past the tile end),
+// a spare word every 32; the staged values follow.
+constexpr int kM4pStage = kM4MaxTile + kM4pSent + (kM4MaxTile + kM4pSent) / 32 + 8;
+// LDS: the padded composite buffer (slices kM4Gap apart, or X and Y), or the
+// values by tile position, or the staged keys and values (read back as rows
+// of `threads` words, the last row partly past the tile).
+__host__ __device__ constexpr int m4p_lds_bytes(int threads) {
+    return 8 * lds_words<uint64_t>(kM4MaxTile + 4 * kM4Gap + 8) >
+                   4 * (kM4pStage + m4_rows(threads) * threads + m4_rows(threads) * threads / 32)
+               ? 8 * lds_words<uint64_t>(kM4MaxTile + 4 * kM4Gap + 8)
+               : 4 * (kM4pStage + m4_rows(threads) * threads + m4_rows(threads) * threads / 32);
+}
+
+template <int DT, int THREADS, int KPT>
+__global__ __launch_bounds__(THREADS) void k_merge4_pairs(
+    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, const int32_t* __restrict__ bnd,
+    M4Geom g4, uint32_t* __restrict__ samp_first, uint32_t* __restrict__ samp_last) {
+    static_assert(DT == kU32 || DT == kI32, "integer keys only");
+    static_assert(kM4MaxTile <= THREADS * KPT, "tile fits");
+    constexpr int MK = kM4pSent;
+    static_assert(kM4MaxTile / MK + 2 <= THREADS && kM4Gap >= MK, "merge shape");
+    constexpr uint64_t kMaxC = ~0ull;
+    __shared__ __align__(16) unsigned char smem[m4p_lds_bytes(THREADS)];
+    uint64_t* cs = reinterpret_cast<uint64_t*>(smem);  // composites
+    uint32_t* w32 = reinterpret_cast<uint32_t*>(smem);  // values, then staging
+
+    const uint32_t t = blockIdx.x;
+    int64_t g, j;
+    {
+        const uint32_t q = m4_udiv(t, g4.by_tiles);
+        g = q < (uint64_t)g4.full_groups ? q : g4.full_groups;
+        j = (int64_t)t - g * g4.tiles_full;
+    }
+    const int64_t row = m4_bound_row(g4, g, j);
+    const int64_t gb = g * 4 * g4.L;
+    int c[4];
+    uint32_t sh[4];  // tile key x of slice r is group key x + sh[r] (< 4L < 2^31)
+    int64_t ostart = gb;
+    int pst[5];
+    pst[0] = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int lo = bnd[row * 4 + r];
+        c[r] = bnd[(row + 1) * 4 + r] - lo;
+        ostart += lo;
+        sh[r] = (uint32_t)(r * g4.L + lo - pst[r]);
+        pst[r + 1] = pst[r] + c[r];
+    }
+    const int p1 = pst[1], p2 = pst[2], p3 = pst[3], cnt = pst[4];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int X0 = (tid >> 6) * 64 * KPT;
+
+    // ---- load: thread keys and values at tile positions X0 + 64 q + lane
+    uint32_t rv[KPT];
+    {
+        const uint32_t* gk = kin + gb;
+        const uint32_t* gv = vin + gb;
+        uint32_t rk[KPT], src[KPT];
+#pragma unroll
+        for (int q = 0; q < KPT; ++q) {
+            const int x = X0 + 64 * q + lane;
+            const int xc = min(x, cnt - 1);
+            const bool c1 = xc >= p1, c2 = xc >= p2, c3 = xc >= p3;
+            src[q] = (uint32_t)xc + (c3 ? sh[3] : c2 ? sh[2] : c1 ? sh[1] : sh[0]);
+        }
+#pragma unroll
+        for (int q = 0; q < KPT; ++q) {
+            rk[q] = ld1_stream(gk + src[q]);
+            rv[q] = ld1_stream(gv + src[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < KPT; ++q) {
+            const int x = X0 + 64 * q + lane;
+            if (x < cnt) {
+                const int gap = x >= p3 ? 3 * kM4Gap : x >= p2 ? 2 * kM4Gap : x >= p1 ? kM4Gap : 0;
+                cs[lds_idx<uint64_t>(x + gap)] = ((uint64_t)ord_key<DT>(rk[q]) << 32) | (uint32_t)x;
+            }
+        }
+        if (tid < MK) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) cs[lds_idx<uint64_t>(pst[r + 1] + r * kM4Gap + tid)] = kMaxC;
+        }
+    }
+    __syncthreads();
+
+    // ---- level 1: X = merge(s0, s1) at 0, Y = merge(s2, s3) at ybase
+    const int nx = p2, ny = cnt - p2;
+    const int ybase = (nx + MK + 15) & ~15;
+    {
+        const int tx = (nx + MK - 1) / MK, ty = (ny + MK - 1) / MK;
+        uint64_t o[MK];
+        const bool in_x = tid < tx;
+        const bool active = tid < tx + ty;
+        const int d = in_x ? tid * MK : (tid - tx) * MK;
+        const int sa = in_x ? 0 : p2 + 2 * kM4Gap, la = in_x ? c[0] : c[2];
+        const int sb = in_x ? p1 + kM4Gap : p3 + 3 * kM4Gap, lb = in_x ? c[1] : c[3];
+        const int base2 = (in_x ? 0 : ybase) + d;  // a multiple of 16
+        if (active) {
+            const int i = corank_lds(cs, sa, la, sb, lb, d, PlainLess{});
+            serial_merge_closed<uint64_t, MK>(cs, sa + i, sb + d - i, o);
+        }
+        __syncthreads();
+        if (active) {
+#pragma unroll
+            for (int k = 0; k < MK; ++k) cs[lds_idx<uint64_t>(base2 + k)] = o[k];
+        }
+        if (tid < MK) {
+            cs[lds_idx<uint64_t>(nx + tid)] = kMaxC;
+            cs[lds_idx<uint64_t>(ybase + ny + tid)] = kMaxC;
+        }
+    }
+    __syncthreads();
+
+    // ---- level 2: merge(X, Y)
+    const int d = tid * MK;
+    uint64_t o[MK];
+    if (d < cnt) {
+        const int i = corank_lds(cs, 0, nx, ybase, ny, d, PlainLess{});
+        serial_merge_closed<uint64_t, MK>(cs, i, ybase + d - i, o);
+    }
+    __syncthreads();
+    // values by tile position, then gathered through the composites
+#pragma unroll
+    for (int q = 0; q < KPT; ++q) {
+        const int x = X0 + 64 * q + lane;
+        if (x < cnt) w32[x + (x >> 5)] = rv[q];
+    }
+    __syncthreads();
+    uint32_t ok[MK], ov[MK];
+#pragma unroll
+    for (int k = 0; k < MK; ++k) {
+        const uint32_t x = (uint32_t)o[k];
+        ok[k] = unord_key<DT>((uint32_t)(o[k] >> 32));
+        ov[k] = d + k < cnt ? w32[x + (x >> 5)] : 0u;
+    }
+    // stage keys, then values (a spare word every 32), and store rows
+    uint32_t* stk = w32;
+    uint32_t* stv = w32 + kM4pStage;
+    __syncthreads();
+    if (d < cnt) {
+#pragma unroll
+        for (int k = 0; k < MK; ++k) {
+            stk[(d + k) + ((d + k) >> 5)] = ok[k];
+            stv[(d + k) + ((d + k) >> 5)] = ov[k];
+        }
+    }
+    __syncthreads();
+    constexpr int QR = m4_rows(THREADS);
+    const __amdgpu_buffer_rsrc_t rk_out =
+        __builtin_amdgcn_make_buffer_rsrc(kout + ostart, 0, cnt * 4, kRawBufferWord3);
+    const __amdgpu_buffer_rsrc_t rv_out =
+        __builtin_amdgcn_make_buffer_rsrc(vout + ostart, 0, cnt * 4, kRawBufferWord3);
+#pragma unroll
+    for (int q = 0; q < QR; ++q) {
+        const int e = tid + q * THREADS;
+        const int pe = e + (e >> 5);
+        __builtin_amdgcn_raw_buffer_store_b32(stk[pe], rk_out, e * 4, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(stv[pe], rv_out, e * 4, 0, 0);
+    }
+    // chunk samples of the output keys for the next pass
+    constexpr int G = kSampleChunk;
+    const int f0 = (int)((G - (ostart % G)) % G);
+    const int l0 = (int)((2 * G - 1 - (ostart % G)) % G);
+    if (tid < 32) {
+        const int e = f0 + tid * G;
+        if (e < cnt) samp_first[(ostart + e) / G] = stk[e + (e >> 5)];
+    } else if (tid < 64) {
+        const int e = l0 + (tid - 32) * G;
+        if (e < cnt) samp_last[(ostart + e) / G] = stk[e + (e >> 5)];
+    }
+}
+
 }  // namespace msn

@@ -306,11 +306,12 @@ int launch_merge4(const SortArgs& a, const uint32_t* in, uint32_t* out, const M4
     return (int)hipGetLastError();
 }
 
-// One four-way pass: runs of L in `in` -> runs of 4L in `out`.  L is a
-// power of two (the first-sweep run length times a power of four).
+// One four-way pass: runs of L in `in` -> runs of 4L in `out` (and their
+// values, vin -> vout, when vin is set).  L is a power of two (the
+// first-sweep run length times a power of four).
 template <int DT>
-int run_merge4(const SortArgs& a, const uint32_t* in, uint32_t* out, int64_t L, const Samples& sm,
-               int32_t* bnd) {
+int run_merge4(const SortArgs& a, const uint32_t* in, uint32_t* out, const uint32_t* vin,
+               uint32_t* vout, int64_t L, const Samples& sm, int32_t* bnd) {
     const M4Geom g4 = m4_geometry(a.n, L);
     const int64_t nck = (a.n + kSampleChunk - 1) / kSampleChunk;
     int lg_cl = 0;
@@ -329,6 +330,13 @@ int run_merge4(const SortArgs& a, const uint32_t* in, uint32_t* out, int64_t L, 
         }
     }
     if (int rc = (int)hipGetLastError()) return rc;
+    if (vin) {
+        LaunchTimer timer("merge4_pairs", a.n, a.stream);
+        hipLaunchKernelGGL((k_merge4_pairs<DT, 1024, 8>), dim3((unsigned)m4_tiles(g4)),
+                           dim3(1024), 0, a.stream, in, vin, out, vout, bnd, g4, sm.first,
+                           sm.last);
+        return (int)hipGetLastError();
+    }
     return a.merge4_kpt == 32 ? launch_merge4<DT, 256, 32>(a, in, out, g4, bnd, sm)
                               : launch_merge4<DT, 512, 16>(a, in, out, g4, bnd, sm);
 }
@@ -336,10 +344,10 @@ int run_merge4(const SortArgs& a, const uint32_t* in, uint32_t* out, int64_t L, 
 template <int DT>
 int run_sort(const SortArgs& a) {
     const int tile = first_run_length(a);
-    // Pass plan: four-way passes (integer keys-only sorts) while at least
-    // three runs remain, binary passes otherwise.
+    // Pass plan: four-way passes (integer keys, with or without values)
+    // while at least three runs remain, binary passes otherwise.
     bool four = false;
-    if constexpr (DT != kF32) four = a.merge_ways == 4 && a.vmode == kNoVals;
+    if constexpr (DT != kF32) four = a.merge_ways == 4;
     int ways[64];
     int passes = 0;
     for (int64_t runs = (a.n + tile - 1) / tile; runs > 1;) {
@@ -359,8 +367,8 @@ int run_sort(const SortArgs& a) {
     const size_t nchunks = (size_t)((a.n + kSampleChunk - 1) / kSampleChunk);
     const size_t ca = align_up(nchunks * 4, 256);
     Samples sm{reinterpret_cast<uint32_t*>(sbase), reinterpret_cast<uint32_t*>(sbase + ca), 0};
-    // boundary table of the four-way passes (keys-only sorts)
-    int32_t* bnd = vals ? nullptr : reinterpret_cast<int32_t*>(sbase + 2 * ca);
+    // boundary table of the four-way passes
+    int32_t* bnd = reinterpret_cast<int32_t*>(sbase + 2 * ca);
 
     // Ping-pong so that the last pass lands in the output.
     uint32_t* kb[2] = {a.kout, wk};
@@ -378,7 +386,9 @@ int run_sort(const SortArgs& a) {
     for (int p = 0; p < passes; ++p) {
         const int nxt = cur ^ 1;
         if (ways[p] == 4) {
-            if constexpr (DT != kF32) rc = run_merge4<DT>(a, kb[cur], kb[nxt], L, sm, bnd);
+            if constexpr (DT != kF32)
+                rc = run_merge4<DT>(a, kb[cur], kb[nxt], vals ? vb[cur] : nullptr,
+                                    vals ? vb[nxt] : nullptr, L, sm, bnd);
         } else {
             rc = vals ? dispatch_merge<DT, true>(a, kb[cur], vb[cur], kb[nxt], vb[nxt], part, L,
                                                  vec, sm)

@@ -187,6 +187,44 @@ def test_four_way_passes_match_oracle_and_binary(orc, dtype, leaf):
         assert np.array_equal(y, orc.sort(x, dtype=dtype)), bt_mult
 
 
+@pytest.mark.parametrize("leaf", ["6To8", "3To5"])
+@pytest.mark.parametrize("dtype", ["u32", "i32"])
+def test_four_way_pairs_stable(orc, dtype, leaf):
+    """Four-way passes over key-value pairs against the oracle's stable sort
+    and against binary passes: tie-heavy, sorted, reversed and extreme keys,
+    explicit payloads and argsort, groups that end in one to three runs."""
+    t = 1024 * (8 if leaf == "6To8" else 4)   # first-sweep run length of pairs
+    runs_list = [3, 4, 5, 6, 7, 9, 17, 64 + 3]
+    kinds = ["random", "few", "equal", "sorted", "reversed", "extremes"]
+    rng = np.random.default_rng(5)
+    for i, runs in enumerate(runs_list):
+        n = runs * t - (i % 3) * 97
+        for kind in kinds:
+            k = _tricky_keys(n, kind, dtype, seed=300 * i + len(kind))
+            v = rng.integers(0, 2**32, n, dtype=np.uint32)
+            rk, rv = orc.sort(k, vals=v, dtype=dtype, stable=True, config=leaf)
+            for ways in (4, 2):
+                say(f"four-way pairs ways={ways} dtype={dtype} leaf={leaf} n={n} kind={kind}")
+                ko, vo = msn.sort_pairs(gpu(k), gpu(v), leaf=leaf, tuning={"merge_ways": ways})
+                assert np.array_equal(host(ko), rk), (n, kind, ways)
+                assert np.array_equal(host(vo), rv), (n, kind, ways)
+            say(f"four-way argsort dtype={dtype} leaf={leaf} n={n} kind={kind}")
+            ko, po = msn.sort_pairs(gpu(k), None, leaf=leaf, tuning={"merge_ways": 4})
+            _, rp = orc.sort(k, dtype=dtype, stable=True, config=leaf, want_perm=True)
+            assert np.array_equal(host(ko), rk), (n, kind)
+            assert np.array_equal(host(po).view(np.uint32), rp), (n, kind)
+    # runs of 2^20 keys and more: boundary brackets wider than the LDS window
+    for kind in ("clustered", "few"):
+        n = 5 * (1 << 20) + 777
+        k = _tricky_keys(n, kind, dtype, seed=13)
+        v = np.arange(n, dtype=np.uint32)
+        say(f"four-way pairs large groups dtype={dtype} leaf={leaf} n={n} kind={kind}")
+        ko, vo = msn.sort_pairs(gpu(k), gpu(v), leaf=leaf)
+        rk, rv = orc.sort(k, vals=v, dtype=dtype, stable=True, config=leaf)
+        assert np.array_equal(host(ko), rk), (n, kind)
+        assert np.array_equal(host(vo), rv), (n, kind)
+
+
 def test_unaligned_views(orc):
     # offsets by one element: 4-byte aligned, not 16-byte aligned
     n = 50001
