@@ -297,6 +297,13 @@ def bench_pairs(args):
     ok &= bool(torch.equal(k.view(torch.int32)[vi], ko.view(torch.int32)))
     if not ok:
         raise SystemExit("[bench] pairs output check failed")
+    # the dominant merge kernel: the four-way passes, unless the plan had none
+    mkind = max((kk for kk in ("merge", "merge4_pairs") if kk in stats),
+                key=lambda kk: stats[kk]["total_ms"], default="merge")
+    pairs_roof = _roof(stats, mkind, lambda m: 16.0 * n)
+    if pairs_roof and mkind == "merge4_pairs":
+        pairs_roof["traffic"] = load_traffic("k_merge4_pairs_2p28_u32_traffic.md", "merge4.hpp")
+        pairs_roof["kernel"] = "k_merge4_pairs (four-way key-value merge pass)"
     return {
         "metric": "Gkeys/s, 2^28 uint32 key-value pairs (keys < 2^16, payload = index), 1 GPU",
         "value": n / (ms / 1e3) / 1e9, "unit": "Gkeys/s", "n_gpus": 1, "steps": args.steps,
@@ -305,7 +312,7 @@ def bench_pairs(args):
         "config": {"workload": f"sort_pairs: 2^{int(np.log2(n))} uint32 keys uniform in "
                                "[0, 2^16), uint32 payload = index, stable", "n": n,
                    "leaf": args.leaf},
-        "roofline": _roof(stats, "merge", lambda m: 16.0 * n),
+        "roofline": pairs_roof,
         "hbm_schedule": {"bytes_per_key": reference_schedule_bytes(n, 8),
                          "implied_gkeys_at_peak": HBM_PEAK_GBPS / reference_schedule_bytes(n, 8)},
         "kernels_ms_per_step": {kk: vv["total_ms"] / args.steps for kk, vv in stats.items()},

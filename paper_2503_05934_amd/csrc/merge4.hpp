@@ -32,22 +32,29 @@ constexpr int kM4MaxTile = (kM4SamplesPerTile + 4) * kSampleChunk - 4;
 // data format; accesses at byte offsets >= num_records are dropped (stores)
 // or return zero (loads).
 constexpr int kRawBufferWord3 = 0x00020000;
+// Cache policy of the passes' output row stores: nontemporal.  The rows
+// start at 64-word boundaries of the output, so every 256-byte store of a
+// wavefront covers two whole cache lines; the next pass's boundary search,
+// which reads the chunk samples and a few keys, then finds more of them in
+// the caches.
+constexpr int kM4StoreNt = 2;
+// Output rows of `threads` words that a tile (plus up to 63 words of
+// alignment) can touch.
+__host__ __device__ constexpr int m4_out_rows(int threads) {
+    return (kM4MaxTile + 63 + threads - 1) / threads;
+}
 constexpr int kM4Gap = 64;  // slice spacing in LDS (> kM4Sent sentinels, lane-aligned)
 constexpr int kM4Sent = 32;  // outputs per thread of the merge levels = sentinels per run
 // LDS keys: the slices with their gaps, or X and Y with theirs (Y starts at a
 // multiple of 32 at least KPT <= 32 past X), plus a dummy slot.
 __host__ __device__ constexpr int m4_buf_keys() { return kM4MaxTile + 4 * kM4Gap + 8; }
 // Level 1 needs ceil(nx/KPT) + ceil(ny/KPT) <= kM4MaxTile/KPT + 2 threads.
-// Rows of `threads` outputs that a tile can fill.
-__host__ __device__ constexpr int m4_rows(int threads) {
-    return (kM4MaxTile + threads - 1) / threads;
-}
 // LDS words: the padded buffer, or the staged output (a spare word every 32).
 __host__ __device__ constexpr int m4_lds_words(int threads) {
     return lds_words<uint32_t>(m4_buf_keys()) + 16 >
-                   m4_rows(threads) * threads + m4_rows(threads) * threads / 32 + 16
+                   m4_out_rows(threads) * threads + m4_out_rows(threads) * threads / 32 + 16
                ? lds_words<uint32_t>(m4_buf_keys()) + 16
-               : m4_rows(threads) * threads + m4_rows(threads) * threads / 32 + 16;
+               : m4_out_rows(threads) * threads + m4_out_rows(threads) * threads / 32 + 16;
 }
 
 // Division by a launch-invariant divisor with a multiply-high and shifts
@@ -723,18 +730,26 @@ __global__ __launch_bounds__(THREADS) void k_merge4(const uint32_t* __restrict__
         for (int k = 0; k < MK; ++k) sd[k] = (uint32_t)o[k];
     }
     __syncthreads();
-    constexpr int QR = m4_rows(THREADS);
+    // rows begin at the 64-word boundary at or before the tile start: the
+    // first `al` words of row 0 belong to the previous tile and are skipped
+    const int al = (int)(ostart & 63);
+    constexpr int QR = m4_out_rows(THREADS);
     uint32_t v[QR];
-    const uint32_t* sr = st + (tid + (tid >> 5));
+    {
+        const int e0 = max(tid - al, 0);
+        v[0] = st[e0 + (e0 >> 5)];
+        const uint32_t* sr = st + m4_idx((uint32_t)(tid - al + THREADS));
 #pragma unroll
-    for (int q = 0; q < QR; ++q) v[q] = sr[q * (THREADS + THREADS / 32)];
-    // raw buffer stores: the descriptor's byte bound (cnt keys) drops the
-    // stores past the tile end, so the rows need no per-lane guard
-    const __amdgpu_buffer_rsrc_t ro =
-        __builtin_amdgcn_make_buffer_rsrc(out + ostart, 0, cnt * 4, kRawBufferWord3);
+        for (int q = 1; q < QR; ++q) v[q] = sr[(q - 1) * (THREADS + THREADS / 32)];
+    }
+    // raw buffer stores: the descriptor's byte bound (the tile's last key)
+    // drops the stores past the tile end, so only row 0 needs a lane guard
+    const __amdgpu_buffer_rsrc_t ro = __builtin_amdgcn_make_buffer_rsrc(
+        out + (ostart - al), 0, (cnt + al) * 4, kRawBufferWord3);
 #pragma unroll
     for (int q = 0; q < QR; ++q)
-        __builtin_amdgcn_raw_buffer_store_b32(v[q], ro, (tid + q * THREADS) * 4, 0, 0);
+        if (q > 0 || tid >= al)
+            __builtin_amdgcn_raw_buffer_store_b32(v[q], ro, (tid + q * THREADS) * 4, 0, kM4StoreNt);
     // chunk samples of the output for the next pass
     constexpr int G = kSampleChunk;
     const int f0 = (int)((G - (ostart % G)) % G);             // first chunk start in the tile
@@ -761,10 +776,6 @@ __global__ __launch_bounds__(THREADS) void k_merge4(const uint32_t* __restrict__
 // position, gathered through the positions the composites carry, staged with
 // the keys and stored as rows.  MK = 16 outputs per thread of each level.
 constexpr int kM4pSent = 16;
-// Cache policy of the pass's output stores: nontemporal.  Measured on 2^28
-// pairs, the next pass's boundary search then runs about a third faster and
-// the pass itself loses less than that.
-constexpr int kM4StoreNt = 2;
 // Staged keys: every output a thread holds (up to MK - 1 past the tile end),
 // a spare word every 32; the staged values follow.
 constexpr int kM4pStage = kM4MaxTile + kM4pSent + (kM4MaxTile + kM4pSent) / 32 + 8;
@@ -773,9 +784,9 @@ constexpr int kM4pStage = kM4MaxTile + kM4pSent + (kM4MaxTile + kM4pSent) / 32 +
 // of `threads` words, the last row partly past the tile).
 __host__ __device__ constexpr int m4p_lds_bytes(int threads) {
     return 8 * lds_words<uint64_t>(kM4MaxTile + 4 * kM4Gap + 8) >
-                   4 * (kM4pStage + m4_rows(threads) * threads + m4_rows(threads) * threads / 32)
+                   4 * (kM4pStage + m4_out_rows(threads) * threads + m4_out_rows(threads) * threads / 32)
                ? 8 * lds_words<uint64_t>(kM4MaxTile + 4 * kM4Gap + 8)
-               : 4 * (kM4pStage + m4_rows(threads) * threads + m4_rows(threads) * threads / 32);
+               : 4 * (kM4pStage + m4_out_rows(threads) * threads + m4_out_rows(threads) * threads / 32);
 }
 
 template <int DT, int THREADS, int KPT>
@@ -940,17 +951,22 @@ __global__ __launch_bounds__(THREADS) void k_merge4_pairs(
         }
     }
     __syncthreads();
-    constexpr int QR = m4_rows(THREADS);
-    const __amdgpu_buffer_rsrc_t rk_out =
-        __builtin_amdgcn_make_buffer_rsrc(kout + ostart, 0, cnt * 4, kRawBufferWord3);
-    const __amdgpu_buffer_rsrc_t rv_out =
-        __builtin_amdgcn_make_buffer_rsrc(vout + ostart, 0, cnt * 4, kRawBufferWord3);
+    const int al = (int)(ostart & 63);  // as in k_merge4: 64-word-aligned rows
+    constexpr int QR = m4_out_rows(THREADS);
+    const __amdgpu_buffer_rsrc_t rk_out = __builtin_amdgcn_make_buffer_rsrc(
+        kout + (ostart - al), 0, (cnt + al) * 4, kRawBufferWord3);
+    const __amdgpu_buffer_rsrc_t rv_out = __builtin_amdgcn_make_buffer_rsrc(
+        vout + (ostart - al), 0, (cnt + al) * 4, kRawBufferWord3);
 #pragma unroll
     for (int q = 0; q < QR; ++q) {
-        const int e = tid + q * THREADS;
+        const int e = max(tid + q * THREADS - al, 0);
         const int pe = e + (e >> 5);
-        __builtin_amdgcn_raw_buffer_store_b32(stk[pe], rk_out, e * 4, 0, kM4StoreNt);
-        __builtin_amdgcn_raw_buffer_store_b32(stv[pe], rv_out, e * 4, 0, kM4StoreNt);
+        if (q > 0 || tid >= al) {
+            __builtin_amdgcn_raw_buffer_store_b32(stk[pe], rk_out, (tid + q * THREADS) * 4, 0,
+                                                  kM4StoreNt);
+            __builtin_amdgcn_raw_buffer_store_b32(stv[pe], rv_out, (tid + q * THREADS) * 4, 0,
+                                                  kM4StoreNt);
+        }
     }
     // chunk samples of the output keys for the next pass
     constexpr int G = kSampleChunk;
