@@ -337,12 +337,14 @@ struct SegTraits {
                                        : (kWaveLds > kMergeLds ? kWaveLds : kMergeLds);
 };
 
-// Keys-only kernels are held to 84 VGPRs so that three workgroups fit a
-// compute unit (their LDS allows it); a few bytes spill, and the extra
-// workgroups hide more of the big segments' load latency (4 % faster on the
-// 100,000-segment workload than two workgroups without spills).
+// Register budgets by occupancy: keys-only kernels are held to 84 VGPRs so
+// that three workgroups fit a compute unit, stable ones to 128 for two (what
+// their LDS allows).  Both spill some registers (a few bytes keys-only, up to
+// a few hundred bytes for the 8-key stable tiles), and both are faster for
+// it: 4 % on the 100,000-segment workload, 25 % on the fp32 row argsort,
+// where one workgroup per compute unit could not hide its LDS latency.
 template <int DT, int K, bool STABLE, int VM>
-__global__ __launch_bounds__(kBlockThreads, STABLE ? 1 : 6) void k_segmented(
+__global__ __launch_bounds__(kBlockThreads, STABLE ? 4 : 6) void k_segmented(
     const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, uint32_t* wk,
     uint32_t* wv, const uint32_t* __restrict__ offsets, int64_t num_segments, uint32_t uni_len,
     SegState* st, const uint32_t* __restrict__ lists) {
