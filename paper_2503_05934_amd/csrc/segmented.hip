@@ -6,12 +6,16 @@
 //          (Table 3, VarSort);
 //   wave   (<= wave_max): one wavefront, networks + bitonic merges;
 //   block  (<= block_max): one workgroup, network + bitonic + LDS merges;
-//   big    (> block_max): one workgroup sorts the segment's tiles in turn and
-//          then merges them pass by pass through global memory.
-// A binning launch sorts segment ids into per-class lists; the persistent
-// launch then pulls work items (largest classes first) from one atomic
-// counter until the list is exhausted.  No workgroup ever waits for another,
-// so any grid size terminates.
+//   tiled  (up to kSegTiledMax tiles): every tile is a work item of its own
+//          (one workgroup sorts it), then up to three merge passes over all
+//          such segments at once, one workgroup per output tile;
+//   big    (longer): one workgroup sorts the segment's tiles in turn and then
+//          merges them pass by pass through global memory.
+// A binning launch sorts segment ids into per-class lists (and the tiles of
+// tiled segments into a tile list); the persistent launch then pulls work
+// items (big segments first) from one atomic counter until the lists are
+// exhausted.  No workgroup ever waits for another, so any grid size
+// terminates.  The tiled segments' merge passes are separate launches.
 #include "block_tile.hpp"
 
 namespace msn {
@@ -20,26 +24,49 @@ enum SegClass : int {
     kCLane = 0,
     kCWave = 1,
     kCBlock = 2,
-    kCBig1 = 3,  // (1, 2] x block_max
-    kCBig2 = 4,  // (2, 4] x block_max
-    kCBig3 = 5,  // > 4 x block_max
-    kNumClasses = 6
+    kCTiled = 3,  // its tiles go to the tile list
+    kCBig = 4,    // longer than kSegTiledMax tiles
+    kNumClasses = 5
 };
 
 struct SegState {
     uint32_t count[8];
     uint32_t head;
-    uint32_t pad[7];
+    uint32_t tiles;  // entries of the tile list
+    uint32_t pad[6];
 };
+
+// Segments of up to this many block-sort tiles take the tiled path (at most
+// three merge passes).
+constexpr int kSegTiledMax = 8;
+constexpr int kSegTiledPasses = 3;
+static_assert((1 << kSegTiledPasses) == kSegTiledMax, "passes of the tiled path");
+
+// Tile list bound: a tiled segment of len keys has ceil(len / tile) tiles,
+// tile >= 4096 keys (3-to-5 leaves).
+inline size_t seg_max_tiles(int64_t n_total, int64_t num_segments) {
+    return (size_t)(n_total / 4096) + (size_t)num_segments + 1;
+}
 
 constexpr int kSegMergeKPT = 16;                               // keys per thread, big merges
 constexpr int kSegMergeTile = kSegMergeKPT * kBlockThreads;    // 8192 outputs per step
 constexpr int kSegBoundWords = kBlockThreads + 4;
 
+// Workspace: ping-pong keys (and values), the class lists, the state block,
+// the tile list (segment, tile) and one merge-path split per tile.
 size_t seg_ws_bytes(int64_t n_total, int64_t num_segments, bool vals) {
     const size_t nk = align_up((size_t)n_total * 4, 256);
     const size_t lists = align_up((size_t)num_segments * 4 * kNumClasses, 256);
-    return nk + (vals ? nk : 0) + lists + align_up(sizeof(SegState), 256);
+    const size_t mt = seg_max_tiles(n_total, num_segments);
+    return nk + (vals ? nk : 0) + lists + align_up(sizeof(SegState), 256) +
+           align_up(mt * 8, 256) + align_up(mt * 4, 256);
+}
+
+// Merge passes of a segment of `tiles` block-sort tiles: ceil(log2(tiles)).
+__host__ __device__ inline int seg_passes(uint32_t tiles) {
+    int p = 0;
+    while ((1u << p) < tiles) ++p;
+    return p;
 }
 
 __device__ __forceinline__ void seg_bounds(const uint32_t* offsets, uint32_t s, uint32_t uni_len,
@@ -59,36 +86,47 @@ __global__ void k_seg_init(SegState* st) {
     if (threadIdx.x < sizeof(SegState) / 4) reinterpret_cast<uint32_t*>(st)[threadIdx.x] = 0u;
 }
 
-// Classes are counted per workgroup in LDS first, so each workgroup makes
-// one global atomic per class instead of one per segment (six global
-// counters shared by every segment would serialise).
+// Classes (and tiles) are counted per workgroup in LDS first, so each
+// workgroup makes one global atomic per class instead of one per segment (a
+// few global counters shared by every segment would serialise).
 __global__ __launch_bounds__(256) void k_seg_bin(const uint32_t* __restrict__ offsets,
                                                  int64_t num_segments, uint32_t uni_len,
                                                  int lane_max, int wave_max, int block_max,
-                                                 SegState* st, uint32_t* __restrict__ lists) {
-    __shared__ uint32_t cnt[kNumClasses], base[kNumClasses];
+                                                 uint32_t tile, SegState* st,
+                                                 uint32_t* __restrict__ lists,
+                                                 uint2* __restrict__ tiles) {
+    __shared__ uint32_t cnt[kNumClasses + 1], base[kNumClasses + 1];  // + the tile count
     const int tid = threadIdx.x;
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + tid;
-    if (tid < kNumClasses) cnt[tid] = 0u;
+    if (tid <= kNumClasses) cnt[tid] = 0u;
     __syncthreads();
     int cls = -1;
-    uint32_t pos = 0;
+    uint32_t pos = 0, nt = 0, tpos = 0;
     if (s < num_segments) {
         uint32_t off, len;
         seg_bounds(offsets, (uint32_t)s, uni_len, off, len);
-        const uint32_t b = (uint32_t)block_max;
         if (len <= (uint32_t)lane_max) cls = kCLane;
         else if (len <= (uint32_t)wave_max) cls = kCWave;
-        else if (len <= b) cls = kCBlock;
-        else if (len <= 2 * b) cls = kCBig1;
-        else if (len <= 4 * b) cls = kCBig2;
-        else cls = kCBig3;
-        pos = atomicAdd(&cnt[cls], 1u);
+        else if (len <= (uint32_t)block_max) cls = kCBlock;
+        else if (len <= (uint32_t)kSegTiledMax * tile) cls = kCTiled;
+        else cls = kCBig;
+        if (cls == kCTiled) {
+            nt = (len + tile - 1) / tile;
+            tpos = atomicAdd(&cnt[kNumClasses], nt);
+        } else {
+            pos = atomicAdd(&cnt[cls], 1u);
+        }
     }
     __syncthreads();
     if (tid < kNumClasses && cnt[tid] != 0u) base[tid] = atomicAdd(&st->count[tid], cnt[tid]);
+    if (tid == kNumClasses && cnt[tid] != 0u) base[tid] = atomicAdd(&st->tiles, cnt[tid]);
     __syncthreads();
-    if (cls >= 0) lists[(int64_t)cls * num_segments + base[cls] + pos] = (uint32_t)s;
+    if (cls == kCTiled) {
+        for (uint32_t c = 0; c < nt; ++c)
+            tiles[base[kNumClasses] + tpos + c] = make_uint2((uint32_t)s, c);
+    } else if (cls >= 0) {
+        lists[(int64_t)cls * num_segments + base[cls] + pos] = (uint32_t)s;
+    }
 }
 
 // ------------------------------------------------------------ lane tasks ---
@@ -219,6 +257,78 @@ __device__ __forceinline__ int corank_global(const uint32_t* A, int la, const ui
     return lo;
 }
 
+// One output tile of a merge pass, by one workgroup: outputs [d0, d1) of the
+// stable merge of A = ks[base, base + la) and B = ks[base + la, base + la +
+// lb) (segment positions), A contributing [i0, i1); they land at kd[base +
+// d0 ...].  sk/sv: LDS of lds_words(KPT * kBlockThreads) words each.
+template <int DT, bool VALS, int KPT>
+__device__ __forceinline__ void seg_merge_tile(const uint32_t* ks, const uint32_t* vs,
+                                               uint32_t* kd, uint32_t* vd, int base, int la,
+                                               int d0, int d1, int i0, int i1, uint32_t* sk,
+                                               uint32_t* sv) {
+    const int tid = threadIdx.x;
+    const int na = i1 - i0;
+    const int cnt = d1 - d0;
+    const int nb = cnt - na;
+    const int j0 = d0 - i0;
+    {
+        uint32_t rk[KPT], rv[KPT];
+#pragma unroll
+        for (int q = 0; q < KPT; ++q) {
+            const int x = min(tid + q * kBlockThreads, cnt - 1);
+            const int src = x < na ? base + i0 + x : base + la + j0 + (x - na);
+            rk[q] = ks[src];
+            if constexpr (VALS) rv[q] = vs[src];
+        }
+#pragma unroll
+        for (int q = 0; q < KPT; ++q) {
+            const int x = tid + q * kBlockThreads;
+            if (x < cnt) {
+                sk[lds_idx<uint32_t>(x)] = rk[q];
+                if constexpr (VALS) sv[lds_idx<uint32_t>(x)] = rv[q];
+            }
+        }
+    }
+    __syncthreads();
+    const int d = tid * KPT;
+    uint32_t o[KPT], ov[KPT];
+    if (d < cnt) {
+        const int i = corank_lds(sk, 0, na, na, nb, d, OrdLess<DT>{});
+        int srcpos[KPT];
+        serial_merge<uint32_t, KPT, VALS>(sk, 0, na, na, nb, i, d - i, cnt - 1, o, srcpos,
+                                          OrdLess<DT>{});
+        if constexpr (VALS) {
+#pragma unroll
+            for (int k = 0; k < KPT; ++k) ov[k] = sv[lds_idx<uint32_t>(srcpos[k])];
+        }
+    }
+    // stage the outputs (a spare word every 32) and store them as rows of
+    // consecutive words, so that every store instruction is coalesced
+    __syncthreads();
+    if (d < cnt) {
+#pragma unroll
+        for (int k = 0; k < KPT; ++k) {
+            const int e = d + k;
+            if (e < cnt) {
+                sk[e + (e >> 5)] = o[k];
+                if constexpr (VALS) sv[e + (e >> 5)] = ov[k];
+            }
+        }
+    }
+    __syncthreads();
+    uint32_t* kr = kd + base + d0;
+    uint32_t* vr = VALS ? vd + base + d0 : nullptr;
+#pragma unroll
+    for (int q = 0; q < KPT; ++q) {
+        const int e = tid + q * kBlockThreads;
+        if (e < cnt) {
+            kr[e] = sk[e + (e >> 5)];
+            if constexpr (VALS) vr[e] = sv[e + (e >> 5)];
+        }
+    }
+    __syncthreads();
+}
+
 // One merge pass over a whole segment by one workgroup: runs of L become
 // runs of 2L, kSegMergeTile outputs per step.
 template <int DT, bool VALS>
@@ -249,45 +359,8 @@ __device__ void wg_merge_pass(const uint32_t* ks, const uint32_t* vs, uint32_t* 
             const int d1 = min(d0 + kSegMergeTile, plen);
             const int i0 = sb[t - t0];
             const int i1 = (d1 == plen) ? la : sb[t + 1 - t0];
-            const int na = i1 - i0;
-            const int cnt = d1 - d0;
-            const int nb = cnt - na;
-            const int j0 = d0 - i0;
-            {
-                uint32_t rk[kSegMergeKPT], rv[kSegMergeKPT];
-#pragma unroll
-                for (int q = 0; q < kSegMergeKPT; ++q) {
-                    const int x = min(tid + q * kBlockThreads, cnt - 1);
-                    const int src = x < na ? base + i0 + x : base + la + j0 + (x - na);
-                    rk[q] = ks[src];
-                    if constexpr (VALS) rv[q] = vs[src];
-                }
-#pragma unroll
-                for (int q = 0; q < kSegMergeKPT; ++q) {
-                    const int x = tid + q * kBlockThreads;
-                    if (x < cnt) {
-                        sk[lds_idx<uint32_t>(x)] = rk[q];
-                        if constexpr (VALS) sv[lds_idx<uint32_t>(x)] = rv[q];
-                    }
-                }
-            }
-            __syncthreads();
-            const int d = tid * kSegMergeKPT;
-            if (d < cnt) {
-                const int i = corank_lds(sk, 0, na, na, nb, d, OrdLess<DT>{});
-                uint32_t o[kSegMergeKPT];
-                int srcpos[kSegMergeKPT];
-                serial_merge<uint32_t, kSegMergeKPT, VALS>(sk, 0, na, na, nb, i, d - i, cnt - 1,
-                                                           o, srcpos, OrdLess<DT>{});
-#pragma unroll
-                for (int k = 0; k < kSegMergeKPT; ++k) {
-                    if (d + k < cnt) {
-                        kd[g0 + d + k] = o[k];
-                        if constexpr (VALS) vd[g0 + d + k] = sv[lds_idx<uint32_t>(srcpos[k])];
-                    }
-                }
-            }
-            __syncthreads();
+            seg_merge_tile<DT, VALS, kSegMergeKPT>(ks, vs, kd, vd, base, la, d0, d1, i0, i1, sk,
+                                                   sv);
         }
     }
 }
@@ -347,59 +420,70 @@ template <int DT, int K, bool STABLE, int VM>
 __global__ __launch_bounds__(kBlockThreads, STABLE ? 4 : 6) void k_segmented(
     const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, uint32_t* wk,
     uint32_t* wv, const uint32_t* __restrict__ offsets, int64_t num_segments, uint32_t uni_len,
-    SegState* st, const uint32_t* __restrict__ lists) {
+    SegState* st, const uint32_t* __restrict__ lists, const uint2* __restrict__ tiles) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t s_item;
     const int tid = threadIdx.x;
+    constexpr int kTile = TileTraits<DT, K, STABLE>::kTile;
 
     const uint32_t n_lane = st->count[kCLane];
     const uint32_t n_wave = st->count[kCWave];
     const uint32_t n_block = st->count[kCBlock];
-    const uint32_t n_big1 = st->count[kCBig1];
-    const uint32_t n_big2 = st->count[kCBig2];
-    const uint32_t n_big3 = st->count[kCBig3];
+    const uint32_t n_big = st->count[kCBig];
+    const uint32_t n_tiles = st->tiles;
     constexpr uint32_t kWavesPerBlock = kBlockThreads / kWave;
     const uint32_t wave_items = (n_wave + kWavesPerBlock - 1) / kWavesPerBlock;
     const uint32_t lane_items = (n_lane + kBlockThreads - 1) / kBlockThreads;
-    // queue order: big3, big2, big1, block, wave items, lane items
-    const uint32_t e0 = n_big3;
-    const uint32_t e1 = e0 + n_big2;
-    const uint32_t e2 = e1 + n_big1;
-    const uint32_t e3 = e2 + n_block;
-    const uint32_t e4 = e3 + wave_items;
-    const uint32_t e5 = e4 + lane_items;
+    // queue order: big segments, tiles of tiled segments, block, wave items,
+    // lane items
+    const uint32_t e0 = n_big;
+    const uint32_t e1 = e0 + n_tiles;
+    const uint32_t e2 = e1 + n_block;
+    const uint32_t e3 = e2 + wave_items;
+    const uint32_t e4 = e3 + lane_items;
     const uint32_t* L = lists;
     const int64_t S = num_segments;
+    auto al = [](const void* p) { return ((uintptr_t)p & 15u) == 0; };
 
     for (;;) {
         if (tid == 0) s_item = atomicAdd(&st->head, 1u);
         __syncthreads();
         const uint32_t item = s_item;
         __syncthreads();
-        if (item >= e5) break;
-        if (item < e3) {
-            uint32_t seg;
-            if (item < e0) seg = L[kCBig3 * S + item];
-            else if (item < e1) seg = L[kCBig2 * S + (item - e0)];
-            else if (item < e2) seg = L[kCBig1 * S + (item - e1)];
-            else seg = L[kCBlock * S + (item - e2)];
+        if (item >= e4) break;
+        if (item < e0) {
             uint32_t off, len;
-            seg_bounds(offsets, seg, uni_len, off, len);
-            if (item < e2) {
-                big_task<DT, K, STABLE, VM>(kin, vin, kout, vout, wk, wv, off, (int)len, smem);
-            } else {
-                auto al = [](const void* p) { return ((uintptr_t)p & 15u) == 0; };
-                const bool vec = al(kin + off) && al(kout + off) &&
-                                 (VM == kNoVals || al(vout + off)) &&
-                                 (VM != kVals || al(vin + off));
-                block_sort_tile<DT, K, STABLE, VM>(kin + off, VM == kVals ? vin + off : nullptr,
-                                                   kout + off,
-                                                   VM != kNoVals ? vout + off : nullptr,
-                                                   (int)len, 0u, smem, vec);
-            }
-        } else if (item < e4) {
+            seg_bounds(offsets, L[kCBig * S + item], uni_len, off, len);
+            big_task<DT, K, STABLE, VM>(kin, vin, kout, vout, wk, wv, off, (int)len, smem);
+        } else if (item < e1) {
+            // one tile of a tiled segment, written where its first merge pass
+            // reads it (the output itself when the segment has one tile)
+            const uint2 tc = tiles[item - e0];
+            uint32_t off, len;
+            seg_bounds(offsets, tc.x, uni_len, off, len);
+            const int passes = seg_passes((len + kTile - 1) / kTile);
+            const uint32_t first = tc.y * (uint32_t)kTile;
+            const int nv = min(kTile, (int)(len - first));
+            uint32_t* kd = ((passes & 1) ? wk : kout) + off + first;
+            uint32_t* vd =
+                VM != kNoVals ? ((passes & 1) ? wv : vout) + off + first : nullptr;
+            const uint32_t* ks = kin + off + first;
+            const uint32_t* vs = VM == kVals ? vin + off + first : nullptr;
+            const bool vec = al(ks) && al(kd) && (VM == kNoVals || al(vd)) &&
+                             (VM != kVals || al(vs));
+            block_sort_tile<DT, K, STABLE, VM>(ks, vs, kd, vd, nv, first, smem, vec);
+        } else if (item < e2) {
+            uint32_t off, len;
+            seg_bounds(offsets, L[kCBlock * S + (item - e1)], uni_len, off, len);
+            const bool vec = al(kin + off) && al(kout + off) &&
+                             (VM == kNoVals || al(vout + off)) &&
+                             (VM != kVals || al(vin + off));
+            block_sort_tile<DT, K, STABLE, VM>(kin + off, VM == kVals ? vin + off : nullptr,
+                                               kout + off, VM != kNoVals ? vout + off : nullptr,
+                                               (int)len, 0u, smem, vec);
+        } else if (item < e3) {
             const uint32_t w = (uint32_t)tid / kWave;
-            const uint32_t idx = (item - e3) * kWavesPerBlock + w;
+            const uint32_t idx = (item - e2) * kWavesPerBlock + w;
             if (idx < n_wave) {
                 uint32_t off, len;
                 seg_bounds(offsets, L[kCWave * S + idx], uni_len, off, len);
@@ -408,7 +492,7 @@ __global__ __launch_bounds__(kBlockThreads, STABLE ? 4 : 6) void k_segmented(
                 wave_task<DT, K, STABLE, VM>(kin, vin, kout, vout, off, (int)len, wst);
             }
         } else {
-            const uint32_t idx = (item - e4) * kBlockThreads + (uint32_t)tid;
+            const uint32_t idx = (item - e3) * kBlockThreads + (uint32_t)tid;
             if (idx < n_lane) {
                 uint32_t off, len;
                 seg_bounds(offsets, L[kCLane * S + idx], uni_len, off, len);
@@ -418,49 +502,173 @@ __global__ __launch_bounds__(kBlockThreads, STABLE ? 4 : 6) void k_segmented(
     }
 }
 
+// ---------------------------------------------- merge passes, tiled path ---
+// Pass p of every tiled segment that has more than p passes: runs of
+// tile << p become runs of tile << (p + 1), one output tile per list entry.
+// The data alternate between the output and the workspace so that the last
+// pass of each segment lands in the output.
+
+struct SegTilePass {
+    const uint32_t* ks;  // keys before the pass (segment-relative after + off)
+    const uint32_t* vs;
+    uint32_t* kd;        // keys after the pass
+    uint32_t* vd;
+    uint32_t off, len;
+    int base, la, lb, d0, d1;  // merge of [base, base+la) and [base+la, base+la+lb)
+};
+
+// Geometry of list entry (seg, c) in pass p; false when the segment has no
+// pass p.
+template <bool VALS>
+__device__ __forceinline__ bool seg_tile_pass(uint2 tc, int p, int tile, const uint32_t* offsets,
+                                              uint32_t uni_len, uint32_t* kout, uint32_t* vout,
+                                              uint32_t* wk, uint32_t* wv, SegTilePass& g) {
+    seg_bounds(offsets, tc.x, uni_len, g.off, g.len);
+    const int passes = seg_passes((g.len + tile - 1) / tile);
+    if (passes <= p) return false;
+    const bool src_ws = ((passes - p) & 1) != 0;  // before pass p the data sit in wk
+    g.ks = (src_ws ? wk : kout) + g.off;
+    g.kd = (src_ws ? kout : wk) + g.off;
+    g.vs = VALS ? (src_ws ? wv : vout) + g.off : nullptr;
+    g.vd = VALS ? (src_ws ? vout : wv) + g.off : nullptr;
+    const int L = tile << p;
+    const int len = (int)g.len;
+    const int g0 = (int)tc.y * tile;
+    g.base = g0 & ~(2 * L - 1);
+    g.la = min(L, len - g.base);
+    g.lb = min(L, len - g.base - g.la);
+    g.d0 = g0 - g.base;
+    g.d1 = min(g.d0 + tile, g.la + g.lb);
+    return true;
+}
+
+// Merge-path split of every list entry's first output (one thread each).
+template <int DT, bool VALS>
+__global__ __launch_bounds__(256) void k_seg_tile_part(
+    uint32_t* kout, uint32_t* vout, uint32_t* wk, uint32_t* wv,
+    const uint32_t* __restrict__ offsets, uint32_t uni_len, const SegState* st,
+    const uint2* __restrict__ tiles, int32_t* __restrict__ part, int tile, int p) {
+    const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= st->tiles) return;
+    SegTilePass g;
+    if (!seg_tile_pass<VALS>(tiles[e], p, tile, offsets, uni_len, kout, vout, wk, wv, g)) return;
+    part[e] = corank_global<DT>(g.ks + g.base, g.la, g.ks + g.base + g.la, g.lb, g.d0);
+}
+
+// The output tiles of pass p, workgroups taking list entries in turn.
+template <int DT, bool VALS, int KPT>
+__global__ __launch_bounds__(kBlockThreads) void k_seg_tile_merge(
+    uint32_t* kout, uint32_t* vout, uint32_t* wk, uint32_t* wv,
+    const uint32_t* __restrict__ offsets, uint32_t uni_len, const SegState* st,
+    const uint2* __restrict__ tiles, const int32_t* __restrict__ part, int p) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int kTile = KPT * kBlockThreads;
+    uint32_t* sk = reinterpret_cast<uint32_t*>(smem);
+    uint32_t* sv = sk + lds_words<uint32_t>(kTile);
+    const uint32_t n = st->tiles;
+    for (uint32_t e = blockIdx.x; e < n; e += gridDim.x) {
+        SegTilePass g;
+        if (!seg_tile_pass<VALS>(tiles[e], p, kTile, offsets, uni_len, kout, vout, wk, wv, g))
+            continue;
+        const int i0 = part[e];
+        const int i1 = g.d1 == g.la + g.lb ? g.la : part[e + 1];
+        seg_merge_tile<DT, VALS, KPT>(g.ks, g.vs, g.kd, g.vd, g.base, g.la, g.d0, g.d1, i0, i1,
+                                      sk, sv);
+    }
+}
+
 // ------------------------------------------------------------------ host ---
 namespace {
 
+// Workgroups that fill every compute unit with kernel `kern` (cached per
+// kernel: one device per process).
+template <typename Kern>
+int fill_grid(Kern kern, int threads, size_t lds, int* cache, int* out) {
+    if (*cache == 0) {
+        int dev = 0, cus = 0, per_cu = 0;
+        if (int rc = (int)hipGetDevice(&dev)) return rc;
+        if (int rc = (int)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev))
+            return rc;
+        if (int rc = (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &per_cu, reinterpret_cast<const void*>(kern), threads, lds))
+            return rc;
+        *cache = cus * (per_cu > 0 ? per_cu : 1);
+    }
+    *out = *cache;
+    return 0;
+}
+
+struct SegWs {
+    uint32_t *wk, *wv, *lists;
+    SegState* st;
+    uint2* tiles;
+    int32_t* part;
+    size_t max_tiles;
+};
+
 template <int DT, int K, bool STABLE, int VM>
-int launch_seg_kernel(const SegArgs& a, uint32_t* wk, uint32_t* wv, SegState* st,
-                      const uint32_t* lists, uint32_t uni_len) {
+int launch_seg_kernel(const SegArgs& a, const SegWs& w, uint32_t uni_len) {
     using Tr = SegTraits<DT, K, STABLE, VM>;
+    constexpr bool kVals = VM != kNoVals;
+    constexpr int kTile = TileTraits<DT, K, STABLE>::kTile;
+    constexpr int kKpt = kTile / kBlockThreads;
     auto kern = &k_segmented<DT, K, STABLE, VM>;
     if (int rc = set_dynamic_lds(reinterpret_cast<const void*>(kern), Tr::kLds)) return rc;
     int grid = a.grid;
     if (grid <= 0) {
         static int cached = 0;
-        if (cached == 0) {
-            int dev = 0, cus = 0, per_cu = 0;
-            if (int rc = (int)hipGetDevice(&dev)) return rc;
-            if (int rc = (int)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
-                                                    dev))
-                return rc;
-            if (int rc = (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                    &per_cu, reinterpret_cast<const void*>(kern), kBlockThreads, Tr::kLds))
-                return rc;
-            cached = cus * (per_cu > 0 ? per_cu : 1);
-        }
-        grid = cached;
+        if (int rc = fill_grid(kern, kBlockThreads, Tr::kLds, &cached, &grid)) return rc;
     }
     {
         LaunchTimer timer("segmented", a.n_total, a.stream);
         hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlockThreads), Tr::kLds, a.stream, a.kin,
-                           a.vin, a.kout, a.vout, wk, wv, a.offsets, a.num_segments, uni_len, st,
-                           lists);
+                           a.vin, a.kout, a.vout, w.wk, w.wv, a.offsets, a.num_segments, uni_len,
+                           w.st, w.lists, w.tiles);
     }
-    return (int)hipGetLastError();
+    if (int rc = (int)hipGetLastError()) return rc;
+    // merge passes of the tiled segments (none of them when the list is empty)
+    auto mkern = &k_seg_tile_merge<DT, kVals, kKpt>;
+    const size_t mlds = (size_t)lds_words<uint32_t>(kTile) * 4 * (kVals ? 2 : 1);
+    if (int rc = set_dynamic_lds(reinterpret_cast<const void*>(mkern), mlds)) return rc;
+    int mgrid = 0;
+    {
+        static int cached = 0;
+        if (int rc = fill_grid(mkern, kBlockThreads, mlds, &cached, &mgrid)) return rc;
+    }
+    const unsigned pgrid = (unsigned)((w.max_tiles + 255) / 256);
+    // equal-length segments: the host knows their class and pass count
+    int npass = kSegTiledPasses;
+    if (!a.offsets) {
+        const int64_t len = uni_len;
+        const bool tiled = len > a.block_max && len <= (int64_t)kSegTiledMax * kTile;
+        npass = tiled ? seg_passes((uint32_t)((len + kTile - 1) / kTile)) : 0;
+    }
+    for (int p = 0; p < npass; ++p) {
+        {
+            LaunchTimer timer("seg_tile_part", a.n_total, a.stream);
+            hipLaunchKernelGGL((k_seg_tile_part<DT, kVals>), dim3(pgrid), dim3(256), 0, a.stream,
+                               a.kout, a.vout, w.wk, w.wv, a.offsets, uni_len, w.st, w.tiles,
+                               w.part, kTile, p);
+        }
+        if (int rc = (int)hipGetLastError()) return rc;
+        {
+            LaunchTimer timer("seg_tile_merge", a.n_total, a.stream);
+            hipLaunchKernelGGL(mkern, dim3(mgrid), dim3(kBlockThreads), mlds, a.stream, a.kout,
+                               a.vout, w.wk, w.wv, a.offsets, uni_len, w.st, w.tiles, w.part, p);
+        }
+        if (int rc = (int)hipGetLastError()) return rc;
+    }
+    return 0;
 }
 
 template <int DT, int K>
-int dispatch_seg(const SegArgs& a, uint32_t* wk, uint32_t* wv, SegState* st,
-                 const uint32_t* lists, uint32_t uni_len) {
-    if (a.vmode == kVals) return launch_seg_kernel<DT, K, true, kVals>(a, wk, wv, st, lists, uni_len);
-    if (a.vmode == kArg) return launch_seg_kernel<DT, K, true, kArg>(a, wk, wv, st, lists, uni_len);
+int dispatch_seg(const SegArgs& a, const SegWs& w, uint32_t uni_len) {
+    if (a.vmode == kVals) return launch_seg_kernel<DT, K, true, kVals>(a, w, uni_len);
+    if (a.vmode == kArg) return launch_seg_kernel<DT, K, true, kArg>(a, w, uni_len);
     if constexpr (DT == kF32)
-        return launch_seg_kernel<DT, K, true, kNoVals>(a, wk, wv, st, lists, uni_len);
+        return launch_seg_kernel<DT, K, true, kNoVals>(a, w, uni_len);
     else
-        return launch_seg_kernel<DT, K, false, kNoVals>(a, wk, wv, st, lists, uni_len);
+        return launch_seg_kernel<DT, K, false, kNoVals>(a, w, uni_len);
 }
 
 }  // namespace
@@ -470,36 +678,44 @@ int launch_segmented(const SegArgs& a) {
     const bool vals = a.vmode != kNoVals;
     uint8_t* ws = static_cast<uint8_t*>(a.ws);
     const size_t nk = align_up((size_t)a.n_total * 4, 256);
-    uint32_t* wk = reinterpret_cast<uint32_t*>(ws);
-    uint32_t* wv = vals ? reinterpret_cast<uint32_t*>(ws + nk) : nullptr;
-    uint32_t* lists = reinterpret_cast<uint32_t*>(ws + nk + (vals ? nk : 0));
-    SegState* st = reinterpret_cast<SegState*>(
-        ws + nk + (vals ? nk : 0) +
-        align_up((size_t)a.num_segments * 4 * kNumClasses, 256));
+    const size_t nl = align_up((size_t)a.num_segments * 4 * kNumClasses, 256);
+    SegWs w;
+    w.max_tiles = seg_max_tiles(a.n_total, a.num_segments);
+    w.wk = reinterpret_cast<uint32_t*>(ws);
+    w.wv = vals ? reinterpret_cast<uint32_t*>(ws + nk) : nullptr;
+    uint8_t* q = ws + nk + (vals ? nk : 0);
+    w.lists = reinterpret_cast<uint32_t*>(q);
+    q += nl;
+    w.st = reinterpret_cast<SegState*>(q);
+    q += align_up(sizeof(SegState), 256);
+    w.tiles = reinterpret_cast<uint2*>(q);
+    q += align_up(w.max_tiles * 8, 256);
+    w.part = reinterpret_cast<int32_t*>(q);
     const uint32_t uni_len = a.offsets ? 0u : (uint32_t)(a.n_total / a.num_segments);
+    const uint32_t tile = 1024u * (uint32_t)a.leaf_k;  // the block-sort tile of every segmented kernel
 
     {
         LaunchTimer timer("seg_init", 1, a.stream);
-        hipLaunchKernelGGL(k_seg_init, dim3(1), dim3(64), 0, a.stream, st);
+        hipLaunchKernelGGL(k_seg_init, dim3(1), dim3(64), 0, a.stream, w.st);
     }
     if (int rc = (int)hipGetLastError()) return rc;
     {
         LaunchTimer timer("seg_bin", a.num_segments, a.stream);
         hipLaunchKernelGGL(k_seg_bin, dim3((unsigned)((a.num_segments + 255) / 256)), dim3(256),
                            0, a.stream, a.offsets, a.num_segments, uni_len, a.lane_max,
-                           a.wave_max, a.block_max, st, lists);
+                           a.wave_max, a.block_max, tile, w.st, w.lists, w.tiles);
     }
     if (int rc = (int)hipGetLastError()) return rc;
     switch (a.dtype) {
         case kU32:
-            return a.leaf_k == 8 ? dispatch_seg<kU32, 8>(a, wk, wv, st, lists, uni_len)
-                                 : dispatch_seg<kU32, 4>(a, wk, wv, st, lists, uni_len);
+            return a.leaf_k == 8 ? dispatch_seg<kU32, 8>(a, w, uni_len)
+                                 : dispatch_seg<kU32, 4>(a, w, uni_len);
         case kI32:
-            return a.leaf_k == 8 ? dispatch_seg<kI32, 8>(a, wk, wv, st, lists, uni_len)
-                                 : dispatch_seg<kI32, 4>(a, wk, wv, st, lists, uni_len);
+            return a.leaf_k == 8 ? dispatch_seg<kI32, 8>(a, w, uni_len)
+                                 : dispatch_seg<kI32, 4>(a, w, uni_len);
         default:
-            return a.leaf_k == 8 ? dispatch_seg<kF32, 8>(a, wk, wv, st, lists, uni_len)
-                                 : dispatch_seg<kF32, 4>(a, wk, wv, st, lists, uni_len);
+            return a.leaf_k == 8 ? dispatch_seg<kF32, 8>(a, w, uni_len)
+                                 : dispatch_seg<kF32, 4>(a, w, uni_len);
     }
 }
 

@@ -116,13 +116,23 @@ def test_networks_exhaustive_on_gpu(leaf):
         assert np.array_equal(host(po), refp), tun
 
 
-def test_equal_rows_without_offsets(orc):
-    rows, cols = 37, 3000
-    x = seg_keys(rows * cols, "u32", seed=3)
-    off = (np.arange(rows + 1) * cols).astype(np.uint32)
-    say("segmented equal rows (offsets=None)")
-    y = msn.segmented_sort(gpu(x), None, num_segments=rows)
-    assert np.array_equal(host(y), orc.segmented_sort(x, off, dtype="u32"))
+@pytest.mark.parametrize("leaf", ["6To8", "3To5"])
+def test_equal_rows_without_offsets(orc, leaf):
+    # one workgroup per row, tiled rows of two to five tiles (one to three
+    # merge passes, their count known on the host), and rows past the tiled
+    # limit
+    for rows, cols in ((37, 3000), (9, 20000), (5, 70000)):
+        x = seg_keys(rows * cols, "u32", seed=3 + cols)
+        off = (np.arange(rows + 1) * cols).astype(np.uint32)
+        say(f"segmented equal rows (offsets=None) leaf={leaf} rows={rows} cols={cols}")
+        y = msn.segmented_sort(gpu(x), None, num_segments=rows, leaf=leaf)
+        assert np.array_equal(host(y), orc.segmented_sort(x, off, dtype="u32", config=leaf))
+        say(f"segmented equal rows argsort leaf={leaf} rows={rows} cols={cols}")
+        yk, yp = msn.segmented_sort(gpu(x), None, num_segments=rows, leaf=leaf, argsort=True)
+        rk, rp = orc.segmented_sort(x, off, dtype="u32", config=leaf, stable=True,
+                                    want_perm=True)
+        assert np.array_equal(host(yk), rk)
+        assert np.array_equal(host(yp).view(np.uint32), rp)
 
 
 def test_only_empty_and_tiny_segments(orc):
