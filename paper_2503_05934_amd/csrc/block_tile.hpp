@@ -42,8 +42,9 @@ struct TileTraits {
 // (key, position) composites; VM selects the payload: vout[i] = vin[p(i)]
 // (kVals) or val_base + p(i) (kArg), p(i) = tile position of output i.  Float
 // keys are copied bit for bit from the input.  All threads of the workgroup
-// must call this (it contains barriers).  vec: kin/kout/vin/vout are 16-byte
-// aligned.  kout may equal kin (and vout vin): each position is read and
+// must call this (it contains barriers).  Full groups of four keys move as
+// 16-byte accesses at any word alignment.  kout may equal kin (and vout vin):
+// each position is read and
 // written only by its owning thread, or read before a barrier that precedes
 // every write.
 // Records the chunk samples among a thread's outputs x[0..N) at tile
@@ -66,7 +67,7 @@ __device__ __forceinline__ void write_samples(const Samples& samp, int first, in
 template <int DT, int K, bool STABLE, int VM, int SHAPE = 0, bool WIDE = false>
 __device__ __forceinline__ void block_sort_tile(const uint32_t* kin, const uint32_t* vin,
                                                 uint32_t* kout, uint32_t* vout, int nv,
-                                                uint32_t val_base, void* smem, bool vec,
+                                                uint32_t val_base, void* smem,
                                                 Samples samp = Samples{nullptr, nullptr, 0}) {
     using Tr = TileTraits<DT, K, STABLE, SHAPE>;
     using T = typename Tr::T;
@@ -77,10 +78,10 @@ __device__ __forceinline__ void block_sort_tile(const uint32_t* kin, const uint3
     const int first = tid * KPL;
 
     uint32_t x[KPL];
-    if (vec && first + KPL <= nv) {
+    if (first + KPL <= nv) {
 #pragma unroll
         for (int q = 0; q < KPL / 4; ++q) {
-            const uint4 w = *reinterpret_cast<const uint4*>(kin + first + 4 * q);
+            const uint4 w = ld4(kin + first + 4 * q);
             x[4 * q + 0] = w.x;
             x[4 * q + 1] = w.y;
             x[4 * q + 2] = w.z;
@@ -113,11 +114,11 @@ __device__ __forceinline__ void block_sort_tile(const uint32_t* kin, const uint3
 #pragma unroll
             for (int j = 0; j < MK; ++j) y[j] = unord_key<DT>(o[j]);
             write_samples(samp, first2, nv, y);
-            if (vec && first2 + MK <= nv) {
+            if (first2 + MK <= nv) {
 #pragma unroll
                 for (int q = 0; q < MK / 4; ++q)
-                    *reinterpret_cast<uint4*>(kout + first2 + 4 * q) =
-                        make_uint4(y[4 * q], y[4 * q + 1], y[4 * q + 2], y[4 * q + 3]);
+                    st4(kout + first2 + 4 * q, y[4 * q], y[4 * q + 1], y[4 * q + 2],
+                    y[4 * q + 3]);
             } else {
 #pragma unroll
                 for (int j = 0; j < MK; ++j)
@@ -129,11 +130,11 @@ __device__ __forceinline__ void block_sort_tile(const uint32_t* kin, const uint3
 #pragma unroll
         for (int j = 0; j < KPL; ++j) x[j] = unord_key<DT>(v[j]);
         write_samples(samp, first, nv, x);
-        if (vec && first + KPL <= nv) {
+        if (first + KPL <= nv) {
 #pragma unroll
             for (int q = 0; q < KPL / 4; ++q)
-                *reinterpret_cast<uint4*>(kout + first + 4 * q) =
-                    make_uint4(x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3]);
+                st4(kout + first + 4 * q, x[4 * q], x[4 * q + 1], x[4 * q + 2],
+                    x[4 * q + 3]);
         } else {
 #pragma unroll
             for (int j = 0; j < KPL; ++j)
@@ -166,14 +167,14 @@ __device__ __forceinline__ void block_sort_tile(const uint32_t* kin, const uint3
             else y[j] = val_base + t;
         }
         write_samples(samp, first, nv, x);
-        if (vec && first + KPL <= nv) {
+        if (first + KPL <= nv) {
 #pragma unroll
             for (int q = 0; q < KPL / 4; ++q) {
-                *reinterpret_cast<uint4*>(kout + first + 4 * q) =
-                    make_uint4(x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3]);
+                st4(kout + first + 4 * q, x[4 * q], x[4 * q + 1], x[4 * q + 2],
+                    x[4 * q + 3]);
                 if constexpr (VM != kNoVals)
-                    *reinterpret_cast<uint4*>(vout + first + 4 * q) =
-                        make_uint4(y[4 * q], y[4 * q + 1], y[4 * q + 2], y[4 * q + 3]);
+                    st4(vout + first + 4 * q, y[4 * q], y[4 * q + 1], y[4 * q + 2],
+                    y[4 * q + 3]);
             }
         } else {
 #pragma unroll

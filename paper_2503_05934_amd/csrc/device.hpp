@@ -51,6 +51,21 @@ __device__ __forceinline__ uint32_t unord_key(uint32_t o) {
     return o;
 }
 
+// ------------------------------------------------------ 16-byte access ---
+// Four consecutive words at any 4-byte-aligned address in one 16-byte load or
+// store: gfx950 code objects run with unaligned multi-dword access enabled,
+// so a tile that starts at any word of an array still moves 16 bytes per
+// lane and instruction.
+typedef uint32_t u32x4_w __attribute__((ext_vector_type(4), aligned(4)));
+__device__ __forceinline__ uint4 ld4(const uint32_t* p) {
+    const u32x4_w r = *reinterpret_cast<const u32x4_w*>(p);
+    return make_uint4(r.x, r.y, r.z, r.w);
+}
+__device__ __forceinline__ void st4(uint32_t* p, uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+    const u32x4_w w = {a, b, c, d};
+    *reinterpret_cast<u32x4_w*>(p) = w;
+}
+
 // ------------------------------------------------------ streaming access ---
 // Global loads and stores with the nontemporal hint, for the binary merge of
 // key-value pairs: each 64-lane load row and 16-byte-per-lane store row there

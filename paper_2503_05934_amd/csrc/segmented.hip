@@ -375,17 +375,13 @@ __device__ void big_task(const uint32_t* kin, const uint32_t* vin, uint32_t* kou
     uint32_t* kb[2] = {kout + off, wk + off};
     uint32_t* vb[2] = {VM != kNoVals ? vout + off : nullptr, VM != kNoVals ? wv + off : nullptr};
     int cur = passes & 1;
-    auto al = [](const void* p) { return ((uintptr_t)p & 15u) == 0; };
-    const bool vec = al(kin + off) && al(kb[0]) && al(kb[1]) &&
-                     (VM == kNoVals || (al(vb[0]) && al(vb[1]))) &&
-                     (VM != kVals || al(vin + off));
     for (int c = 0; c < chunks; ++c) {
         const int nv = min(kTile, len - c * kTile);
         block_sort_tile<DT, K, STABLE, VM>(kin + off + c * kTile,
                                            VM == kVals ? vin + off + c * kTile : nullptr,
                                            kb[cur] + c * kTile,
                                            VM != kNoVals ? vb[cur] + c * kTile : nullptr, nv,
-                                           (uint32_t)(c * kTile), smem, vec);
+                                           (uint32_t)(c * kTile), smem);
         __syncthreads();
     }
     for (int p = 0; p < passes; ++p) {
@@ -420,30 +416,26 @@ template <int DT, int K, bool STABLE, int VM>
 __global__ __launch_bounds__(kBlockThreads, STABLE ? 4 : 6) void k_segmented(
     const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, uint32_t* wk,
     uint32_t* wv, const uint32_t* __restrict__ offsets, int64_t num_segments, uint32_t uni_len,
-    SegState* st, const uint32_t* __restrict__ lists, const uint2* __restrict__ tiles) {
+    SegState* st, const uint32_t* __restrict__ lists) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t s_item;
     const int tid = threadIdx.x;
-    constexpr int kTile = TileTraits<DT, K, STABLE>::kTile;
 
     const uint32_t n_lane = st->count[kCLane];
     const uint32_t n_wave = st->count[kCWave];
     const uint32_t n_block = st->count[kCBlock];
     const uint32_t n_big = st->count[kCBig];
-    const uint32_t n_tiles = st->tiles;
     constexpr uint32_t kWavesPerBlock = kBlockThreads / kWave;
     const uint32_t wave_items = (n_wave + kWavesPerBlock - 1) / kWavesPerBlock;
     const uint32_t lane_items = (n_lane + kBlockThreads - 1) / kBlockThreads;
-    // queue order: big segments, tiles of tiled segments, block, wave items,
-    // lane items
+    // queue order: big segments, block, wave items, lane items (the tiles of
+    // tiled segments have a launch of their own)
     const uint32_t e0 = n_big;
-    const uint32_t e1 = e0 + n_tiles;
-    const uint32_t e2 = e1 + n_block;
+    const uint32_t e2 = e0 + n_block;
     const uint32_t e3 = e2 + wave_items;
     const uint32_t e4 = e3 + lane_items;
     const uint32_t* L = lists;
     const int64_t S = num_segments;
-    auto al = [](const void* p) { return ((uintptr_t)p & 15u) == 0; };
 
     for (;;) {
         if (tid == 0) s_item = atomicAdd(&st->head, 1u);
@@ -455,32 +447,12 @@ __global__ __launch_bounds__(kBlockThreads, STABLE ? 4 : 6) void k_segmented(
             uint32_t off, len;
             seg_bounds(offsets, L[kCBig * S + item], uni_len, off, len);
             big_task<DT, K, STABLE, VM>(kin, vin, kout, vout, wk, wv, off, (int)len, smem);
-        } else if (item < e1) {
-            // one tile of a tiled segment, written where its first merge pass
-            // reads it (the output itself when the segment has one tile)
-            const uint2 tc = tiles[item - e0];
-            uint32_t off, len;
-            seg_bounds(offsets, tc.x, uni_len, off, len);
-            const int passes = seg_passes((len + kTile - 1) / kTile);
-            const uint32_t first = tc.y * (uint32_t)kTile;
-            const int nv = min(kTile, (int)(len - first));
-            uint32_t* kd = ((passes & 1) ? wk : kout) + off + first;
-            uint32_t* vd =
-                VM != kNoVals ? ((passes & 1) ? wv : vout) + off + first : nullptr;
-            const uint32_t* ks = kin + off + first;
-            const uint32_t* vs = VM == kVals ? vin + off + first : nullptr;
-            const bool vec = al(ks) && al(kd) && (VM == kNoVals || al(vd)) &&
-                             (VM != kVals || al(vs));
-            block_sort_tile<DT, K, STABLE, VM>(ks, vs, kd, vd, nv, first, smem, vec);
         } else if (item < e2) {
             uint32_t off, len;
-            seg_bounds(offsets, L[kCBlock * S + (item - e1)], uni_len, off, len);
-            const bool vec = al(kin + off) && al(kout + off) &&
-                             (VM == kNoVals || al(vout + off)) &&
-                             (VM != kVals || al(vin + off));
+            seg_bounds(offsets, L[kCBlock * S + (item - e0)], uni_len, off, len);
             block_sort_tile<DT, K, STABLE, VM>(kin + off, VM == kVals ? vin + off : nullptr,
                                                kout + off, VM != kNoVals ? vout + off : nullptr,
-                                               (int)len, 0u, smem, vec);
+                                               (int)len, 0u, smem);
         } else if (item < e3) {
             const uint32_t w = (uint32_t)tid / kWave;
             const uint32_t idx = (item - e2) * kWavesPerBlock + w;
@@ -499,6 +471,36 @@ __global__ __launch_bounds__(kBlockThreads, STABLE ? 4 : 6) void k_segmented(
                 lane_task<DT, K, STABLE, VM>(kin, vin, kout, vout, off, (int)len);
             }
         }
+    }
+}
+
+// ---------------------------------------------- sorts, tiled path ---
+// The tiles of the tiled segments, workgroups taking list entries in turn:
+// the flat sort's block sort (32 outputs per thread in its LDS levels for
+// keys-only tiles, its own register budget), each tile written where its
+// segment's first merge pass reads it (the output itself for one tile).
+template <int DT, int K, bool STABLE, int VM>
+__global__ __launch_bounds__(kBlockThreads, (TileTraits<DT, K, STABLE>::kWavesPerSimd))
+void k_seg_tile_sort(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
+                     uint32_t* wk, uint32_t* wv, const uint32_t* __restrict__ offsets,
+                     uint32_t uni_len, const SegState* st, const uint2* __restrict__ tiles) {
+    using Tr = TileTraits<DT, K, STABLE>;
+    __shared__ __align__(16) unsigned char smem[Tr::kLdsBytes];
+    constexpr int kTile = Tr::kTile;
+    const uint32_t n = st->tiles;
+    for (uint32_t e = blockIdx.x; e < n; e += gridDim.x) {
+        const uint2 tc = tiles[e];
+        uint32_t off, len;
+        seg_bounds(offsets, tc.x, uni_len, off, len);
+        const int passes = seg_passes((len + kTile - 1) / kTile);
+        const uint32_t first = tc.y * (uint32_t)kTile;
+        const int nv = min(kTile, (int)(len - first));
+        uint32_t* kd = ((passes & 1) ? wk : kout) + off + first;
+        uint32_t* vd = VM != kNoVals ? ((passes & 1) ? wv : vout) + off + first : nullptr;
+        const uint32_t* ks = kin + off + first;
+        const uint32_t* vs = VM == kVals ? vin + off + first : nullptr;
+        block_sort_tile<DT, K, STABLE, VM, 0, true>(ks, vs, kd, vd, nv, first, smem);
+        __syncthreads();  // the next tile reuses the LDS
     }
 }
 
@@ -619,11 +621,29 @@ int launch_seg_kernel(const SegArgs& a, const SegWs& w, uint32_t uni_len) {
         static int cached = 0;
         if (int rc = fill_grid(kern, kBlockThreads, Tr::kLds, &cached, &grid)) return rc;
     }
+    // equal-length segments: the host knows their class and pass count
+    bool any_tiled = true;
+    int npass = kSegTiledPasses;
+    if (!a.offsets) {
+        const int64_t len = uni_len;
+        any_tiled = len > a.block_max && len <= (int64_t)kSegTiledMax * kTile;
+        npass = any_tiled ? seg_passes((uint32_t)((len + kTile - 1) / kTile)) : 0;
+    }
+    if (any_tiled) {
+        auto skern = &k_seg_tile_sort<DT, K, STABLE, VM>;
+        int sgrid = 0;
+        static int cached_s = 0;
+        if (int rc = fill_grid(skern, kBlockThreads, 0, &cached_s, &sgrid)) return rc;
+        LaunchTimer timer("seg_tile_sort", a.n_total, a.stream);
+        hipLaunchKernelGGL(skern, dim3(sgrid), dim3(kBlockThreads), 0, a.stream, a.kin, a.vin,
+                           a.kout, a.vout, w.wk, w.wv, a.offsets, uni_len, w.st, w.tiles);
+    }
+    if (int rc = (int)hipGetLastError()) return rc;
     {
         LaunchTimer timer("segmented", a.n_total, a.stream);
         hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlockThreads), Tr::kLds, a.stream, a.kin,
                            a.vin, a.kout, a.vout, w.wk, w.wv, a.offsets, a.num_segments, uni_len,
-                           w.st, w.lists, w.tiles);
+                           w.st, w.lists);
     }
     if (int rc = (int)hipGetLastError()) return rc;
     // merge passes of the tiled segments (none of them when the list is empty)
@@ -636,13 +656,6 @@ int launch_seg_kernel(const SegArgs& a, const SegWs& w, uint32_t uni_len) {
         if (int rc = fill_grid(mkern, kBlockThreads, mlds, &cached, &mgrid)) return rc;
     }
     const unsigned pgrid = (unsigned)((w.max_tiles + 255) / 256);
-    // equal-length segments: the host knows their class and pass count
-    int npass = kSegTiledPasses;
-    if (!a.offsets) {
-        const int64_t len = uni_len;
-        const bool tiled = len > a.block_max && len <= (int64_t)kSegTiledMax * kTile;
-        npass = tiled ? seg_passes((uint32_t)((len + kTile - 1) / kTile)) : 0;
-    }
     for (int p = 0; p < npass; ++p) {
         {
             LaunchTimer timer("seg_tile_part", a.n_total, a.stream);

@@ -14,7 +14,7 @@ template <int DT, int K, bool STABLE, int VM, int SHAPE>
 __global__ __launch_bounds__((TileTraits<DT, K, STABLE, SHAPE>::kThreads),
                              (TileTraits<DT, K, STABLE, SHAPE>::kWavesPerSimd)) void k_block_sort(
     const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, int64_t n,
-    int vec, uint32_t* samp_first, uint32_t* samp_last) {
+    uint32_t* samp_first, uint32_t* samp_last) {
     // static LDS (gfx950 allows up to 160 KiB): its base is a compile-time
     // constant that the padded-slot address math folds away
     __shared__ __align__(16) unsigned char smem[TileTraits<DT, K, STABLE, SHAPE>::kLdsBytes];
@@ -23,7 +23,7 @@ __global__ __launch_bounds__((TileTraits<DT, K, STABLE, SHAPE>::kThreads),
     const int nv = (int)((n - base) < kTile ? (n - base) : kTile);
     block_sort_tile<DT, K, STABLE, VM, SHAPE, true>(kin + base, VM == kVals ? vin + base : nullptr,
                                              kout + base, VM != kNoVals ? vout + base : nullptr,
-                                             nv, (uint32_t)base, smem, vec != 0,
+                                             nv, (uint32_t)base, smem,
                                              Samples{samp_first, samp_last, base});
 }
 
@@ -205,7 +205,7 @@ int ensure_lds(Kern kern, size_t bytes) {
 }
 
 template <int DT, int K, bool STABLE, int VM, int SHAPE = 0>
-int launch_block_sort(const SortArgs& a, uint32_t* kdst, uint32_t* vdst, int vec,
+int launch_block_sort(const SortArgs& a, uint32_t* kdst, uint32_t* vdst,
                       const Samples& sm) {
     using Tr = TileTraits<DT, K, STABLE, SHAPE>;
     auto kern = &k_block_sort<DT, K, STABLE, VM, SHAPE>;
@@ -213,7 +213,7 @@ int launch_block_sort(const SortArgs& a, uint32_t* kdst, uint32_t* vdst, int vec
     {
         LaunchTimer timer("block_sort", a.n, a.stream);
         hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(Tr::kThreads), 0, a.stream, a.kin,
-                           a.vin, kdst, vdst, a.n, vec, sm.first, sm.last);
+                           a.vin, kdst, vdst, a.n, sm.first, sm.last);
     }
     return (int)hipGetLastError();
 }
@@ -227,17 +227,17 @@ inline int block_shape(const SortArgs& a) {
 }
 
 template <int DT, int K>
-int dispatch_block_sort(const SortArgs& a, uint32_t* kdst, uint32_t* vdst, int vec,
+int dispatch_block_sort(const SortArgs& a, uint32_t* kdst, uint32_t* vdst,
                         const Samples& sm) {
-    if (a.vmode == kVals) return launch_block_sort<DT, K, true, kVals>(a, kdst, vdst, vec, sm);
-    if (a.vmode == kArg) return launch_block_sort<DT, K, true, kArg>(a, kdst, vdst, vec, sm);
+    if (a.vmode == kVals) return launch_block_sort<DT, K, true, kVals>(a, kdst, vdst, sm);
+    if (a.vmode == kArg) return launch_block_sort<DT, K, true, kArg>(a, kdst, vdst, sm);
     if constexpr (DT == kF32) {
-        return launch_block_sort<DT, K, true, kNoVals>(a, kdst, vdst, vec, sm);
+        return launch_block_sort<DT, K, true, kNoVals>(a, kdst, vdst, sm);
     } else {
         switch (block_shape(a)) {
-            case 1: return launch_block_sort<DT, K, false, kNoVals, 1>(a, kdst, vdst, vec, sm);
-            case 2: return launch_block_sort<DT, K, false, kNoVals, 2>(a, kdst, vdst, vec, sm);
-            default: return launch_block_sort<DT, K, false, kNoVals, 0>(a, kdst, vdst, vec, sm);
+            case 1: return launch_block_sort<DT, K, false, kNoVals, 1>(a, kdst, vdst, sm);
+            case 2: return launch_block_sort<DT, K, false, kNoVals, 2>(a, kdst, vdst, sm);
+            default: return launch_block_sort<DT, K, false, kNoVals, 0>(a, kdst, vdst, sm);
         }
     }
 }
@@ -379,8 +379,8 @@ int run_sort(const SortArgs& a) {
                                (a.vmode != kVals || aligned(a.vin))));
 
     int cur = passes & 1;
-    int rc = a.leaf_k == 8 ? dispatch_block_sort<DT, 8>(a, kb[cur], vb[cur], vec, sm)
-                           : dispatch_block_sort<DT, 4>(a, kb[cur], vb[cur], vec, sm);
+    int rc = a.leaf_k == 8 ? dispatch_block_sort<DT, 8>(a, kb[cur], vb[cur], sm)
+                           : dispatch_block_sort<DT, 4>(a, kb[cur], vb[cur], sm);
     if (rc) return rc;
     int64_t L = tile;
     for (int p = 0; p < passes; ++p) {
