@@ -62,6 +62,12 @@ size_t seg_ws_bytes(int64_t n_total, int64_t num_segments, bool vals) {
            align_up(mt * 8, 256) + align_up(mt * 4, 256);
 }
 
+// LDS words of one merge tile of t outputs (keys or values): the tile, the
+// two runs' sentinels and a dummy slot, padded.
+__host__ __device__ constexpr int seg_merge_words(int t) {
+    return lds_words<uint32_t>(t + 2 * (t / kBlockThreads) + 1);
+}
+
 // Merge passes of a segment of `tiles` block-sort tiles: ceil(log2(tiles)).
 __host__ __device__ inline int seg_passes(uint32_t tiles) {
     int p = 0;
@@ -260,7 +266,7 @@ __device__ __forceinline__ int corank_global(const uint32_t* A, int la, const ui
 // One output tile of a merge pass, by one workgroup: outputs [d0, d1) of the
 // stable merge of A = ks[base, base + la) and B = ks[base + la, base + la +
 // lb) (segment positions), A contributing [i0, i1); they land at kd[base +
-// d0 ...].  sk/sv: LDS of lds_words(KPT * kBlockThreads) words each.
+// d0 ...].  sk/sv: LDS of seg_merge_words(KPT * kBlockThreads) words each.
 template <int DT, bool VALS, int KPT>
 __device__ __forceinline__ void seg_merge_tile(const uint32_t* ks, const uint32_t* vs,
                                                uint32_t* kd, uint32_t* vd, int base, int la,
@@ -271,6 +277,55 @@ __device__ __forceinline__ void seg_merge_tile(const uint32_t* ks, const uint32_
     const int cnt = d1 - d0;
     const int nb = cnt - na;
     const int j0 = d0 - i0;
+    if constexpr (!VALS && DT != kF32) {
+        // integer keys alone: both pieces closed by KPT maxima in LDS (B
+        // starts KPT past A's end), so the sequential merge checks no bounds;
+        // equal keys may come from either piece, which keys alone cannot show
+        using Key = std::conditional_t<DT == kI32, int32_t, uint32_t>;
+        constexpr Key kMax = DT == kI32 ? (Key)0x7fffffff : (Key)0xffffffffu;
+        constexpr int kDummy = KPT * kBlockThreads + 2 * KPT;
+        Key* s = reinterpret_cast<Key*>(sk);
+        const int b0 = na + KPT;
+        Key r[KPT];
+#pragma unroll
+        for (int q = 0; q < KPT; ++q) {
+            const int x = min(tid + q * kBlockThreads, cnt - 1);
+            r[q] = (Key)ks[x < na ? base + i0 + x : base + la + j0 + (x - na)];
+        }
+#pragma unroll
+        for (int q = 0; q < KPT; ++q) {
+            const int x = tid + q * kBlockThreads;
+            s[lds_idx<Key>(x < na ? x : (x < cnt ? x + KPT : kDummy))] = r[q];
+        }
+        if (tid < KPT) {
+            s[lds_idx<Key>(na + tid)] = kMax;
+            s[lds_idx<Key>(b0 + nb + tid)] = kMax;
+        }
+        __syncthreads();
+        const int d = tid * KPT;
+        Key o[KPT];
+        if (d < cnt) {
+            const int i = corank_lds(s, 0, na, b0, nb, d, PlainLess{});
+            serial_merge_closed<Key, KPT>(s, i, b0 + d - i, o);
+        }
+        __syncthreads();
+        if (d < cnt) {
+#pragma unroll
+            for (int k = 0; k < KPT; ++k) {
+                const int e = d + k;
+                if (e < cnt) sk[e + (e >> 5)] = (uint32_t)o[k];
+            }
+        }
+        __syncthreads();
+        uint32_t* kr = kd + base + d0;
+#pragma unroll
+        for (int q = 0; q < KPT; ++q) {
+            const int e = tid + q * kBlockThreads;
+            if (e < cnt) kr[e] = sk[e + (e >> 5)];
+        }
+        __syncthreads();
+        return;
+    }
     {
         uint32_t rk[KPT], rv[KPT];
 #pragma unroll
@@ -336,7 +391,7 @@ __device__ void wg_merge_pass(const uint32_t* ks, const uint32_t* vs, uint32_t* 
                               int len, int L, void* smem) {
     int32_t* sb = reinterpret_cast<int32_t*>(smem);
     uint32_t* sk = reinterpret_cast<uint32_t*>(sb + kSegBoundWords);
-    uint32_t* sv = sk + lds_words<uint32_t>(kSegMergeTile);
+    uint32_t* sv = sk + seg_merge_words(kSegMergeTile);
     const int tid = threadIdx.x;
     const int ntiles = (len + kSegMergeTile - 1) / kSegMergeTile;
     for (int t0 = 0; t0 < ntiles; t0 += kBlockThreads) {
@@ -400,7 +455,7 @@ struct SegTraits {
         STABLE ? (size_t)(kBlockThreads / kWave) * 2 * kWave * keys_per_lane<K>() * 4 : 0;
     static constexpr size_t kMergeLds =
         (size_t)kSegBoundWords * 4 +
-        (size_t)lds_words<uint32_t>(kSegMergeTile) * 4 * (VM != kNoVals ? 2 : 1);
+        (size_t)seg_merge_words(kSegMergeTile) * 4 * (VM != kNoVals ? 2 : 1);
     static constexpr size_t kLds = kTileLds > kWaveLds
                                        ? (kTileLds > kMergeLds ? kTileLds : kMergeLds)
                                        : (kWaveLds > kMergeLds ? kWaveLds : kMergeLds);
@@ -557,16 +612,18 @@ __global__ __launch_bounds__(256) void k_seg_tile_part(
     part[e] = corank_global<DT>(g.ks + g.base, g.la, g.ks + g.base + g.la, g.lb, g.d0);
 }
 
-// The output tiles of pass p, workgroups taking list entries in turn.
+// The output tiles of pass p, workgroups taking list entries in turn.  The
+// integer kernels are held to three workgroups per compute unit (84 VGPRs,
+// which they fit without spilling); the float ones would spill.
 template <int DT, bool VALS, int KPT>
-__global__ __launch_bounds__(kBlockThreads) void k_seg_tile_merge(
+__global__ __launch_bounds__(kBlockThreads, DT == kF32 ? 1 : 6) void k_seg_tile_merge(
     uint32_t* kout, uint32_t* vout, uint32_t* wk, uint32_t* wv,
     const uint32_t* __restrict__ offsets, uint32_t uni_len, const SegState* st,
     const uint2* __restrict__ tiles, const int32_t* __restrict__ part, int p) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int kTile = KPT * kBlockThreads;
     uint32_t* sk = reinterpret_cast<uint32_t*>(smem);
-    uint32_t* sv = sk + lds_words<uint32_t>(kTile);
+    uint32_t* sv = sk + seg_merge_words(kTile);
     const uint32_t n = st->tiles;
     for (uint32_t e = blockIdx.x; e < n; e += gridDim.x) {
         SegTilePass g;
@@ -648,7 +705,7 @@ int launch_seg_kernel(const SegArgs& a, const SegWs& w, uint32_t uni_len) {
     if (int rc = (int)hipGetLastError()) return rc;
     // merge passes of the tiled segments (none of them when the list is empty)
     auto mkern = &k_seg_tile_merge<DT, kVals, kKpt>;
-    const size_t mlds = (size_t)lds_words<uint32_t>(kTile) * 4 * (kVals ? 2 : 1);
+    const size_t mlds = (size_t)seg_merge_words(kTile) * 4 * (kVals ? 2 : 1);
     if (int rc = set_dynamic_lds(reinterpret_cast<const void*>(mkern), mlds)) return rc;
     int mgrid = 0;
     {
