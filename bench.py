@@ -393,6 +393,15 @@ def bench_segmented(args):
     base_wall = time.perf_counter() - t0
     if not torch.equal(out, out2):
         raise SystemExit("[bench] per-array baseline disagrees with the segmented sort")
+    # the dominant kernel: the block sort of every tile of the segments that
+    # take the tiled path (longer than seg_block_max, at most 8 tiles)
+    lens = (off_np[1:] - off_np[:-1]).astype(np.int64)
+    kk_ = 8 if args.leaf == "6To8" else 4
+    bmax = (tuning or {}).get("seg_block_max") or 1024 * kk_
+    tiled = int(lens[(lens > bmax) & (lens <= 8 * 1024 * kk_)].sum())
+    seg_roof = _roof(stats, "seg_tile_sort", lambda m: 8.0 * tiled) if tiled else None
+    if seg_roof:
+        seg_roof["kernel"] = "k_seg_tile_sort (every tile of the tiled segments, one launch)"
     return {
         "metric": "Gkeys/s, batched segmented sort: 100,000 int32 arrays, lengths log-uniform "
                   "in [3, 65536], 30% presorted, 1 GPU",
@@ -406,7 +415,7 @@ def bench_segmented(args):
                                "gkeys_per_s": n / (base_ms / 1e3) / 1e9,
                                "how": "one msn_sort_keys call per segment, eager, same GPU"},
         "speedup_vs_per_array": base_ms / ms,
-        "roofline": _roof(stats, "segmented", lambda m: 8.0 * n),
+        "roofline": seg_roof,
         "kernels_ms_per_step": {kk: vv["total_ms"] / args.steps for kk, vv in stats.items()},
     }
 
