@@ -774,19 +774,25 @@ __global__ __launch_bounds__(THREADS) void k_merge4(const uint32_t* __restrict__
 // the stable order and the merge levels need no tie rule.  Values stay in
 // registers until the merge is done; then they are written to LDS by tile
 // position, gathered through the positions the composites carry, staged with
-// the keys and stored as rows.  MK = 16 outputs per thread of each level.
-constexpr int kM4pSent = 16;
+// the keys and stored as rows.  Each level gives m4p_mk(threads) outputs to
+// each merging thread (16 for 1024-thread tiles, which hold them in 64
+// VGPRs; 32 for 512-thread tiles).
+__host__ __device__ constexpr int m4p_mk(int threads) { return threads >= 1024 ? 16 : 32; }
 // Staged keys: every output a thread holds (up to MK - 1 past the tile end),
 // a spare word every 32; the staged values follow.
-constexpr int kM4pStage = kM4MaxTile + kM4pSent + (kM4MaxTile + kM4pSent) / 32 + 8;
+__host__ __device__ constexpr int m4p_stage(int mk) {
+    return kM4MaxTile + mk + (kM4MaxTile + mk) / 32 + 8;
+}
 // LDS: the padded composite buffer (slices kM4Gap apart, or X and Y), or the
 // values by tile position, or the staged keys and values (read back as rows
 // of `threads` words, the last row partly past the tile).
 __host__ __device__ constexpr int m4p_lds_bytes(int threads) {
     return 8 * lds_words<uint64_t>(kM4MaxTile + 4 * kM4Gap + 8) >
-                   4 * (kM4pStage + m4_out_rows(threads) * threads + m4_out_rows(threads) * threads / 32)
+                   4 * (m4p_stage(m4p_mk(threads)) + m4_out_rows(threads) * threads +
+                        m4_out_rows(threads) * threads / 32)
                ? 8 * lds_words<uint64_t>(kM4MaxTile + 4 * kM4Gap + 8)
-               : 4 * (kM4pStage + m4_out_rows(threads) * threads + m4_out_rows(threads) * threads / 32);
+               : 4 * (m4p_stage(m4p_mk(threads)) + m4_out_rows(threads) * threads +
+                      m4_out_rows(threads) * threads / 32);
 }
 
 template <int DT, int THREADS, int KPT>
@@ -796,7 +802,7 @@ __global__ __launch_bounds__(THREADS) void k_merge4_pairs(
     M4Geom g4, uint32_t* __restrict__ samp_first, uint32_t* __restrict__ samp_last) {
     static_assert(DT == kU32 || DT == kI32, "integer keys only");
     static_assert(kM4MaxTile <= THREADS * KPT, "tile fits");
-    constexpr int MK = kM4pSent;
+    constexpr int MK = m4p_mk(THREADS);
     static_assert(kM4MaxTile / MK + 2 <= THREADS && kM4Gap >= MK, "merge shape");
     constexpr uint64_t kMaxC = ~0ull;
     __shared__ __align__(16) unsigned char smem[m4p_lds_bytes(THREADS)];
@@ -941,7 +947,7 @@ __global__ __launch_bounds__(THREADS) void k_merge4_pairs(
     }
     // stage keys, then values (a spare word every 32), and store rows
     uint32_t* stk = w32;
-    uint32_t* stv = w32 + kM4pStage;
+    uint32_t* stv = w32 + m4p_stage(MK);
     __syncthreads();
     if (d < cnt) {
 #pragma unroll
