@@ -1,21 +1,23 @@
-// Batched (segmented) sort: many independent arrays of uneven length in one
-// persistent kernel launch.  Algorithm 1 of the paper (Sec. 3) is applied to
+// Batched (segmented) sort: many independent arrays of uneven length in a
+// fixed sequence of launches that never reads the offsets on the host (so a
+// graph can capture it).  Algorithm 1 of the paper (Sec. 3) is applied to
 // every segment; the work unit is chosen by segment length:
 //   lane   (<= lane_max keys, at most one leaf): one lane, one network with
 //          padding -- the role of the paper's variable-size networks
 //          (Table 3, VarSort);
 //   wave   (<= wave_max): one wavefront, networks + bitonic merges;
 //   block  (<= block_max): one workgroup, network + bitonic + LDS merges;
-//   tiled  (up to kSegTiledMax tiles): every tile is a work item of its own
-//          (one workgroup sorts it), then up to three merge passes over all
-//          such segments at once, one workgroup per output tile;
+//   tiled  (up to kSegTiledMax block-sort tiles): every tile is a work item
+//          of its own (k_seg_tile_sort), then up to three merge passes over
+//          all such segments at once, one workgroup per output tile
+//          (k_seg_tile_part, then k_seg_tile_merge);
 //   big    (longer): one workgroup sorts the segment's tiles in turn and then
 //          merges them pass by pass through global memory.
-// A binning launch sorts segment ids into per-class lists (and the tiles of
-// tiled segments into a tile list); the persistent launch then pulls work
-// items (big segments first) from one atomic counter until the lists are
-// exhausted.  No workgroup ever waits for another, so any grid size
-// terminates.  The tiled segments' merge passes are separate launches.
+// k_seg_bin sorts segment ids into per-class lists and the tiles of tiled
+// segments into a tile list; the persistent k_segmented pulls the lane, wave,
+// block and big work items (big segments first) from one atomic counter
+// until the lists are exhausted.  No workgroup ever waits for another, so any
+// grid size terminates.
 #include "block_tile.hpp"
 
 namespace msn {
