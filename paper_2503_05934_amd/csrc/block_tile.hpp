@@ -38,6 +38,10 @@ struct TileTraits {
     static constexpr int kWavesPerSimd = kLdsWaves < 1 ? 1 : kLdsWaves > 8 ? 8 : kLdsWaves;
 };
 
+// Bits of a tile position in the 32-bit composites of stable tiles whose keys
+// all fit the remaining bits.
+constexpr int kPackPosBits = 13;
+
 // Sorts kin[0..nv) into kout[0..nv) (nv <= 2K*512).  STABLE sorts
 // (key, position) composites; VM selects the payload: vout[i] = vin[p(i)]
 // (kVals) or val_base + p(i) (kArg), p(i) = tile position of output i.  Float
@@ -64,7 +68,11 @@ __device__ __forceinline__ void write_samples(const Samples& samp, int first, in
 
 // WIDE (keys-only tiles of 16 keys per lane): LDS merge levels at 32 outputs
 // per thread; fewer co-rank searches for more live registers.
-template <int DT, int K, bool STABLE, int VM, int SHAPE = 0, bool WIDE = false>
+// PACK (stable integer tiles of 16 keys per lane): tiles whose keys all fit
+// 32 - kPackPosBits bits sort 32-bit (key, position) composites instead of
+// 64-bit ones (a run-time choice per tile).
+template <int DT, int K, bool STABLE, int VM, int SHAPE = 0, bool WIDE = false,
+          bool PACK = false>
 __device__ __forceinline__ void block_sort_tile(const uint32_t* kin, const uint32_t* vin,
                                                 uint32_t* kout, uint32_t* vout, int nv,
                                                 uint32_t val_base, void* smem,
@@ -141,12 +149,71 @@ __device__ __forceinline__ void block_sort_tile(const uint32_t* kin, const uint3
                 if (first + j < nv) kout[first + j] = x[j];
         }
     } else {
-        block_sort_regs<T, K, KPL>(v, s, span);
-        // Stage what must be gathered by position (float bits, payload).
-        uint32_t* sbits = reinterpret_cast<uint32_t*>(smem);
-        uint32_t* svals = sbits + Tr::kTile;
         constexpr bool kNeedBits = DT == kF32;
         constexpr bool kNeedVals = VM == kVals;
+        uint32_t* sbits = reinterpret_cast<uint32_t*>(smem);
+        uint32_t* svals = sbits + Tr::kTile;
+        if constexpr (PACK && DT != kF32 && KPL == 16 && Tr::kTile <= (1 << kPackPosBits)) {
+            // Every key of the tile below 2^(32 - kPackPosBits): the composite
+            // (key, position) fits 32 bits, and the tile takes the keys-only
+            // sort (32 outputs per thread in the LDS levels); keys (float
+            // bits) and payloads are then gathered by position as below.
+            uint32_t orv = 0;
+#pragma unroll
+            for (int j = 0; j < KPL; ++j) orv |= (first + j < nv) ? ord_key<DT>(x[j]) : 0u;
+            if (__syncthreads_or((int)(orv >> (32 - kPackPosBits))) == 0) {
+                constexpr int MK = 2 * KPL;
+                uint32_t w[KPL], o[MK];
+#pragma unroll
+                for (int j = 0; j < KPL; ++j)
+                    w[j] = (first + j < nv)
+                               ? (ord_key<DT>(x[j]) << kPackPosBits) | (uint32_t)(first + j)
+                               : 0xffffffffu;
+                block_sort_regs2<uint32_t, K, KPL, MK>(w, o, reinterpret_cast<uint32_t*>(smem),
+                                                       span);
+                if constexpr (kNeedBits || kNeedVals) {
+                    for (int i = tid; i < nv; i += Tr::kThreads) {
+                        if constexpr (kNeedBits) sbits[i] = kin[i];
+                        if constexpr (kNeedVals) svals[i] = vin[i];
+                    }
+                }
+                __syncthreads();
+                const int first2 = tid * MK;
+                if (first2 < span) {
+                    uint32_t kx[MK], vy[MK];
+#pragma unroll
+                    for (int j = 0; j < MK; ++j) {
+                        const uint32_t t =
+                            first2 + j < nv ? (o[j] & ((1u << kPackPosBits) - 1u)) : 0u;
+                        if constexpr (kNeedBits) kx[j] = sbits[t];
+                        else kx[j] = unord_key<DT>(o[j] >> kPackPosBits);
+                        if constexpr (VM == kVals) vy[j] = svals[t];
+                        else vy[j] = val_base + t;
+                    }
+                    write_samples(samp, first2, nv, kx);
+                    if (first2 + MK <= nv) {
+#pragma unroll
+                        for (int q = 0; q < MK / 4; ++q) {
+                            st4(kout + first2 + 4 * q, kx[4 * q], kx[4 * q + 1], kx[4 * q + 2],
+                                kx[4 * q + 3]);
+                            if constexpr (VM != kNoVals)
+                                st4(vout + first2 + 4 * q, vy[4 * q], vy[4 * q + 1],
+                                    vy[4 * q + 2], vy[4 * q + 3]);
+                        }
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < MK; ++j)
+                            if (first2 + j < nv) {
+                                kout[first2 + j] = kx[j];
+                                if constexpr (VM != kNoVals) vout[first2 + j] = vy[j];
+                            }
+                    }
+                }
+                return;
+            }
+        }
+        block_sort_regs<T, K, KPL>(v, s, span);
+        // Stage what must be gathered by position (float bits, payload).
         __syncthreads();
         if constexpr (kNeedBits || kNeedVals) {
             for (int i = tid; i < nv; i += Tr::kThreads) {

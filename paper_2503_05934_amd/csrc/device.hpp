@@ -369,15 +369,15 @@ __device__ __forceinline__ void serial_merge_closed(const T* s, int pa, int pb, 
     } else {
         // 64-bit composites: track both runs' positions (fewer live registers)
         const int sum0 = pa + pb;  // grows by one per output
-        T a = s[lds_idx<T>(pa)];
-        T b = s[lds_idx<T>(pb)];
+        T a = lds_load(s, (uint32_t)pa);
+        T b = lds_load(s, (uint32_t)pb);
 #pragma unroll
         for (int k = 0; k < N; ++k) {
             const bool take_a = !(b < a);
             out[k] = take_a ? a : b;
             pa += take_a ? 1 : 0;
             const int p = take_a ? pa : sum0 + k + 1 - pa;
-            const T x = s[lds_idx<T>(p)];
+            const T x = lds_load(s, (uint32_t)p);
             a = take_a ? x : a;
             b = take_a ? b : x;
         }

@@ -21,7 +21,7 @@ __global__ __launch_bounds__((TileTraits<DT, K, STABLE, SHAPE>::kThreads),
     constexpr int kTile = TileTraits<DT, K, STABLE, SHAPE>::kTile;
     const int64_t base = (int64_t)blockIdx.x * kTile;
     const int nv = (int)((n - base) < kTile ? (n - base) : kTile);
-    block_sort_tile<DT, K, STABLE, VM, SHAPE, true>(kin + base, VM == kVals ? vin + base : nullptr,
+    block_sort_tile<DT, K, STABLE, VM, SHAPE, true, true>(kin + base, VM == kVals ? vin + base : nullptr,
                                              kout + base, VM != kNoVals ? vout + base : nullptr,
                                              nv, (uint32_t)base, smem,
                                              Samples{samp_first, samp_last, base});
