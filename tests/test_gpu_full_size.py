@@ -1,0 +1,162 @@
+"""Parity at the full workload sizes, in the launch configurations the
+benchmark times: 2^28 uint32 keys (random, sorted, nearly sorted) through a
+SortPlan with the default tuning; 2^28 key-value pairs with keys in [0, 2^16);
+the 100,000-array batch with the default and the tuned thresholds; 4096 x 8192
+fp32 rows forward and backward.
+
+The oracle sorts a 2^28-key array in about half a minute and the batch in
+minutes, so the flat and batched sorts are checked by
+  * properties that fix the sorted result at any size, over every element
+    (order, and the multiset through a library sort or per-array hashes), and
+  * sampled outputs that the oracle computes one at a time: out[r] == v holds
+    in a sorted array exactly when #(keys < v) <= r < #(keys <= v), and in the
+    stable sort the output of original index i with key k sits at
+    #(keys < k) + #(keys[:i] == k).
+The rows are small enough for the oracle to sort whole.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2503_05934_amd as msn
+from paper_2503_05934_amd import workloads
+from gpu_util import DEV, bits, gpu, host, say
+
+pytestmark = pytest.mark.gpu
+
+N_FULL = 2**28
+
+
+@pytest.fixture(scope="module")
+def orc():
+    return oracle.load()
+
+
+def _sample_positions(n, count, seed):
+    rng = np.random.default_rng(seed)
+    return sorted({0, n // 2, n - 1, *rng.integers(0, n, count).tolist()})
+
+
+@pytest.mark.parametrize("dist", workloads.DISTRIBUTIONS)
+def test_full_keys_2p28(orc, dist):
+    say(f"full sort_keys 2^28 u32 {dist}: generating")
+    x = workloads.keys(N_FULL, dist, "u32", seed=0)
+    plan = msn.SortPlan(N_FULL, torch.uint32, DEV)
+    say(f"full sort_keys 2^28 u32 {dist}: sorting")
+    out = host(plan.run(gpu(x)))
+    torch.cuda.synchronize()
+    assert out.shape == x.shape
+    assert bool(np.all(out[1:] >= out[:-1])), "output not non-decreasing"
+    assert np.array_equal(out, np.sort(x)), "output is not the input's multiset in order"
+    for r in _sample_positions(N_FULL, 10, seed=1):
+        lt, le = orc.rank_bounds(x, out[r], dtype="u32")
+        assert lt <= r < le, f"position {r}: value {out[r]} has rank bounds [{lt}, {le})"
+
+
+def test_full_pairs_2p28(orc):
+    say("full sort_pairs 2^28 (keys < 2^16, payload = index): generating")
+    k, v = workloads.pairs(N_FULL, seed=0)
+    plan = msn.SortPlan(N_FULL, torch.uint32, DEV, pairs=True)
+    say("full sort_pairs 2^28: sorting")
+    ko_t, vo_t = plan.run(gpu(k), gpu(v))
+    ko, vo = host(ko_t), host(vo_t).view(np.uint32)
+    torch.cuda.synchronize()
+    # the stable sort is the unique arrangement with keys non-decreasing,
+    # payload (the original index) rising inside equal keys, every index once,
+    # and each key travelling with its own index
+    assert bool(np.all(ko[1:] >= ko[:-1]))
+    assert bool(np.all((ko[1:] > ko[:-1]) | (vo[1:] > vo[:-1])))
+    seen = np.bincount(vo, minlength=N_FULL)
+    assert seen.shape[0] == N_FULL and bool(np.all(seen == 1)), "payload not a permutation"
+    assert np.array_equal(k[vo], ko)
+    for r in _sample_positions(N_FULL, 6, seed=2):
+        key, idx = ko[r], int(vo[r])
+        lt, _ = orc.rank_bounds(k, key, dtype="u32")
+        lt_pre, le_pre = orc.rank_bounds(k[:idx], key, dtype="u32")
+        assert r == lt + (le_pre - lt_pre), f"position {r}: index {idx} belongs elsewhere"
+
+
+def _segment_hashes(a, starts):
+    """Per-array sum of keys and sum of a mixing of the keys (mod 2^64):
+    equal for equal multisets."""
+    u = a.astype(np.int64).view(np.uint64)
+    s1 = np.add.reduceat(u, starts, dtype=np.uint64)
+    m = (u + np.uint64(0x9E3779B97F4A7C15)) * np.uint64(0xBF58476D1CE4E5B9)
+    m ^= m >> np.uint64(31)
+    m *= np.uint64(0x94D049BB133111EB)
+    s2 = np.add.reduceat(m, starts, dtype=np.uint64)
+    return s1, s2
+
+
+def test_full_segmented_100k(orc):
+    from paper_2503_05934_amd import _lib, autotune
+
+    say("full segmented 100,000 arrays: generating")
+    x, off, _ = workloads.segments(100_000, seed=0)
+    S = off.shape[0] - 1
+    n = x.shape[0]
+    lens = np.diff(off.astype(np.int64))
+    assert lens.min() > 0
+    xg, og = gpu(x), gpu(off)
+    ws = torch.empty(_lib.segmented_workspace_bytes(n, S, 1, False), dtype=torch.uint8,
+                     device=DEV)
+    say(f"full segmented: {n} keys, default thresholds")
+    out_t = msn.segmented_sort(xg, og, workspace=ws)
+    say("full segmented: tuned thresholds")
+    tuning = autotune.tuned_segmented_params(xg, og, num_segments=S)
+    out_tuned = msn.segmented_sort(xg, og, tuning=tuning, workspace=ws)
+    assert torch.equal(out_t, out_tuned), f"thresholds {tuning} change the output"
+    assert torch.equal(og, gpu(off)), "offsets were written"
+    out = host(out_t)
+    del out_tuned
+    starts = off[:-1].astype(np.int64)
+    first = np.zeros(n, dtype=bool)
+    first[starts] = True
+    assert bool(np.all((out[1:] >= out[:-1]) | first[1:])), "an array is out of order"
+    h_in, h_out = _segment_hashes(x, starts), _segment_hashes(out, starts)
+    assert np.array_equal(h_in[0], h_out[0]) and np.array_equal(h_in[1], h_out[1]), \
+        "an array's multiset changed"
+    # whole arrays from the oracle: the longest ones, and a sample of every size class
+    rng = np.random.default_rng(3)
+    pick = set(np.argsort(lens)[-4:].tolist())
+    for lo, hi in ((3, 8), (9, 512), (513, 8192), (8193, 65536)):
+        cls = np.nonzero((lens >= lo) & (lens <= hi))[0]
+        pick.update(rng.choice(cls, size=min(8, cls.shape[0]), replace=False).tolist())
+    for s in sorted(pick):
+        a, b = int(off[s]), int(off[s + 1])
+        assert np.array_equal(out[a:b], orc.sort(x[a:b], dtype="i32")), f"array {s}"
+
+
+def test_full_rows_4096x8192(orc):
+    say("full rows 4096x8192 tiefree: generating")
+    x, g, _ = workloads.rows(4096, 8192, variant="tiefree", seed=0)
+    say("full rows: forward")
+    vals, perm = msn.sort_rows(gpu(x))
+    say("full rows: backward")
+    gi = host(msn.sort_backward(gpu(g), perm))
+    rv, rp = orc.row_argsort(x)
+    assert np.array_equal(host(perm), rp)
+    assert np.array_equal(bits(host(vals)), bits(rv))
+    assert np.array_equal(bits(gi), bits(orc.gather_backward(g, rp)))
+
+
+@pytest.mark.timeout(300)
+def test_max_size_keys(orc):
+    """The largest array the boundary accepts, 2^31 - 1 keys: every 64-bit
+    offset of the passes (eight four-way passes and a binary one) is used."""
+    n = 2**31 - 1
+    say(f"max-size sort_keys {n} u32: generating")
+    x = np.random.default_rng(5).integers(0, 2**32, n, dtype=np.uint32)
+    plan = msn.SortPlan(n, torch.uint32, DEV)
+    say(f"max-size sort_keys {n} u32: sorting")
+    out_t = plan.run(gpu(x))
+    torch.cuda.synchronize()
+    out = host(out_t)
+    del out_t, plan
+    assert bool(np.all(out[1:] >= out[:-1])), "output not non-decreasing"
+    for r in (0, n - 1, 1_234_567_891):
+        lt, le = orc.rank_bounds(x, out[r], dtype="u32")
+        assert lt <= r < le, f"position {r}: value {out[r]} has rank bounds [{lt}, {le})"
+    x.sort()
+    assert np.array_equal(out, x), "output is not the input's multiset in order"
