@@ -88,14 +88,15 @@ inline size_t m4_max_bounds(int64_t n) {
 inline size_t m4_ws_bytes(int64_t n) { return align_up(m4_max_bounds(n) * 16, 256); }
 
 // Workspace of the flat sort: ping-pong keys (+ values), one merge-path split
-// per merge tile, the two chunk-sample arrays, and the four-way passes'
-// boundary table.
+// per merge tile, the two chunk-sample arrays, the four-way passes' boundary
+// table, and the presorted-input flag.
 inline size_t sort_ws_bytes(int64_t n, bool vals) {
     const size_t nk = align_up((size_t)n * 4, 256);
     const size_t nv = vals ? nk : 0;
     const size_t tiles = (size_t)((n + kMinMergeTile - 1) / kMinMergeTile) + 1;
     const size_t chunks = (size_t)((n + kSampleChunk - 1) / kSampleChunk);
-    return nk + nv + align_up(tiles * 4, 256) + 2 * align_up(chunks * 4, 256) + m4_ws_bytes(n);
+    return nk + nv + align_up(tiles * 4, 256) + 2 * align_up(chunks * 4, 256) + m4_ws_bytes(n) +
+           256;
 }
 
 size_t seg_ws_bytes(int64_t n_total, int64_t num_segments, bool vals);

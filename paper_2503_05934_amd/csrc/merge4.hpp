@@ -84,6 +84,7 @@ struct M4Geom {
     int tiles_full;       // tiles per full group
     int tiles_tail;       // tiles of the last, partial group (0 if none)
     M4Div by_tiles;       // division by tiles_full
+    const int* skip;      // *skip set: the input is already sorted, the pass returns at once
 };
 
 __host__ __device__ inline int64_t m4_ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -100,7 +101,7 @@ __host__ __device__ inline int64_t m4_group_samples(const M4Geom& g4, int64_t g)
 }
 
 inline M4Geom m4_geometry(int64_t n, int64_t L) {
-    M4Geom g4{n, L, n / (4 * L), 0, 0, {}};
+    M4Geom g4{n, L, n / (4 * L), 0, 0, {}, nullptr};
     g4.tiles_full = (int)m4_ceil_div(4 * L / kSampleChunk, kM4SamplesPerTile);
     g4.by_tiles = m4_div((uint32_t)g4.tiles_full);
     if (n - g4.full_groups * 4 * L > 0)
@@ -312,6 +313,7 @@ __global__ __launch_bounds__(256) void k_m4_bounds_small(const uint32_t* __restr
                                                          const uint32_t* __restrict__ samp_first,
                                                          int32_t* __restrict__ bnd, M4Geom g4,
                                                          int lg_cl, int64_t nck) {
+    const int skip = *g4.skip;  // tested once the sample loads are in flight
     __shared__ uint32_t smp_g[1 + kM4BoundsBlock];  // a guard word, then the samples
     __shared__ M4Cut cuts[kM4MaxCuts];
     __shared__ int ncut;
@@ -322,6 +324,7 @@ __global__ __launch_bounds__(256) void k_m4_bounds_small(const uint32_t* __restr
     const int nh = (int)(nck - c0 < kM4BoundsBlock ? nck - c0 : kM4BoundsBlock);
     if (threadIdx.x == 0) ncut = 0;
     for (int i = threadIdx.x; i < nh; i += blockDim.x) smp[i] = ord_key<DT>(samp_first[c0 + i]);
+    if (skip) return;  // the input is already sorted
     __syncthreads();
     for (int i = threadIdx.x; i < nh; i += blockDim.x) {
         const int gl = i / GS, j = i - gl * GS;
@@ -363,6 +366,7 @@ __global__ __launch_bounds__(256) void k_m4_bounds_large(const uint32_t* __restr
                                                          const uint32_t* __restrict__ samp_first,
                                                          int32_t* __restrict__ bnd, M4Geom g4,
                                                          int lg_cl, int64_t nck) {
+    const int skip = *g4.skip;  // tested once the sample loads are in flight
     __shared__ uint32_t vs[kM4BoundsBlock];
     __shared__ uint32_t stage_g[3][1 + kM4Window];  // guard word + coarse samples / window
     __shared__ M4Cut cuts[kM4MaxCuts];
@@ -394,6 +398,7 @@ __global__ __launch_bounds__(256) void k_m4_bounds_large(const uint32_t* __restr
         const int nc = (int)m4_ceil_div(nsm[j], cs);
         for (int i = tid; i < nc; i += 256) (stage_g[j] + 1)[i] = ord_key<DT>(rs[j][(int64_t)i << lg_cs]);
     }
+    if (skip) return;  // the input is already sorted
     __syncthreads();
     // brackets: with c coarse samples before v, the count lies in
     // [(c - 1) cs + 1, min(c cs, n)] (or is 0 when c == 0)
@@ -532,6 +537,7 @@ __global__ __launch_bounds__(THREADS) void k_merge4(const uint32_t* __restrict__
                                                     const int32_t* __restrict__ bnd, M4Geom g4,
                                                     uint32_t* __restrict__ samp_first,
                                                     uint32_t* __restrict__ samp_last) {
+    const int skip = *g4.skip;  // tested once the boundary loads are in flight
     static_assert(DT == kU32 || DT == kI32, "integer keys only");
     static_assert(kM4MaxTile <= THREADS * KPT, "tile fits");
     static_assert(KPT == 16 || KPT == 32, "outputs of a thread stay in one padded 32-block");
@@ -562,6 +568,7 @@ __global__ __launch_bounds__(THREADS) void k_merge4(const uint32_t* __restrict__
         c[r] = bnd[(row + 1) * 4 + r] - lo[r];
         ostart += lo[r];
     }
+    if (skip) return;  // the input is already sorted
     const int p1 = c[0], p2 = p1 + c[1], p3 = p2 + c[2], cnt = p3 + c[3];
     const int tid = threadIdx.x;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -801,6 +808,7 @@ __global__ __launch_bounds__(THREADS) void k_merge4_pairs(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
     uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, const int32_t* __restrict__ bnd,
     M4Geom g4, uint32_t* __restrict__ samp_first, uint32_t* __restrict__ samp_last) {
+    const int skip = *g4.skip;  // tested once the boundary loads are in flight
     static_assert(DT == kU32 || DT == kI32, "integer keys only");
     static_assert(kM4MaxTile <= THREADS * KPT, "tile fits");
     constexpr int MK = m4p_mk(THREADS);
@@ -832,6 +840,7 @@ __global__ __launch_bounds__(THREADS) void k_merge4_pairs(
         sh[r] = (uint32_t)(r * g4.L + lo - pst[r]);
         pst[r + 1] = pst[r] + c[r];
     }
+    if (skip) return;  // the input is already sorted
     const int p1 = pst[1], p2 = pst[2], p3 = pst[3], cnt = pst[4];
     const int tid = threadIdx.x;
     const int lane = tid & 63;

@@ -21,8 +21,10 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge_keys(const uint32_t* __
                                                               const int32_t* __restrict__ part,
                                                               int64_t n, int64_t L, int vec,
                                                               uint32_t* __restrict__ samp_first,
-                                                              uint32_t* __restrict__ samp_last) {
+                                                              uint32_t* __restrict__ samp_last,
+                                                              const int* __restrict__ skip) {
     static_assert(DT == kU32 || DT == kI32, "integer keys only");
+    if (*skip) return;  // the input is already sorted
     using Key = std::conditional_t<DT == kI32, int32_t, uint32_t>;
     constexpr Key kMax = DT == kI32 ? (Key)0x7fffffff : (Key)0xffffffffu;
     constexpr int MT = KPT * kMergeThreads;

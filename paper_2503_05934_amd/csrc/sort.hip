@@ -14,7 +14,9 @@ template <int DT, int K, bool STABLE, int VM, int SHAPE>
 __global__ __launch_bounds__((TileTraits<DT, K, STABLE, SHAPE>::kThreads),
                              (TileTraits<DT, K, STABLE, SHAPE>::kWavesPerSimd)) void k_block_sort(
     const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, int64_t n,
-    uint32_t* samp_first, uint32_t* samp_last) {
+    uint32_t* samp_first, uint32_t* samp_last, int* sorted_flag) {
+    // presumed sorted until k_runs_in_order finds two runs out of order
+    if (blockIdx.x == 0 && threadIdx.x == 0) *sorted_flag = 1;
     // static LDS (gfx950 allows up to 160 KiB): its base is a compile-time
     // constant that the padded-slot address math folds away
     __shared__ __align__(16) unsigned char smem[TileTraits<DT, K, STABLE, SHAPE>::kLdsBytes];
@@ -40,7 +42,9 @@ __global__ __launch_bounds__(256) void k_partition(const uint32_t* __restrict__ 
                                                    const uint32_t* __restrict__ samp_first,
                                                    const uint32_t* __restrict__ samp_last,
                                                    int32_t* __restrict__ part, int64_t n,
-                                                   int64_t L, int mt, int ntiles) {
+                                                   int64_t L, int mt, int ntiles,
+                                                   const int* __restrict__ skip) {
+    if (*skip) return;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= ntiles) return;
     const int64_t g0 = (int64_t)t * mt;
@@ -97,7 +101,9 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge(const uint32_t* __restr
                                                          const int32_t* __restrict__ part,
                                                          int64_t n, int64_t L, int vec,
                                                          uint32_t* __restrict__ samp_first,
-                                                         uint32_t* __restrict__ samp_last) {
+                                                         uint32_t* __restrict__ samp_last,
+                                                         const int* __restrict__ skip) {
+    if (*skip) return;
     constexpr int MT = KPT * kMergeThreads;
     extern __shared__ __align__(16) unsigned char smem[];
     uint32_t* sk = reinterpret_cast<uint32_t*>(smem);
@@ -196,6 +202,53 @@ __global__ __launch_bounds__(kMergeThreads) void k_merge(const uint32_t* __restr
     }
 }
 
+// ------------------------------------------------------ presorted input ---
+// After the first sweep every run is sorted, so the whole array is sorted
+// exactly when no run's last key is ordered after the next run's first key
+// (ties keep the runs' order, which is the stable order).  Runs are whole
+// chunks, so both keys are chunk samples the sweep left behind.  The first
+// sweep sets *flag; here one thread per pair of neighbouring runs clears it
+// when the pair is out of order (every writer stores 0).  With the flag
+// still set the global passes return at entry and the first sweep's result
+// is the sorted array (k_copy_if moves it to the output when the sweep
+// wrote the workspace).
+template <int DT>
+__global__ __launch_bounds__(256) void k_runs_in_order(const uint32_t* __restrict__ samp_first,
+                                                       const uint32_t* __restrict__ samp_last,
+                                                       int64_t runs, int64_t run_chunks,
+                                                       int* __restrict__ flag) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r + 1 < runs; r += stride) {
+        const uint32_t a = samp_last[(r + 1) * run_chunks - 1];
+        const uint32_t b = samp_first[(r + 1) * run_chunks];
+        if (ord_key<DT>(b) < ord_key<DT>(a)) *flag = 0;
+    }
+}
+
+// kd = ks (and vd = vs) when *flag is set; returns at once otherwise.
+__global__ __launch_bounds__(512) void k_copy_if(const uint32_t* __restrict__ ks,
+                                                 const uint32_t* __restrict__ vs,
+                                                 uint32_t* __restrict__ kd,
+                                                 uint32_t* __restrict__ vd, int64_t n,
+                                                 const int* __restrict__ flag) {
+    if (!*flag) return;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n4 = n / 4;
+    for (int64_t i = t0; i < n4; i += stride) {
+        const uint4 k = ld4(ks + 4 * i);
+        st4(kd + 4 * i, k.x, k.y, k.z, k.w);
+        if (vs) {
+            const uint4 v = ld4(vs + 4 * i);
+            st4(vd + 4 * i, v.x, v.y, v.z, v.w);
+        }
+    }
+    if (t0 < n - 4 * n4) {
+        kd[4 * n4 + t0] = ks[4 * n4 + t0];
+        if (vs) vd[4 * n4 + t0] = vs[4 * n4 + t0];
+    }
+}
+
 // ------------------------------------------------------------------ host ---
 namespace {
 
@@ -206,14 +259,14 @@ int ensure_lds(Kern kern, size_t bytes) {
 
 template <int DT, int K, bool STABLE, int VM, int SHAPE = 0>
 int launch_block_sort(const SortArgs& a, uint32_t* kdst, uint32_t* vdst,
-                      const Samples& sm) {
+                      const Samples& sm, int* sorted_flag) {
     using Tr = TileTraits<DT, K, STABLE, SHAPE>;
     auto kern = &k_block_sort<DT, K, STABLE, VM, SHAPE>;
     const int64_t blocks = (a.n + Tr::kTile - 1) / Tr::kTile;
     {
         LaunchTimer timer("block_sort", a.n, a.stream);
         hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(Tr::kThreads), 0, a.stream, a.kin,
-                           a.vin, kdst, vdst, a.n, sm.first, sm.last);
+                           a.vin, kdst, vdst, a.n, sm.first, sm.last, sorted_flag);
     }
     return (int)hipGetLastError();
 }
@@ -228,16 +281,16 @@ inline int block_shape(const SortArgs& a) {
 
 template <int DT, int K>
 int dispatch_block_sort(const SortArgs& a, uint32_t* kdst, uint32_t* vdst,
-                        const Samples& sm) {
-    if (a.vmode == kVals) return launch_block_sort<DT, K, true, kVals>(a, kdst, vdst, sm);
-    if (a.vmode == kArg) return launch_block_sort<DT, K, true, kArg>(a, kdst, vdst, sm);
+                        const Samples& sm, int* fl) {
+    if (a.vmode == kVals) return launch_block_sort<DT, K, true, kVals>(a, kdst, vdst, sm, fl);
+    if (a.vmode == kArg) return launch_block_sort<DT, K, true, kArg>(a, kdst, vdst, sm, fl);
     if constexpr (DT == kF32) {
-        return launch_block_sort<DT, K, true, kNoVals>(a, kdst, vdst, sm);
+        return launch_block_sort<DT, K, true, kNoVals>(a, kdst, vdst, sm, fl);
     } else {
         switch (block_shape(a)) {
-            case 1: return launch_block_sort<DT, K, false, kNoVals, 1>(a, kdst, vdst, sm);
-            case 2: return launch_block_sort<DT, K, false, kNoVals, 2>(a, kdst, vdst, sm);
-            default: return launch_block_sort<DT, K, false, kNoVals, 0>(a, kdst, vdst, sm);
+            case 1: return launch_block_sort<DT, K, false, kNoVals, 1>(a, kdst, vdst, sm, fl);
+            case 2: return launch_block_sort<DT, K, false, kNoVals, 2>(a, kdst, vdst, sm, fl);
+            default: return launch_block_sort<DT, K, false, kNoVals, 0>(a, kdst, vdst, sm, fl);
         }
     }
 }
@@ -256,13 +309,14 @@ inline int first_run_length(const SortArgs& a) {
 
 template <int DT, int KPT, bool VALS>
 int launch_merge(const SortArgs& a, const uint32_t* ks, const uint32_t* vs, uint32_t* kd,
-                 uint32_t* vd, int32_t* part, int64_t L, int vec, const Samples& sm) {
+                 uint32_t* vd, int32_t* part, int64_t L, int vec, const Samples& sm,
+                 const int* skip) {
     constexpr int MT = KPT * kMergeThreads;
     const int ntiles = (int)((a.n + MT - 1) / MT);
     {
         LaunchTimer timer("partition", ntiles, a.stream);
         hipLaunchKernelGGL(k_partition<DT>, dim3((ntiles + 255) / 256), dim3(256), 0, a.stream,
-                           ks, sm.first, sm.last, part, a.n, L, MT, ntiles);
+                           ks, sm.first, sm.last, part, a.n, L, MT, ntiles, skip);
     }
     if (int rc = (int)hipGetLastError()) return rc;
     if constexpr (!VALS && DT != kF32) {
@@ -272,7 +326,7 @@ int launch_merge(const SortArgs& a, const uint32_t* ks, const uint32_t* vs, uint
         if (int rc = ensure_lds(kern, lds)) return rc;
         LaunchTimer timer("merge", a.n, a.stream);
         hipLaunchKernelGGL(kern, dim3(ntiles), dim3(kMergeThreads), lds, a.stream, ks, kd, part,
-                           a.n, L, vec, sm.first, sm.last);
+                           a.n, L, vec, sm.first, sm.last, skip);
     } else {
         auto kern = &k_merge<DT, KPT, VALS>;
         const size_t lds = (size_t)std::max(lds_words<uint32_t>(MT), MT + MT / 16) * 4 *
@@ -280,18 +334,19 @@ int launch_merge(const SortArgs& a, const uint32_t* ks, const uint32_t* vs, uint
         if (int rc = ensure_lds(kern, lds)) return rc;
         LaunchTimer timer("merge", a.n, a.stream);
         hipLaunchKernelGGL(kern, dim3(ntiles), dim3(kMergeThreads), lds, a.stream, ks, vs, kd, vd,
-                           part, a.n, L, vec, sm.first, sm.last);
+                           part, a.n, L, vec, sm.first, sm.last, skip);
     }
     return (int)hipGetLastError();
 }
 
 template <int DT, bool VALS>
 int dispatch_merge(const SortArgs& a, const uint32_t* ks, const uint32_t* vs, uint32_t* kd,
-                   uint32_t* vd, int32_t* part, int64_t L, int vec, const Samples& sm) {
+                   uint32_t* vd, int32_t* part, int64_t L, int vec, const Samples& sm,
+                   const int* skip) {
     switch (a.merge_tile) {
-        case 2048: return launch_merge<DT, 8, VALS>(a, ks, vs, kd, vd, part, L, vec, sm);
-        case 8192: return launch_merge<DT, 32, VALS>(a, ks, vs, kd, vd, part, L, vec, sm);
-        default: return launch_merge<DT, 16, VALS>(a, ks, vs, kd, vd, part, L, vec, sm);
+        case 2048: return launch_merge<DT, 8, VALS>(a, ks, vs, kd, vd, part, L, vec, sm, skip);
+        case 8192: return launch_merge<DT, 32, VALS>(a, ks, vs, kd, vd, part, L, vec, sm, skip);
+        default: return launch_merge<DT, 16, VALS>(a, ks, vs, kd, vd, part, L, vec, sm, skip);
     }
 }
 
@@ -311,8 +366,9 @@ int launch_merge4(const SortArgs& a, const uint32_t* in, uint32_t* out, const M4
 // first-sweep run length times a power of four).
 template <int DT>
 int run_merge4(const SortArgs& a, const uint32_t* in, uint32_t* out, const uint32_t* vin,
-               uint32_t* vout, int64_t L, const Samples& sm, int32_t* bnd) {
-    const M4Geom g4 = m4_geometry(a.n, L);
+               uint32_t* vout, int64_t L, const Samples& sm, int32_t* bnd, const int* skip) {
+    M4Geom g4 = m4_geometry(a.n, L);
+    g4.skip = skip;
     const int64_t nck = (a.n + kSampleChunk - 1) / kSampleChunk;
     int lg_cl = 0;
     while ((int64_t)kSampleChunk << lg_cl < L) ++lg_cl;
@@ -367,8 +423,9 @@ int run_sort(const SortArgs& a) {
     const size_t nchunks = (size_t)((a.n + kSampleChunk - 1) / kSampleChunk);
     const size_t ca = align_up(nchunks * 4, 256);
     Samples sm{reinterpret_cast<uint32_t*>(sbase), reinterpret_cast<uint32_t*>(sbase + ca), 0};
-    // boundary table of the four-way passes
+    // boundary table of the four-way passes, then the presorted flag
     int32_t* bnd = reinterpret_cast<int32_t*>(sbase + 2 * ca);
+    int* sorted_flag = reinterpret_cast<int*>(sbase + 2 * ca + m4_ws_bytes(a.n));
 
     // Ping-pong so that the last pass lands in the output.
     uint32_t* kb[2] = {a.kout, wk};
@@ -379,21 +436,39 @@ int run_sort(const SortArgs& a) {
                                (a.vmode != kVals || aligned(a.vin))));
 
     int cur = passes & 1;
-    int rc = a.leaf_k == 8 ? dispatch_block_sort<DT, 8>(a, kb[cur], vb[cur], sm)
-                           : dispatch_block_sort<DT, 4>(a, kb[cur], vb[cur], sm);
+    int rc = a.leaf_k == 8 ? dispatch_block_sort<DT, 8>(a, kb[cur], vb[cur], sm, sorted_flag)
+                           : dispatch_block_sort<DT, 4>(a, kb[cur], vb[cur], sm, sorted_flag);
     if (rc) return rc;
+    if (passes > 0) {
+        const int64_t runs = (a.n + tile - 1) / tile;
+        {
+            LaunchTimer timer("presorted", a.n, a.stream);
+            hipLaunchKernelGGL(k_runs_in_order<DT>,
+                               dim3((unsigned)std::min<int64_t>((runs + 254) / 256, 512)),
+                               dim3(256), 0, a.stream, sm.first, sm.last, runs,
+                               (int64_t)(tile / kSampleChunk), sorted_flag);
+        }
+        if (int e = (int)hipGetLastError()) return e;
+        if (cur == 1) {
+            LaunchTimer timer("copy", a.n, a.stream);
+            hipLaunchKernelGGL(k_copy_if, dim3(512), dim3(512), 0, a.stream, kb[1],
+                               vals ? vb[1] : nullptr, kb[0], vals ? vb[0] : nullptr, a.n,
+                               sorted_flag);
+        }
+        if (int e = (int)hipGetLastError()) return e;
+    }
     int64_t L = tile;
     for (int p = 0; p < passes; ++p) {
         const int nxt = cur ^ 1;
         if (ways[p] == 4) {
             if constexpr (DT != kF32)
                 rc = run_merge4<DT>(a, kb[cur], kb[nxt], vals ? vb[cur] : nullptr,
-                                    vals ? vb[nxt] : nullptr, L, sm, bnd);
+                                    vals ? vb[nxt] : nullptr, L, sm, bnd, sorted_flag);
         } else {
             rc = vals ? dispatch_merge<DT, true>(a, kb[cur], vb[cur], kb[nxt], vb[nxt], part, L,
-                                                 vec, sm)
+                                                 vec, sm, sorted_flag)
                       : dispatch_merge<DT, false>(a, kb[cur], nullptr, kb[nxt], nullptr, part, L,
-                                                  vec, sm);
+                                                  vec, sm, sorted_flag);
         }
         if (rc) return rc;
         L *= ways[p];

@@ -225,6 +225,69 @@ def test_four_way_pairs_stable(orc, dtype, leaf):
         assert np.array_equal(host(vo), rv), (n, kind)
 
 
+def _presorted_variant(x, variant, t, rng):
+    """Sorted keys x, then: "sorted" as is; "local": swaps inside first-sweep
+    runs of length t, away from their ends (the runs come out of the first
+    sweep in order); "edge": one swap across a run boundary; "last": the
+    smallest key moved to the end (the two take every pass)."""
+    x = x.copy()
+    n = x.shape[0]
+    if variant == "local":
+        for _ in range(32):
+            r = int(rng.integers(0, max(1, n // t)))
+            lo, hi = r * t + 1, min(n, (r + 1) * t) - 1
+            if hi - lo >= 2:
+                i, j = rng.integers(lo, hi, 2)
+                x[i], x[j] = x[j], x[i]
+    elif variant == "edge":
+        b = t * int(rng.integers(1, -(-n // t)))
+        x[b - 1], x[b] = x[b], x[b - 1]
+        if x[b - 1] == x[b]:
+            x[b - 1], x[b] = x[0], x[-1]
+    elif variant == "last":
+        x = np.concatenate([x[1:], x[:1]])
+    return x
+
+
+@pytest.mark.parametrize("leaf", ["6To8", "3To5"])
+@pytest.mark.parametrize("dtype", ["u32", "i32", "f32"])
+def test_presorted_inputs(orc, dtype, leaf):
+    """Inputs whose first-sweep runs already follow each other in order skip
+    every global pass (the first sweep's result is copied to the output when
+    it went to the workspace): keys, pairs and argsort under both pass plans,
+    with odd and even pass counts, against inputs where a single pair of keys
+    across a run boundary, or the last key, keeps the passes."""
+    k = 8 if leaf == "6To8" else 4
+    rng = np.random.default_rng(77)
+    for runs in (2, 3, 5, 17, 65):
+        for ways in (4, 2):
+            for pairs in (False, True):
+                t = (1024 if pairs or dtype == "f32" else 2048) * k  # first-sweep run
+                n = runs * t - (runs % 3) * 51
+                if dtype == "f32":
+                    base = orc.sort(make_keys(n, "f32", seed=runs), dtype="f32", stable=True)
+                else:
+                    base = np.sort(_tricky_keys(n, "few" if runs % 2 else "random", dtype, runs))
+                for variant in ("sorted", "local", "edge", "last"):
+                    x = _presorted_variant(base, variant, t, rng)
+                    tag = (dtype, leaf, n, ways, pairs, variant)
+                    say(f"presorted {tag}")
+                    tuning = {"merge_ways": ways}
+                    if not pairs:
+                        y = host(msn.sort(gpu(x), leaf=leaf, tuning=tuning))
+                        ref = orc.sort(x, dtype=dtype, stable=True)
+                        assert np.array_equal(bits(y), bits(ref)), tag
+                        continue
+                    v = rng.integers(0, 2**32, n, dtype=np.uint32)
+                    ko, vo = msn.sort_pairs(gpu(x), gpu(v), leaf=leaf, tuning=tuning)
+                    rk, rv = orc.sort(x, vals=v, dtype=dtype, stable=True)
+                    assert np.array_equal(bits(host(ko)), bits(rk)), tag
+                    assert np.array_equal(host(vo), rv), tag
+                    _, po = msn.sort_pairs(gpu(x), None, leaf=leaf, tuning=tuning)
+                    _, rp = orc.sort(x, dtype=dtype, stable=True, want_perm=True)
+                    assert np.array_equal(host(po).view(np.uint32), rp), tag
+
+
 def test_unaligned_views(orc):
     # offsets by one element: 4-byte aligned, not 16-byte aligned
     n = 50001
