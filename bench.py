@@ -539,7 +539,7 @@ def main():
     ap.add_argument("--merge4-kpt", type=int, default=0,
                     help="keys per thread of the four-way merge kernel (16 or 32)")
     ap.add_argument("--dists", default="random,sorted,nearly")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 26)
+    ap.add_argument("--cpu-sample", type=int, default=1 << 27)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--eager", action="store_true",
                     help="time eager calls instead of replays of a captured HIP graph")
