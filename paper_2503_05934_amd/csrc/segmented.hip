@@ -422,6 +422,53 @@ __device__ void wg_merge_pass(const uint32_t* ks, const uint32_t* vs, uint32_t* 
     }
 }
 
+// A keys-only tile that is already in order (a presorted array, or a piece
+// of one) is copied as it stands.  Every thread checks its own keys and its
+// first key against the previous thread's last (one LDS word per thread),
+// and the workgroup agrees through one barrier-or.  Returns whether it
+// copied; on false the caller sorts the tile (reading it again, from L2).
+// The keys live only here, so the sort that may follow keeps its registers.
+template <int DT, int KPL>
+__device__ __forceinline__ bool copy_if_in_order(const uint32_t* kin, uint32_t* kout, int nv,
+                                              void* smem) {
+    uint32_t* edge = reinterpret_cast<uint32_t*>(smem);
+    const int tid = threadIdx.x;
+    const int first = tid * KPL;
+    uint32_t x[KPL];
+    if (first + KPL <= nv) {
+#pragma unroll
+        for (int q = 0; q < KPL / 4; ++q) {
+            const uint4 w = ld4(kin + first + 4 * q);
+            x[4 * q + 0] = w.x;
+            x[4 * q + 1] = w.y;
+            x[4 * q + 2] = w.z;
+            x[4 * q + 3] = w.w;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < KPL; ++j) x[j] = (first + j < nv) ? kin[first + j] : 0u;
+    }
+    int bad = 0;
+#pragma unroll
+    for (int j = 0; j + 1 < KPL; ++j)
+        bad |= (int)((first + j + 1 < nv) & (ord_key<DT>(x[j + 1]) < ord_key<DT>(x[j])));
+    if (first < nv) edge[tid] = ord_key<DT>(first + KPL <= nv ? x[KPL - 1] : kin[nv - 1]);
+    __syncthreads();
+    if (tid > 0 && first < nv) bad |= (int)(ord_key<DT>(x[0]) < edge[tid - 1]);
+    // the same for every thread: a uniform branch for the compiler too
+    if (__builtin_amdgcn_readfirstlane(__syncthreads_or(bad))) return false;
+    if (first + KPL <= nv) {
+#pragma unroll
+        for (int q = 0; q < KPL / 4; ++q)
+            st4(kout + first + 4 * q, x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3]);
+    } else {
+#pragma unroll
+        for (int j = 0; j < KPL; ++j)
+            if (first + j < nv) kout[first + j] = x[j];
+    }
+    return true;
+}
+
 template <int DT, int K, bool STABLE, int VM>
 __device__ void big_task(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
                          uint32_t* wk, uint32_t* wv, uint32_t off, int len, void* smem) {
@@ -507,9 +554,15 @@ __global__ __launch_bounds__(kBlockThreads, STABLE ? 4 : 6) void k_segmented(
         } else if (item < e2) {
             uint32_t off, len;
             seg_bounds(offsets, L[kCBlock * S + (item - e0)], uni_len, off, len);
-            block_sort_tile<DT, K, STABLE, VM>(kin + off, VM == kVals ? vin + off : nullptr,
-                                               kout + off, VM != kNoVals ? vout + off : nullptr,
-                                               (int)len, 0u, smem);
+            bool done = false;
+            if constexpr (!STABLE)
+                done = copy_if_in_order<DT, keys_per_lane<K>()>(kin + off, kout + off, (int)len,
+                                                                smem);
+            if (!__builtin_amdgcn_readfirstlane(done))
+                block_sort_tile<DT, K, STABLE, VM>(kin + off, VM == kVals ? vin + off : nullptr,
+                                                   kout + off,
+                                                   VM != kNoVals ? vout + off : nullptr, (int)len,
+                                                   0u, smem);
         } else if (item < e3) {
             const uint32_t w = (uint32_t)tid / kWave;
             const uint32_t idx = (item - e2) * kWavesPerBlock + w;
@@ -556,7 +609,10 @@ void k_seg_tile_sort(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, u
         uint32_t* vd = VM != kNoVals ? ((passes & 1) ? wv : vout) + off + first : nullptr;
         const uint32_t* ks = kin + off + first;
         const uint32_t* vs = VM == kVals ? vin + off + first : nullptr;
-        block_sort_tile<DT, K, STABLE, VM, 0, true>(ks, vs, kd, vd, nv, first, smem);
+        bool done = false;
+        if constexpr (!STABLE) done = copy_if_in_order<DT, Tr::kKPL>(ks, kd, nv, smem);
+        if (!__builtin_amdgcn_readfirstlane(done))
+            block_sort_tile<DT, K, STABLE, VM, 0, true>(ks, vs, kd, vd, nv, first, smem);
         __syncthreads();  // the next tile reuses the LDS
     }
 }

@@ -135,6 +135,53 @@ def test_equal_rows_without_offsets(orc, leaf):
         assert np.array_equal(host(yp).view(np.uint32), rp)
 
 
+@pytest.mark.parametrize("leaf", ["6To8", "3To5"])
+@pytest.mark.parametrize("dtype", ["i32", "u32", "f32"])
+def test_presorted_segments(orc, dtype, leaf):
+    """Arrays that arrive sorted, or sorted but for one pair of keys at a
+    thread edge (keys-per-thread apart), at a tile edge, or inside a thread,
+    next to random arrays: keys-only integer tiles already in order are
+    copied as they stand, every other tile is sorted."""
+    kpt = 16 if leaf == "6To8" else 8
+    tile = 512 * kpt
+    lengths = np.concatenate([CLASS_LENGTHS, [tile * 3, tile * 8, tile * 2 + 5, 3 * kpt + 1],
+                              mixed_lengths(seed=31, count=200)])
+    off = offsets_of(lengths)
+    x = seg_keys(int(off[-1]), dtype, seed=32)
+    rng = np.random.default_rng(33)
+    kinds = []
+    for s in range(lengths.shape[0]):
+        a, b = int(off[s]), int(off[s + 1])
+        kind = ("random", "sorted", "thread", "tile", "inside")[s % 5]
+        kinds.append(kind)
+        if kind == "random" or b - a < 2:
+            continue
+        seg = orc.sort(x[a:b], dtype=dtype, stable=True)
+        n = b - a
+        if kind == "thread" and n > kpt:
+            i = kpt * int(rng.integers(1, (n - 1) // kpt + 1))
+            seg[i - 1], seg[i] = seg[i], seg[i - 1]
+        elif kind == "tile" and n > tile:
+            i = tile * int(rng.integers(1, (n - 1) // tile + 1))
+            seg[i - 1], seg[i] = seg[i], seg[i - 1]
+        elif kind == "inside" and n > 3:
+            i = int(rng.integers(1, n - 1))
+            seg[i - 1], seg[i] = seg[i], seg[i - 1]
+        x[a:b] = seg
+    say(f"segmented presorted dtype={dtype} leaf={leaf} segments={lengths.shape[0]}")
+    y = msn.segmented_sort(gpu(x), gpu(off), leaf=leaf)
+    ref = orc.segmented_sort(x, off, dtype=dtype, stable=True)
+    assert np.array_equal(bits(host(y)), bits(ref))
+    say("segmented presorted, in place")
+    t = gpu(x)
+    msn.segmented_sort(t, gpu(off), out_keys=t, leaf=leaf)
+    assert np.array_equal(bits(host(t)), bits(ref))
+    say("segmented presorted, argsort")
+    _, p = msn.segmented_sort(gpu(x), gpu(off), argsort=True, leaf=leaf)
+    _, rp = orc.segmented_sort(x, off, dtype=dtype, stable=True, want_perm=True)
+    assert np.array_equal(host(p).view(np.uint32), rp)
+
+
 def test_only_empty_and_tiny_segments(orc):
     lengths = np.array([0] * 50 + [1] * 50 + [0, 2, 0, 3])
     off = offsets_of(lengths)
