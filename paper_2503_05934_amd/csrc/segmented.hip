@@ -294,6 +294,22 @@ __device__ __forceinline__ void seg_merge_tile(const uint32_t* ks, const uint32_
             const int x = min(tid + q * kBlockThreads, cnt - 1);
             r[q] = (Key)ks[x < na ? base + i0 + x : base + la + j0 + (x - na)];
         }
+        // A's piece ends at or below the start of B's (runs already in
+        // order, as in a presorted array): the merge is the concatenation
+        // the loads just read, stored as it stands
+        const int pa = max(base + i1 - 1, base);                 // A's last (when na > 0)
+        const int pb = min(base + la + j0, base + la + nb + j0 - 1);  // B's first (nb > 0)
+        const bool concat = na == 0 || nb == 0 || !((Key)ks[pb] < (Key)ks[pa]);
+        if (__builtin_amdgcn_readfirstlane((int)concat)) {
+            uint32_t* kr = kd + base + d0;
+#pragma unroll
+            for (int q = 0; q < KPT; ++q) {
+                const int x = tid + q * kBlockThreads;
+                if (x < cnt) kr[x] = (uint32_t)r[q];
+            }
+            __syncthreads();  // as the merge path ends: callers reuse the LDS after it
+            return;
+        }
 #pragma unroll
         for (int q = 0; q < KPT; ++q) {
             const int x = tid + q * kBlockThreads;
