@@ -7,10 +7,13 @@
 //          (Table 3, VarSort);
 //   wave   (<= wave_max): one wavefront, networks + bitonic merges;
 //   block  (<= block_max): one workgroup, network + bitonic + LDS merges;
-//   tiled  (up to kSegTiledMax block-sort tiles): every tile is a work item
-//          of its own (k_seg_tile_sort), then up to three merge passes over
+//   tiled  (up to kSegTiledMax block-sort tiles): every run is a work item
+//          of its own (k_seg_tile_sort: keys-only runs are two tiles long,
+//          sorted by the flat sort's 1024-thread block sort; stable runs are
+//          one tile), then up to two (keys-only) or three merge passes over
 //          all such segments at once, one workgroup per output tile
-//          (k_seg_tile_part, then k_seg_tile_merge);
+//          (k_seg_tile_part, then k_seg_tile_merge); tiles already in order
+//          are copied rather than sorted or merged;
 //   big    (longer): one workgroup sorts the segment's tiles in turn and then
 //          merges them pass by pass through global memory.
 // k_seg_bin sorts segment ids into per-class lists and the tiles of tiled
@@ -39,10 +42,8 @@ struct SegState {
 };
 
 // Segments of up to this many block-sort tiles take the tiled path (at most
-// three merge passes).
+// three merge passes from one-tile runs, two from keys-only two-tile runs).
 constexpr int kSegTiledMax = 8;
-constexpr int kSegTiledPasses = 3;
-static_assert((1 << kSegTiledPasses) == kSegTiledMax, "passes of the tiled path");
 
 // Tile list bound: a tiled segment of len keys has ceil(len / tile) tiles,
 // tile >= 4096 keys (3-to-5 leaves).
@@ -76,6 +77,18 @@ __host__ __device__ inline int seg_passes(uint32_t tiles) {
     while ((1u << p) < tiles) ++p;
     return p;
 }
+
+// Runs the tile sort leaves in a tiled segment: keys-only tiles take the
+// flat sort's 1024-thread shape (runs of two list tiles, one merge pass
+// fewer); stable tiles keep the list tile.
+template <int DT, int K, bool STABLE>
+struct SegRun {
+    static constexpr int kShape = STABLE ? 0 : 1;
+    using Tr = TileTraits<DT, K, STABLE, kShape>;
+    static constexpr int kRun = Tr::kTile;
+    static constexpr int kListTile = TileTraits<DT, K, STABLE>::kTile;
+    static_assert(kRun % kListTile == 0, "runs are whole list tiles");
+};
 
 __device__ __forceinline__ void seg_bounds(const uint32_t* offsets, uint32_t s, uint32_t uni_len,
                                            uint32_t& off, uint32_t& len) {
@@ -601,26 +614,32 @@ __global__ __launch_bounds__(kBlockThreads, STABLE ? 4 : 6) void k_segmented(
 }
 
 // ---------------------------------------------- sorts, tiled path ---
-// The tiles of the tiled segments, workgroups taking list entries in turn:
-// the flat sort's block sort (32 outputs per thread in its LDS levels for
-// keys-only tiles, its own register budget), each tile written where its
-// segment's first merge pass reads it (the output itself for one tile).
+// The runs of the tiled segments, workgroups taking list entries in turn
+// (the entry of a run's first list tile sorts the run; the others pass):
+// the flat sort's block sort (for keys-only runs its 1024-thread shape, 32
+// outputs per thread in its LDS levels, its own register budget), each run
+// written where its segment's first merge pass reads it (the output itself
+// for one run).
 template <int DT, int K, bool STABLE, int VM>
-__global__ __launch_bounds__(kBlockThreads, (TileTraits<DT, K, STABLE>::kWavesPerSimd))
+__global__ __launch_bounds__((SegRun<DT, K, STABLE>::Tr::kThreads),
+                             (SegRun<DT, K, STABLE>::Tr::kWavesPerSimd))
 void k_seg_tile_sort(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
                      uint32_t* wk, uint32_t* wv, const uint32_t* __restrict__ offsets,
                      uint32_t uni_len, const SegState* st, const uint2* __restrict__ tiles) {
-    using Tr = TileTraits<DT, K, STABLE>;
+    using R = SegRun<DT, K, STABLE>;
+    using Tr = typename R::Tr;
     __shared__ __align__(16) unsigned char smem[Tr::kLdsBytes];
-    constexpr int kTile = Tr::kTile;
+    constexpr int kRun = R::kRun;
+    constexpr uint32_t kPer = R::kRun / R::kListTile;  // list tiles per run
     const uint32_t n = st->tiles;
     for (uint32_t e = blockIdx.x; e < n; e += gridDim.x) {
         const uint2 tc = tiles[e];
+        if (tc.y % kPer != 0) continue;  // uniform: one entry per workgroup
         uint32_t off, len;
         seg_bounds(offsets, tc.x, uni_len, off, len);
-        const int passes = seg_passes((len + kTile - 1) / kTile);
-        const uint32_t first = tc.y * (uint32_t)kTile;
-        const int nv = min(kTile, (int)(len - first));
+        const int passes = seg_passes((len + kRun - 1) / kRun);
+        const uint32_t first = tc.y * (uint32_t)R::kListTile;
+        const int nv = min(kRun, (int)(len - first));
         uint32_t* kd = ((passes & 1) ? wk : kout) + off + first;
         uint32_t* vd = VM != kNoVals ? ((passes & 1) ? wv : vout) + off + first : nullptr;
         const uint32_t* ks = kin + off + first;
@@ -628,14 +647,15 @@ void k_seg_tile_sort(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, u
         bool done = false;
         if constexpr (!STABLE) done = copy_if_in_order<DT, Tr::kKPL>(ks, kd, nv, smem);
         if (!__builtin_amdgcn_readfirstlane(done))
-            block_sort_tile<DT, K, STABLE, VM, 0, true>(ks, vs, kd, vd, nv, first, smem);
-        __syncthreads();  // the next tile reuses the LDS
+            block_sort_tile<DT, K, STABLE, VM, R::kShape, true>(ks, vs, kd, vd, nv, first, smem);
+        __syncthreads();  // the next run reuses the LDS
     }
 }
 
 // ---------------------------------------------- merge passes, tiled path ---
 // Pass p of every tiled segment that has more than p passes: runs of
-// tile << p become runs of tile << (p + 1), one output tile per list entry.
+// run << p become runs of run << (p + 1), one output tile (a list tile) per
+// list entry.
 // The data alternate between the output and the workspace so that the last
 // pass of each segment lands in the output.
 
@@ -648,21 +668,23 @@ struct SegTilePass {
     int base, la, lb, d0, d1;  // merge of [base, base+la) and [base+la, base+la+lb)
 };
 
-// Geometry of list entry (seg, c) in pass p; false when the segment has no
+// Geometry of list entry (seg, c) in pass p (runs of `run` keys after the
+// tile sort, output tiles of `tile` keys); false when the segment has no
 // pass p.
 template <bool VALS>
-__device__ __forceinline__ bool seg_tile_pass(uint2 tc, int p, int tile, const uint32_t* offsets,
-                                              uint32_t uni_len, uint32_t* kout, uint32_t* vout,
-                                              uint32_t* wk, uint32_t* wv, SegTilePass& g) {
+__device__ __forceinline__ bool seg_tile_pass(uint2 tc, int p, int tile, int run,
+                                              const uint32_t* offsets, uint32_t uni_len,
+                                              uint32_t* kout, uint32_t* vout, uint32_t* wk,
+                                              uint32_t* wv, SegTilePass& g) {
     seg_bounds(offsets, tc.x, uni_len, g.off, g.len);
-    const int passes = seg_passes((g.len + tile - 1) / tile);
+    const int passes = seg_passes((g.len + run - 1) / run);
     if (passes <= p) return false;
     const bool src_ws = ((passes - p) & 1) != 0;  // before pass p the data sit in wk
     g.ks = (src_ws ? wk : kout) + g.off;
     g.kd = (src_ws ? kout : wk) + g.off;
     g.vs = VALS ? (src_ws ? wv : vout) + g.off : nullptr;
     g.vd = VALS ? (src_ws ? vout : wv) + g.off : nullptr;
-    const int L = tile << p;
+    const int L = run << p;
     const int len = (int)g.len;
     const int g0 = (int)tc.y * tile;
     g.base = g0 & ~(2 * L - 1);
@@ -678,11 +700,12 @@ template <int DT, bool VALS>
 __global__ __launch_bounds__(256) void k_seg_tile_part(
     uint32_t* kout, uint32_t* vout, uint32_t* wk, uint32_t* wv,
     const uint32_t* __restrict__ offsets, uint32_t uni_len, const SegState* st,
-    const uint2* __restrict__ tiles, int32_t* __restrict__ part, int tile, int p) {
+    const uint2* __restrict__ tiles, int32_t* __restrict__ part, int tile, int run, int p) {
     const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= st->tiles) return;
     SegTilePass g;
-    if (!seg_tile_pass<VALS>(tiles[e], p, tile, offsets, uni_len, kout, vout, wk, wv, g)) return;
+    if (!seg_tile_pass<VALS>(tiles[e], p, tile, run, offsets, uni_len, kout, vout, wk, wv, g))
+        return;
     part[e] = corank_global<DT>(g.ks + g.base, g.la, g.ks + g.base + g.la, g.lb, g.d0);
 }
 
@@ -693,7 +716,7 @@ template <int DT, bool VALS, int KPT>
 __global__ __launch_bounds__(kBlockThreads, DT == kF32 ? 1 : 6) void k_seg_tile_merge(
     uint32_t* kout, uint32_t* vout, uint32_t* wk, uint32_t* wv,
     const uint32_t* __restrict__ offsets, uint32_t uni_len, const SegState* st,
-    const uint2* __restrict__ tiles, const int32_t* __restrict__ part, int p) {
+    const uint2* __restrict__ tiles, const int32_t* __restrict__ part, int run, int p) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int kTile = KPT * kBlockThreads;
     uint32_t* sk = reinterpret_cast<uint32_t*>(smem);
@@ -701,7 +724,8 @@ __global__ __launch_bounds__(kBlockThreads, DT == kF32 ? 1 : 6) void k_seg_tile_
     const uint32_t n = st->tiles;
     for (uint32_t e = blockIdx.x; e < n; e += gridDim.x) {
         SegTilePass g;
-        if (!seg_tile_pass<VALS>(tiles[e], p, kTile, offsets, uni_len, kout, vout, wk, wv, g))
+        if (!seg_tile_pass<VALS>(tiles[e], p, kTile, run, offsets, uni_len, kout, vout, wk, wv,
+                                 g))
             continue;
         const int i0 = part[e];
         const int i1 = g.d1 == g.la + g.lb ? g.la : part[e + 1];
@@ -745,6 +769,7 @@ int launch_seg_kernel(const SegArgs& a, const SegWs& w, uint32_t uni_len) {
     constexpr bool kVals = VM != kNoVals;
     constexpr int kTile = TileTraits<DT, K, STABLE>::kTile;
     constexpr int kKpt = kTile / kBlockThreads;
+    constexpr int kRun = SegRun<DT, K, STABLE>::kRun;
     auto kern = &k_segmented<DT, K, STABLE, VM>;
     if (int rc = set_dynamic_lds(reinterpret_cast<const void*>(kern), Tr::kLds)) return rc;
     int grid = a.grid;
@@ -754,19 +779,20 @@ int launch_seg_kernel(const SegArgs& a, const SegWs& w, uint32_t uni_len) {
     }
     // equal-length segments: the host knows their class and pass count
     bool any_tiled = true;
-    int npass = kSegTiledPasses;
+    int npass = seg_passes((uint32_t)(kSegTiledMax * kTile / kRun));
     if (!a.offsets) {
         const int64_t len = uni_len;
         any_tiled = len > a.block_max && len <= (int64_t)kSegTiledMax * kTile;
-        npass = any_tiled ? seg_passes((uint32_t)((len + kTile - 1) / kTile)) : 0;
+        npass = any_tiled ? seg_passes((uint32_t)((len + kRun - 1) / kRun)) : 0;
     }
     if (any_tiled) {
         auto skern = &k_seg_tile_sort<DT, K, STABLE, VM>;
+        constexpr int kSortThreads = SegRun<DT, K, STABLE>::Tr::kThreads;
         int sgrid = 0;
         static int cached_s = 0;
-        if (int rc = fill_grid(skern, kBlockThreads, 0, &cached_s, &sgrid)) return rc;
+        if (int rc = fill_grid(skern, kSortThreads, 0, &cached_s, &sgrid)) return rc;
         LaunchTimer timer("seg_tile_sort", a.n_total, a.stream);
-        hipLaunchKernelGGL(skern, dim3(sgrid), dim3(kBlockThreads), 0, a.stream, a.kin, a.vin,
+        hipLaunchKernelGGL(skern, dim3(sgrid), dim3(kSortThreads), 0, a.stream, a.kin, a.vin,
                            a.kout, a.vout, w.wk, w.wv, a.offsets, uni_len, w.st, w.tiles);
     }
     if (int rc = (int)hipGetLastError()) return rc;
@@ -792,13 +818,14 @@ int launch_seg_kernel(const SegArgs& a, const SegWs& w, uint32_t uni_len) {
             LaunchTimer timer("seg_tile_part", a.n_total, a.stream);
             hipLaunchKernelGGL((k_seg_tile_part<DT, kVals>), dim3(pgrid), dim3(256), 0, a.stream,
                                a.kout, a.vout, w.wk, w.wv, a.offsets, uni_len, w.st, w.tiles,
-                               w.part, kTile, p);
+                               w.part, kTile, kRun, p);
         }
         if (int rc = (int)hipGetLastError()) return rc;
         {
             LaunchTimer timer("seg_tile_merge", a.n_total, a.stream);
             hipLaunchKernelGGL(mkern, dim3(mgrid), dim3(kBlockThreads), mlds, a.stream, a.kout,
-                               a.vout, w.wk, w.wv, a.offsets, uni_len, w.st, w.tiles, w.part, p);
+                               a.vout, w.wk, w.wv, a.offsets, uni_len, w.st, w.tiles, w.part,
+                               kRun, p);
         }
         if (int rc = (int)hipGetLastError()) return rc;
     }
