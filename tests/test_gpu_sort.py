@@ -288,6 +288,29 @@ def test_presorted_inputs(orc, dtype, leaf):
                     assert np.array_equal(host(po).view(np.uint32), rp), tag
 
 
+@pytest.mark.parametrize("dtype", ["u32", "f32"])
+def test_presorted_in_place_and_unaligned(orc, dtype):
+    """The presorted path's copy when the output is the input (odd pass
+    counts: the first sweep writes the workspace) and on views offset by one
+    element (4-byte aligned only)."""
+    for runs in (2, 3, 4, 5, 17):
+        t = 2048 * 8 if dtype == "u32" else 1024 * 8
+        n = runs * t - 7
+        x = orc.sort(make_keys(n + 1, dtype, seed=runs), dtype=dtype, stable=True)
+        ref = x[1:]
+        say(f"presorted in place dtype={dtype} n={n}")
+        buf = gpu(x[1:].copy())
+        msn.sort(buf, out=buf)
+        assert np.array_equal(bits(host(buf)), bits(ref)), (runs, "in place")
+        say(f"presorted unaligned dtype={dtype} n={n}")
+        view = gpu(x)[1:]
+        y = host(msn.sort(view))
+        assert np.array_equal(bits(y), bits(ref)), (runs, "unaligned")
+        ko, po = msn.sort_pairs(view)
+        assert np.array_equal(bits(host(ko)), bits(ref)), (runs, "argsort keys")
+        assert np.array_equal(host(po), np.arange(n, dtype=np.int32)), (runs, "argsort")
+
+
 def test_unaligned_views(orc):
     # offsets by one element: 4-byte aligned, not 16-byte aligned
     n = 50001
