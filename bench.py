@@ -11,7 +11,7 @@ variants are timed too.  Prints ONE JSON line:
   cpu_baseline the CPU oracle (Algorithm 1, 6-to-8, one thread) on a bounded
                sample of the same input
 
-Other workloads (--workload pairs|segmented|rows) print their own line.
+Other workloads (--workload pairs|segmented|rows|small|leaves|copy) print their own line.
 """
 from __future__ import annotations
 
@@ -501,6 +501,62 @@ def bench_small(args):
     }
 
 
+def bench_leaves(args):
+    """The paper's merge sort measurement (Figs. 1-3) replayed on the GPU:
+    the speedup of network leaves (6-to-8, 3-to-5) over the same sort with no
+    network (merges from single keys, the classical merge sort), Eq. 1:
+    t_classical / t_leaves, over the paper's sizes (10,000 to 1,000,000 int32
+    keys) and 2^28 uint32 keys, for random, sorted and nearly sorted inputs.
+    One graph replay per timed step; inputs up to 1,000,000 keys fit in the
+    Infinity Cache, so those numbers are cache-resident."""
+    import torch
+
+    import paper_2503_05934_amd as msn
+    from paper_2503_05934_amd import workloads
+
+    dev = torch.device("cuda:0")
+    sizes = [10_000, 25_000, 50_000, 100_000, 250_000, 500_000, 1_000_000, 1 << 28]
+    table = {}
+    for n in sizes:
+        dtype, tdt = ("u32", torch.uint32) if n == 1 << 28 else ("i32", torch.int32)
+        steps = max(args.steps, 20) if n < 1 << 28 else max(2, args.steps // 4)
+        for dist in workloads.DISTRIBUTIONS:
+            x = torch.from_numpy(workloads.keys(n, dist, dtype, seed=0)).to(dev)
+            row = {}
+            for leaf in ("classical", "6To8", "3To5"):
+                plan = msn.SortPlan(n, tdt, dev, leaf=leaf)
+                plan.run(x)
+                torch.cuda.synchronize()
+                s = torch.cuda.Stream()
+                s.wait_stream(torch.cuda.current_stream())
+                gph = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(gph, stream=s):
+                    plan.run(x)
+                ms, _ = time_steps(gph.replay, steps, args.warmup)
+                if n == 1 << 28 and not check_sorted_u32(plan.out, x):
+                    raise SystemExit(f"[bench] {leaf} output check failed")
+                row[leaf] = {"us": ms * 1e3, "gkeys_per_s": n / (ms / 1e3) / 1e9}
+                del plan, gph
+            for leaf in ("6To8", "3To5"):
+                row[leaf]["speedup"] = row["classical"]["us"] / row[leaf]["us"]
+            table[f"n={n} {dist}"] = row
+            log(f"[bench] n={n} {dist}: classical {row['classical']['us']:.1f} us, "
+                f"6To8 x{row['6To8']['speedup']:.2f}, 3To5 x{row['3To5']['speedup']:.2f}")
+    head = table[f"n={1 << 28} random"]
+    return {
+        "metric": "speedup of 6-to-8 network leaves over the network-free merge sort (Eq. 1), "
+                  "2^28 uint32 keys random, 1 GPU",
+        "value": head["6To8"]["speedup"], "unit": "x", "n_gpus": 1,
+        "steps": max(2, args.steps // 4), "warmup": args.warmup,
+        "ms_per_step": head["6To8"]["us"] / 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "sort_keys with 6-to-8, 3-to-5 and no networks; 10,000 to "
+                               "1,000,000 int32 keys and 2^28 uint32 keys; random, sorted, "
+                               "nearly sorted; graph replay"},
+        "table": table,
+    }
+
+
 def bench_copy(args):
     """A plain device-to-device copy of n uint32 words: the achievable
     read+write bandwidth, and the reference kernel that calibrates the HBM
@@ -530,9 +586,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="keys",
-                    choices=["keys", "pairs", "segmented", "rows", "small", "copy"])
+                    choices=["keys", "pairs", "segmented", "rows", "small", "leaves", "copy"])
     ap.add_argument("--n", type=int, default=1 << 28)
-    ap.add_argument("--leaf", default="6To8", choices=["6To8", "3To5"])
+    ap.add_argument("--leaf", default="6To8", choices=["6To8", "3To5", "classical"])
     ap.add_argument("--merge-tile", type=int, default=0)
     ap.add_argument("--block-tile", type=int, default=0)
     ap.add_argument("--merge-ways", type=int, default=0)
@@ -556,7 +612,8 @@ def main():
               "(this build has no multi-GPU path)", file=sys.stderr)
         return 2
     fn = {"keys": bench_keys, "pairs": bench_pairs, "segmented": bench_segmented,
-          "rows": bench_rows, "small": bench_small, "copy": bench_copy}[args.workload]
+          "rows": bench_rows, "small": bench_small, "leaves": bench_leaves,
+          "copy": bench_copy}[args.workload]
     out = fn(args)
     print(json.dumps(out), flush=True)
     return 0

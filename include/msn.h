@@ -56,6 +56,10 @@ extern "C" {
 /* base-case network sets (Table 3): the network size each lane applies */
 #define MSN_LEAF_6TO8 0 /* 8-key networks (6- and 7-key tails by padding) */
 #define MSN_LEAF_3TO5 1 /* 4-key networks (3-key tails by padding)        */
+/* no network at all: merges from runs of one key, the classical merge sort
+   the paper measures against (its empty network set); flat sorts only
+   (msn_segmented_sort returns MSN_ERR_UNSUPPORTED), tiles as for 6-to-8 */
+#define MSN_LEAF_NONE 2
 
 /* status codes */
 #define MSN_OK 0

@@ -16,10 +16,10 @@ LIB_PATH = os.path.join(_HERE, "libmsn.so")
 
 # include/msn.h constants
 MSN_U32, MSN_I32, MSN_F32 = 0, 1, 2
-MSN_LEAF_6TO8, MSN_LEAF_3TO5 = 0, 1
+MSN_LEAF_6TO8, MSN_LEAF_3TO5, MSN_LEAF_NONE = 0, 1, 2
 MSN_ARGSORT = 1
 
-LEAVES = {"6To8": MSN_LEAF_6TO8, "3To5": MSN_LEAF_3TO5}
+LEAVES = {"6To8": MSN_LEAF_6TO8, "3To5": MSN_LEAF_3TO5, "classical": MSN_LEAF_NONE}
 _DTYPES = {torch.uint32: MSN_U32, torch.int32: MSN_I32, torch.float32: MSN_F32}
 
 

@@ -75,7 +75,11 @@ namespace {
 constexpr int64_t kMaxN = 0x7fffffffLL;
 
 bool valid_dtype(int d) { return d == MSN_U32 || d == MSN_I32 || d == MSN_F32; }
-int leaf_keys(int leaf) { return leaf == MSN_LEAF_6TO8 ? 8 : leaf == MSN_LEAF_3TO5 ? 4 : 0; }
+// Keys of the base-case network (the network-free sort keeps the 6-to-8
+// tile shapes).
+int leaf_keys(int leaf) {
+    return leaf == MSN_LEAF_6TO8 || leaf == MSN_LEAF_NONE ? 8 : leaf == MSN_LEAF_3TO5 ? 4 : 0;
+}
 
 bool misaligned(const void* p) { return p && ((uintptr_t)p & 3u) != 0; }
 
@@ -144,6 +148,7 @@ int sort_common(const void* keys_in, const uint32_t* vals_in, void* keys_out, ui
     msn::SortArgs a{static_cast<const uint32_t*>(keys_in), vals_in,
                     static_cast<uint32_t*>(keys_out), vals_out, n, dtype, k, vmode, mt, bt, mw, m4k, ws,
                     ws_bytes, static_cast<hipStream_t>(stream)};
+    a.nets = leaf != MSN_LEAF_NONE;
     return msn::launch_sort(a);
 }
 
@@ -257,6 +262,7 @@ int msn_segmented_sort(const void* keys_in, const uint32_t* vals_in, void* keys_
     if (!valid_dtype(dtype)) return MSN_ERR_DTYPE;
     const int k = leaf_keys(leaf);
     if (!k) return MSN_ERR_CONFIG;
+    if (leaf == MSN_LEAF_NONE) return MSN_ERR_UNSUPPORTED;  // flat sorts only
     if (flags & ~MSN_ARGSORT) return MSN_ERR_CONFIG;
     const bool argsort = (flags & MSN_ARGSORT) != 0;
     if (argsort && vals_in) return MSN_ERR_CONFIG;

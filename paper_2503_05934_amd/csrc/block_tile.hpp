@@ -72,7 +72,7 @@ __device__ __forceinline__ void write_samples(const Samples& samp, int first, in
 // 32 - kPackPosBits bits sort 32-bit (key, position) composites instead of
 // 64-bit ones (a run-time choice per tile).
 template <int DT, int K, bool STABLE, int VM, int SHAPE = 0, bool WIDE = false,
-          bool PACK = false>
+          bool PACK = false, bool NETS = true>
 __device__ __forceinline__ void block_sort_tile(const uint32_t* kin, const uint32_t* vin,
                                                 uint32_t* kout, uint32_t* vout, int nv,
                                                 uint32_t val_base, void* smem,
@@ -80,6 +80,7 @@ __device__ __forceinline__ void block_sort_tile(const uint32_t* kin, const uint3
     using Tr = TileTraits<DT, K, STABLE, SHAPE>;
     using T = typename Tr::T;
     static_assert(STABLE || (DT != kF32 && VM == kNoVals), "float keys and pairs sort stably");
+    static_assert(NETS || (!WIDE && !PACK), "the network-free tile takes the plain paths");
     T* s = reinterpret_cast<T*>(smem);
     const int tid = threadIdx.x;
     constexpr int KPL = Tr::kKPL;
@@ -134,7 +135,10 @@ __device__ __forceinline__ void block_sort_tile(const uint32_t* kin, const uint3
             }
         }
     } else if constexpr (!STABLE) {
-        block_sort_regs<T, K, KPL>(v, s, span);
+        if constexpr (NETS)
+            block_sort_regs<T, K, KPL>(v, s, span);
+        else
+            block_merge_only<T, KPL>(v, s, span);
 #pragma unroll
         for (int j = 0; j < KPL; ++j) x[j] = unord_key<DT>(v[j]);
         write_samples(samp, first, nv, x);
@@ -212,7 +216,10 @@ __device__ __forceinline__ void block_sort_tile(const uint32_t* kin, const uint3
                 return;
             }
         }
-        block_sort_regs<T, K, KPL>(v, s, span);
+        if constexpr (NETS)
+            block_sort_regs<T, K, KPL>(v, s, span);
+        else
+            block_merge_only<T, KPL>(v, s, span);
         // Stage what must be gathered by position (float bits, payload).
         __syncthreads();
         if constexpr (kNeedBits || kNeedVals) {

@@ -481,6 +481,59 @@ __device__ __forceinline__ void block_sort_regs(T (&v)[KPL], T* s, int span) {
     }
 }
 
+// The same contract as block_sort_regs with no network anywhere: the
+// classical merge sort the paper measures its network leaves against (its
+// empty network set), in the same tile shape.  Each thread first merges its
+// KPL keys from runs of one key up to one run of KPL, pairs of runs read
+// back from its own LDS window; merge-path levels across threads then double
+// the runs up to `span`.  Every merge is sequential and stable, and checks
+// the run ends instead of relying on sentinels, so the LDS holds the span
+// and nothing more.
+template <typename T, int L, int KPL>
+__device__ __forceinline__ void merge_in_thread(T (&v)[KPL], T* s, int e) {
+    if constexpr (L < KPL) {
+        // the window is this thread's own: its earlier reads precede these
+        // writes in program order, and no other thread touches it
+#pragma unroll
+        for (int j = 0; j < KPL; ++j) s[lds_idx<T>(e + j)] = v[j];
+#pragma unroll
+        for (int p = 0; p < KPL / (2 * L); ++p) {
+            T o[2 * L];
+            int src[2 * L];
+            const int a0 = e + p * 2 * L;
+            serial_merge<T, 2 * L, false>(s, a0, L, a0 + L, L, 0, 0, e + KPL - 1, o, src,
+                                          PlainLess{});
+#pragma unroll
+            for (int k = 0; k < 2 * L; ++k) v[p * 2 * L + k] = o[k];
+        }
+        merge_in_thread<T, 2 * L, KPL>(v, s, e);
+    }
+}
+
+template <typename T, int KPL>
+__device__ __forceinline__ void block_merge_only(T (&v)[KPL], T* s, int span) {
+    const int e = (int)threadIdx.x * KPL;
+    const bool active = e < span;
+    if (active) merge_in_thread<T, 1, KPL>(v, s, e);
+    for (int L = KPL; L < span; L <<= 1) {
+        __syncthreads();  // the previous level's readers are done with s
+        if (active) {
+#pragma unroll
+            for (int j = 0; j < KPL; ++j) s[lds_idx<T>(e + j)] = v[j];
+        }
+        __syncthreads();
+        if (active) {
+            const int a0 = e & ~(2 * L - 1);
+            const int d = e - a0;
+            const int i = corank_lds(s, a0, L, a0 + L, L, d, PlainLess{});
+            int src[KPL];
+            serial_merge<T, KPL, false>(s, a0, L, a0 + L, L, i, d - i, span - 1, v, src,
+                                        PlainLess{});
+        }
+    }
+    __syncthreads();  // the caller may reuse s
+}
+
 // LDS words block_sort_regs2 needs: as block_lds_words with MK sentinels per run.
 template <typename T, int KPL, int MK>
 __host__ __device__ constexpr int block_lds_words2(int n) {

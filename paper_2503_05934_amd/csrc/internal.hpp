@@ -38,6 +38,7 @@ struct SortArgs {
     void* ws;
     size_t ws_bytes;
     hipStream_t stream;
+    int nets = 1;         // 0: no networks (the classical merge sort), tiles of leaf_k = 8
 };
 
 struct SegArgs {

@@ -10,7 +10,7 @@
 namespace msn {
 
 // ----------------------------------------------------------- first sweep ---
-template <int DT, int K, bool STABLE, int VM, int SHAPE>
+template <int DT, int K, bool STABLE, int VM, int SHAPE, bool NETS>
 __global__ __launch_bounds__((TileTraits<DT, K, STABLE, SHAPE>::kThreads),
                              (TileTraits<DT, K, STABLE, SHAPE>::kWavesPerSimd)) void k_block_sort(
     const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, int64_t n,
@@ -23,7 +23,9 @@ __global__ __launch_bounds__((TileTraits<DT, K, STABLE, SHAPE>::kThreads),
     constexpr int kTile = TileTraits<DT, K, STABLE, SHAPE>::kTile;
     const int64_t base = (int64_t)blockIdx.x * kTile;
     const int nv = (int)((n - base) < kTile ? (n - base) : kTile);
-    block_sort_tile<DT, K, STABLE, VM, SHAPE, true, true>(kin + base, VM == kVals ? vin + base : nullptr,
+    // network tiles take the wide LDS levels and packed composites
+    block_sort_tile<DT, K, STABLE, VM, SHAPE, NETS, NETS, NETS>(kin + base,
+                                             VM == kVals ? vin + base : nullptr,
                                              kout + base, VM != kNoVals ? vout + base : nullptr,
                                              nv, (uint32_t)base, smem,
                                              Samples{samp_first, samp_last, base});
@@ -257,11 +259,11 @@ int ensure_lds(Kern kern, size_t bytes) {
     return set_dynamic_lds(reinterpret_cast<const void*>(kern), bytes);
 }
 
-template <int DT, int K, bool STABLE, int VM, int SHAPE = 0>
+template <int DT, int K, bool STABLE, int VM, int SHAPE, bool NETS>
 int launch_block_sort(const SortArgs& a, uint32_t* kdst, uint32_t* vdst,
                       const Samples& sm, int* sorted_flag) {
     using Tr = TileTraits<DT, K, STABLE, SHAPE>;
-    auto kern = &k_block_sort<DT, K, STABLE, VM, SHAPE>;
+    auto kern = &k_block_sort<DT, K, STABLE, VM, SHAPE, NETS>;
     const int64_t blocks = (a.n + Tr::kTile - 1) / Tr::kTile;
     {
         LaunchTimer timer("block_sort", a.n, a.stream);
@@ -279,18 +281,21 @@ inline int block_shape(const SortArgs& a) {
     return ratio >= 4 ? 2 : ratio == 2 ? 1 : 0;
 }
 
-template <int DT, int K>
+template <int DT, int K, bool NETS>
 int dispatch_block_sort(const SortArgs& a, uint32_t* kdst, uint32_t* vdst,
                         const Samples& sm, int* fl) {
-    if (a.vmode == kVals) return launch_block_sort<DT, K, true, kVals>(a, kdst, vdst, sm, fl);
-    if (a.vmode == kArg) return launch_block_sort<DT, K, true, kArg>(a, kdst, vdst, sm, fl);
+    if (a.vmode == kVals)
+        return launch_block_sort<DT, K, true, kVals, 0, NETS>(a, kdst, vdst, sm, fl);
+    if (a.vmode == kArg)
+        return launch_block_sort<DT, K, true, kArg, 0, NETS>(a, kdst, vdst, sm, fl);
     if constexpr (DT == kF32) {
-        return launch_block_sort<DT, K, true, kNoVals>(a, kdst, vdst, sm, fl);
+        return launch_block_sort<DT, K, true, kNoVals, 0, NETS>(a, kdst, vdst, sm, fl);
     } else {
         switch (block_shape(a)) {
-            case 1: return launch_block_sort<DT, K, false, kNoVals, 1>(a, kdst, vdst, sm, fl);
-            case 2: return launch_block_sort<DT, K, false, kNoVals, 2>(a, kdst, vdst, sm, fl);
-            default: return launch_block_sort<DT, K, false, kNoVals, 0>(a, kdst, vdst, sm, fl);
+            case 1: return launch_block_sort<DT, K, false, kNoVals, 1, NETS>(a, kdst, vdst, sm, fl);
+            case 2: return launch_block_sort<DT, K, false, kNoVals, 2, NETS>(a, kdst, vdst, sm, fl);
+            default:
+                return launch_block_sort<DT, K, false, kNoVals, 0, NETS>(a, kdst, vdst, sm, fl);
         }
     }
 }
@@ -436,8 +441,9 @@ int run_sort(const SortArgs& a) {
                                (a.vmode != kVals || aligned(a.vin))));
 
     int cur = passes & 1;
-    int rc = a.leaf_k == 8 ? dispatch_block_sort<DT, 8>(a, kb[cur], vb[cur], sm, sorted_flag)
-                           : dispatch_block_sort<DT, 4>(a, kb[cur], vb[cur], sm, sorted_flag);
+    int rc = !a.nets         ? dispatch_block_sort<DT, 8, false>(a, kb[cur], vb[cur], sm, sorted_flag)
+             : a.leaf_k == 8 ? dispatch_block_sort<DT, 8, true>(a, kb[cur], vb[cur], sm, sorted_flag)
+                             : dispatch_block_sort<DT, 4, true>(a, kb[cur], vb[cur], sm, sorted_flag);
     if (rc) return rc;
     if (passes > 0) {
         const int64_t runs = (a.n + tile - 1) / tile;

@@ -311,6 +311,43 @@ def test_presorted_in_place_and_unaligned(orc, dtype):
         assert np.array_equal(host(po), np.arange(n, dtype=np.int32)), (runs, "argsort")
 
 
+@pytest.mark.parametrize("dtype", ["u32", "i32", "f32"])
+def test_classical_leaf(orc, dtype):
+    """No networks at all (merges from runs of one key: the classical merge
+    sort the paper measures against): keys, pairs and argsort against the
+    oracle's merge sort with the empty network set, over the first-sweep tile
+    shapes and both pass plans; the segmented sort refuses this leaf."""
+    rng = np.random.default_rng(41)
+    sizes = [0, 1, 2, 3, 7, 16, 17, 1023, 1025, 8191, 8193, 16385, 100003, 262145, 1_000_000]
+    for n in sizes:
+        x = make_keys(n, dtype, seed=n + 3)
+        ref = orc.sort(x, dtype=dtype, stable=True, config=0)
+        tunings = [None] if dtype == "f32" else [None, {"block_tile": 8192},
+                                                 {"block_tile": 32768}, {"merge_ways": 2}]
+        for t in tunings:
+            say(f"classical sort_keys dtype={dtype} n={n} tuning={t}")
+            y = host(msn.sort(gpu(x), leaf="classical", tuning=t))
+            assert np.array_equal(bits(y), bits(ref)), (n, t)
+        v = rng.integers(0, 2**32, n, dtype=np.uint32)
+        say(f"classical sort_pairs dtype={dtype} n={n}")
+        ko, vo = msn.sort_pairs(gpu(x), gpu(v), leaf="classical")
+        rk, rv = orc.sort(x, vals=v, dtype=dtype, stable=True, config=0)
+        assert np.array_equal(bits(host(ko)), bits(rk)), n
+        assert np.array_equal(host(vo), rv), n
+        _, po = msn.sort_pairs(gpu(x), None, leaf="classical")
+        _, rp = orc.sort(x, dtype=dtype, stable=True, config=0, want_perm=True)
+        assert np.array_equal(host(po).view(np.uint32), rp), n
+    if dtype != "f32":
+        for dist in ("sorted", "nearly"):
+            x = workloads.keys(1_000_000, dist, dtype, 5)
+            say(f"classical sort_keys dtype={dtype} 1e6 {dist}")
+            y = host(msn.sort(gpu(x), leaf="classical"))
+            assert np.array_equal(y, orc.sort(x, dtype=dtype, config=0)), dist
+    off = gpu(np.array([0, 5, 9], dtype=np.uint32))
+    with pytest.raises(msn.MsnError):
+        msn.segmented_sort(gpu(make_keys(9, dtype, seed=1)), off, leaf="classical")
+
+
 def test_unaligned_views(orc):
     # offsets by one element: 4-byte aligned, not 16-byte aligned
     n = 50001
