@@ -21,6 +21,8 @@
 // block and big work items (big segments first) from one atomic counter
 // until the lists are exhausted.  No workgroup ever waits for another, so any
 // grid size terminates.
+#include <algorithm>
+
 #include "block_tile.hpp"
 
 namespace msn {
@@ -791,6 +793,12 @@ int launch_seg_kernel(const SegArgs& a, const SegWs& w, uint32_t uni_len) {
         int sgrid = 0;
         static int cached_s = 0;
         if (int rc = fill_grid(skern, kSortThreads, 0, &cached_s, &sgrid)) return rc;
+        // a workgroup per possible run (capped at 256 resident rounds): a
+        // persistent loop over the list put each run's setup behind the
+        // previous run (2.72 against 2.44 ms on the 100,000-array batch);
+        // surplus workgroups find no entry and return
+        constexpr size_t kPer = SegRun<DT, K, STABLE>::kRun / kTile;
+        sgrid = (int)std::min<size_t>((w.max_tiles + kPer - 1) / kPer, (size_t)sgrid * 256);
         LaunchTimer timer("seg_tile_sort", a.n_total, a.stream);
         hipLaunchKernelGGL(skern, dim3(sgrid), dim3(kSortThreads), 0, a.stream, a.kin, a.vin,
                            a.kout, a.vout, w.wk, w.wv, a.offsets, uni_len, w.st, w.tiles);
