@@ -162,28 +162,37 @@ __device__ __forceinline__ bool m4_before(uint32_t ox, uint32_t ov, int k, int r
 
 // Keys of run `run` (len keys) before the sample, given that `cnt` of the
 // run's chunk samples precede it: the count lies in [(cnt-1) G + 1,
-// min(cnt G, len)].  Two rounds of 16 independent loads: first the last key
-// of each 16-key block, then the keys of the block holding the transition.
+// min(cnt G, len)].  Three rounds of independent loads narrow it: the last
+// key of each 64-key block (4 loads), of each 16-key block inside the block
+// found (4 loads), then the 16 keys of the block found.  Most of a chunk's
+// cache lines are never fetched (the search reads about two thirds of the
+// lines that reading every 16th key would).
 template <int DT>
 __device__ int64_t m4_key_count(const uint32_t* __restrict__ run, int64_t len, int64_t cnt,
                                 uint32_t ov, int k, int r) {
     constexpr int64_t G = kSampleChunk;
+    static_assert(G == 256, "three rounds of 64, 16 and 1 cover one chunk");
     if (cnt == 0) return 0;
     const int64_t A = (cnt - 1) * G + 1;
     const int64_t B = cnt * G < len ? cnt * G : len;
-    // indices are clamped to B - 1 (>= A - 1, a valid key) so that the 16
-    // loads of a round issue together; results past B are masked off
-    uint32_t x[16];
+    // indices are clamped to B - 1 (>= A - 1, a valid key) so that the loads
+    // of a round issue together; results past B are masked off
+    int64_t a = A;
 #pragma unroll
-    for (int m = 0; m < 16; ++m) {
-        const int64_t idx = A + 16 * m + 15;
-        x[m] = run[idx < B ? idx : B - 1];
+    for (int step = 64; step >= 16; step >>= 2) {
+        uint32_t x[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int64_t idx = a + step * m + step - 1;
+            x[m] = run[idx < B ? idx : B - 1];
+        }
+        int full = 0;
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            full += (int)((a + step * m + step - 1 < B) & m4_before(ord_key<DT>(x[m]), ov, k, r));
+        a += step * full;
     }
-    int full = 0;
-#pragma unroll
-    for (int m = 0; m < 16; ++m)
-        full += (int)((A + 16 * m + 15 < B) & m4_before(ord_key<DT>(x[m]), ov, k, r));
-    const int64_t a = A + 16 * full;
+    uint32_t x[16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) x[u] = run[a + u < B ? a + u : B - 1];
     int part = 0;
