@@ -168,10 +168,12 @@ def test_presorted_segments(orc, dtype, leaf):
             i = int(rng.integers(1, n - 1))
             seg[i - 1], seg[i] = seg[i], seg[i - 1]
         x[a:b] = seg
-    say(f"segmented presorted dtype={dtype} leaf={leaf} segments={lengths.shape[0]}")
-    y = msn.segmented_sort(gpu(x), gpu(off), leaf=leaf)
     ref = orc.segmented_sort(x, off, dtype=dtype, stable=True)
-    assert np.array_equal(bits(host(y)), bits(ref))
+    # default classes, then every array of two keys or more through the tiled path
+    for tun in (None, {"seg_lane_max": 1, "seg_wave_max": 1, "seg_block_max": 1}):
+        say(f"segmented presorted dtype={dtype} leaf={leaf} segments={lengths.shape[0]} {tun}")
+        y = msn.segmented_sort(gpu(x), gpu(off), leaf=leaf, tuning=tun)
+        assert np.array_equal(bits(host(y)), bits(ref)), tun
     say("segmented presorted, in place")
     t = gpu(x)
     msn.segmented_sort(t, gpu(off), out_keys=t, leaf=leaf)
