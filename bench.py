@@ -156,7 +156,8 @@ def bench_keys(args):
         x = torch.from_numpy(x_np).to(dev)
         steps = args.steps if dist == "random" else max(2, args.steps // 4)
         log(f"[bench] {dist}: warmup {args.warmup}, timing {steps} steps")
-        if dist == "random":
+        stats = {}
+        if dist == "random" and not args.graph_only:
             # eager steps with HIP events around every launch (per-kernel times)
             for _ in range(args.warmup):
                 plan.run(x)
@@ -165,8 +166,10 @@ def bench_keys(args):
             ms_eager, wall = time_steps(lambda: plan.run(x), steps, 0)
             stats = _lib.timing_read()
             _lib.timing_disable()
-        else:
+        elif not args.graph_only:
             ms_eager, wall = time_steps(lambda: plan.run(x), steps, args.warmup)
+        else:
+            ms_eager = None
         # the same sort captured once in a HIP graph and replayed (no launch gaps)
         if args.eager:
             ms = ms_eager
@@ -366,8 +369,49 @@ def bench_segmented(args):
     ok = bool(okd.all()) and x.to(torch.int64).sum().item() == o.sum().item()
     if not ok:
         raise SystemExit("[bench] segmented output check failed")
-    # baseline: one flat sort launch sequence per array, same GPU, eager
+    if args.no_per_array:
+        base_ms = base_wall = None
+    else:
+        base_ms, base_wall = _per_array_baseline(x, off_np, out, args)
+    # the dominant kernel: the block sort of every tile of the segments that
+    # take the tiled path (longer than seg_block_max, at most 8 tiles)
+    lens = (off_np[1:] - off_np[:-1]).astype(np.int64)
+    kk_ = 8 if args.leaf == "6To8" else 4
+    bmax = (tuning or {}).get("seg_block_max") or 1024 * kk_
+    tiled = int(lens[(lens > bmax) & (lens <= 8 * 1024 * kk_)].sum())
+    seg_roof = _roof(stats, "seg_tile_sort", lambda m: 8.0 * tiled) if tiled else None
+    if seg_roof:
+        seg_roof["kernel"] = "k_seg_tile_sort (every tile of the tiled segments, one launch)"
+    return {
+        "metric": "Gkeys/s, batched segmented sort: 100,000 int32 arrays, lengths log-uniform "
+                  "in [3, 65536], 30% presorted, 1 GPU",
+        "value": n / (ms / 1e3) / 1e9, "unit": "Gkeys/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "i32", "data": "synthetic",
+        "config": {"workload": "segmented_sort, one hipGraph replay per step", "segments": S,
+                   "keys": n, "leaf": args.leaf, "tuning": tuning},
+        "eager_ms_per_step": ms_eager,
+        "per_array_baseline": None if base_ms is None else {
+            "ms": base_ms, "wall_s": base_wall, "gkeys_per_s": n / (base_ms / 1e3) / 1e9,
+            "how": "one msn_sort_keys call per segment, eager, same GPU"},
+        "speedup_vs_per_array": None if base_ms is None else base_ms / ms,
+        "roofline": seg_roof,
+        "kernels_ms_per_step": {kk: vv["total_ms"] / args.steps for kk, vv in stats.items()},
+    }
+
+
+def _per_array_baseline(x, off_np, out, args):
+    """The batch sorted by one msn_sort_keys call per array (eager, same GPU);
+    returns (GPU ms, wall s) and checks the result against the batched sort."""
+    import ctypes
+
+    import torch
+
+    from paper_2503_05934_amd import _lib
+
     log("[bench] per-array baseline (one msn_sort_keys call per segment)")
+    dev = x.device
+    S = off_np.shape[0] - 1
     L = _lib.lib()
     wsb = _lib.sort_workspace_bytes(int((off_np[1:] - off_np[:-1]).max()), 1, False)
     ws2 = torch.empty(wsb, dtype=torch.uint8, device=dev)
@@ -393,31 +437,7 @@ def bench_segmented(args):
     base_wall = time.perf_counter() - t0
     if not torch.equal(out, out2):
         raise SystemExit("[bench] per-array baseline disagrees with the segmented sort")
-    # the dominant kernel: the block sort of every tile of the segments that
-    # take the tiled path (longer than seg_block_max, at most 8 tiles)
-    lens = (off_np[1:] - off_np[:-1]).astype(np.int64)
-    kk_ = 8 if args.leaf == "6To8" else 4
-    bmax = (tuning or {}).get("seg_block_max") or 1024 * kk_
-    tiled = int(lens[(lens > bmax) & (lens <= 8 * 1024 * kk_)].sum())
-    seg_roof = _roof(stats, "seg_tile_sort", lambda m: 8.0 * tiled) if tiled else None
-    if seg_roof:
-        seg_roof["kernel"] = "k_seg_tile_sort (every tile of the tiled segments, one launch)"
-    return {
-        "metric": "Gkeys/s, batched segmented sort: 100,000 int32 arrays, lengths log-uniform "
-                  "in [3, 65536], 30% presorted, 1 GPU",
-        "value": n / (ms / 1e3) / 1e9, "unit": "Gkeys/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "i32", "data": "synthetic",
-        "config": {"workload": "segmented_sort, one hipGraph replay per step", "segments": S,
-                   "keys": n, "leaf": args.leaf, "tuning": tuning},
-        "eager_ms_per_step": ms_eager,
-        "per_array_baseline": {"ms": base_ms, "wall_s": base_wall,
-                               "gkeys_per_s": n / (base_ms / 1e3) / 1e9,
-                               "how": "one msn_sort_keys call per segment, eager, same GPU"},
-        "speedup_vs_per_array": base_ms / ms,
-        "roofline": seg_roof,
-        "kernels_ms_per_step": {kk: vv["total_ms"] / args.steps for kk, vv in stats.items()},
-    }
+    return base_ms, base_wall
 
 
 def bench_rows(args):
@@ -601,6 +621,10 @@ def main():
                     help="time eager calls instead of replays of a captured HIP graph")
     ap.add_argument("--segments", type=int, default=100_000)
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-per-array", action="store_true",
+                    help="segmented: skip the one-call-per-array comparison")
+    ap.add_argument("--graph-only", action="store_true",
+                    help="keys: time graph replays only (no eager per-kernel event pass)")
     ap.add_argument("--retune", action="store_true", help="ignore the autotuner cache")
     ap.add_argument("--rows", type=int, default=4096)
     ap.add_argument("--cols", type=int, default=8192)

@@ -71,7 +71,16 @@ extern "C" {
 #define MSN_ERR_UNSUPPORTED (-6) /* valid request this build cannot serve     */
 
 /* flags for msn_segmented_sort */
-#define MSN_ARGSORT 1u /* vals_in must be NULL; vals_out receives segment-local indices */
+#define MSN_ARGSORT 1u     /* vals_in must be NULL; vals_out receives segment-local indices */
+#define MSN_DEBUG_CHECK 2u /* after sorting, check every segment's keys on the device      */
+
+/* Bits of the segmented sort's status word (msn_segmented_status_offset).
+ * The first three describe invalid offsets; they are checked on every call,
+ * with or without MSN_DEBUG_CHECK. */
+#define MSN_SEG_BAD_FIRST 1u  /* offsets[0] != 0                                  */
+#define MSN_SEG_BAD_ORDER 2u  /* some offsets[s + 1] < offsets[s]                 */
+#define MSN_SEG_BAD_LAST 4u   /* an entry above n_total, or the last != n_total   */
+#define MSN_SEG_BAD_RESULT 8u /* MSN_DEBUG_CHECK found a segment out of order     */
 
 /*
  * Optional tuning.  Pass NULL for the defaults.  A zero field means "default".
@@ -111,7 +120,9 @@ typedef struct {
 /*
  * Bytes of workspace msn_sort_keys (pairs = 0) or msn_sort_pairs (pairs = 1)
  * needs for n keys.  Writes *bytes; returns a status code.
+ * msn_sort_workspace_bytes is the same function under its earlier name.
  */
+int msn_sort_keys_workspace_bytes(int64_t n, int dtype, int pairs, size_t* bytes);
 int msn_sort_workspace_bytes(int64_t n, int dtype, int pairs, size_t* bytes);
 
 /*
@@ -120,7 +131,7 @@ int msn_sort_workspace_bytes(int64_t n, int dtype, int pairs, size_t* bytes);
  *   leaf               MSN_LEAF_* base-case network set.
  *   ws, ws_bytes       device workspace of at least
  *                      msn_sort_workspace_bytes(n, dtype, 0) bytes.
- * Paper: Sec. 3, Algorithm 1 (OptimizedMergeSort on the whole array).
+ * Paper: Sec. 3, Algorithm 1 applied to the whole array.
  */
 int msn_sort_keys(const void* keys_in, void* keys_out, int64_t n, int dtype, int leaf,
                   const msn_tuning* tuning, void* ws, size_t ws_bytes, void* stream);
@@ -146,14 +157,21 @@ int msn_segmented_sort_workspace_bytes(int64_t n_total, int64_t num_segments, in
                                        int pairs, size_t* bytes);
 
 /*
- * Sorts each segment independently, in one persistent kernel launch after a
- * small binning launch.  Segment s covers positions [offsets[s],
- * offsets[s+1]) of the key (and value) arrays.
+ * Sorts each segment independently.  Segment s covers positions
+ * [offsets[s], offsets[s+1]) of the key (and value) arrays.  The work is a
+ * fixed sequence of launches that never reads the offsets on the host: a
+ * clearing kernel, a binning kernel that also validates the offsets, a
+ * tile-sort launch for segments of a few tiles, one persistent launch for
+ * the rest (work queue), and up to three pairs of tile-merge launches.
  *   offsets        device uint32 array of num_segments + 1 entries, starting
- *                  at 0, non-decreasing, ending at n_total (not checked on the
- *                  device: a bad array gives undefined results).  NULL means
- *                  equal rows: n_total must be a multiple of num_segments and
- *                  every segment has n_total / num_segments keys.
+ *                  at 0, non-decreasing, ending at n_total.  The binning
+ *                  kernel checks these rules on every call; if one fails, the
+ *                  status word (msn_segmented_status_offset) gets the
+ *                  MSN_SEG_BAD_* bits, every later kernel returns at entry
+ *                  and the outputs are left unwritten: no access goes outside
+ *                  the arrays.  NULL means equal rows: n_total must be a
+ *                  multiple of num_segments and every segment has
+ *                  n_total / num_segments keys.
  *   vals_in/out    as msn_sort_pairs, per segment; both NULL sorts keys only.
  *                  With flags & MSN_ARGSORT, vals_in must be NULL and
  *                  vals_out[i] receives the index, local to its segment, of
@@ -166,6 +184,18 @@ int msn_segmented_sort(const void* keys_in, const uint32_t* vals_in, void* keys_
                        uint32_t* vals_out, const uint32_t* offsets, int64_t num_segments,
                        int64_t n_total, int dtype, int leaf, unsigned flags,
                        const msn_tuning* tuning, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Byte offset, inside the workspace of a msn_segmented_sort call with these
+ * sizes, of its uint32 status word: 0 when the offsets were valid (and, with
+ * MSN_DEBUG_CHECK, every segment came out in order), else MSN_SEG_BAD_* bits.
+ * The call writes it on the device in stream order; the caller reads it after
+ * the call's work has completed (the library itself never reads it back).
+ * Problem statement: Algorithm 1 sorts one array given by its bounds; each
+ * CSR segment is such an array, which the rules above make well-formed.
+ */
+int msn_segmented_status_offset(int64_t n_total, int64_t num_segments, int pairs,
+                                size_t* offset);
 
 /*
  * Backward of a row-wise sort y[r][i] = x[r][perm[r][i]]:

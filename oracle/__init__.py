@@ -6,9 +6,9 @@ arithmetic lives in ``oracle.c`` (plain C, single-threaded); this module only
 builds it with gcc and marshals numpy arrays through ctypes.
 
 Functions follow the paper (arXiv 2503.05934):
-  * :func:`sort` with ``algo="ms"``: Algorithm 1 (OptimizedMergeSort); the
+  * :func:`sort` with ``algo="ms"``: Algorithm 1 (merge sort with network base cases); the
     empty network set gives the classical merge sort of Eq. 1's baseline.
-  * :func:`sort` with ``algo="qs"``: Algorithm 2 (OptimizedQuickSort).
+  * :func:`sort` with ``algo="qs"``: Algorithm 2 (quick sort with network base cases).
   * :func:`config_mask`: the network sets of Table 3.
   * :func:`network`: the fixed 2..8-input networks used as base cases.
   * :func:`segmented_sort`, :func:`row_argsort`: the above per segment / row.

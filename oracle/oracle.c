@@ -6,19 +6,21 @@
  * the benchmark load this library; the product path never does.  Nothing in
  * here is shared with the HIP sources: the networks are generated from their
  * textbook definition at run time, comparisons use the plain dtype order, and
- * every sort is the paper's recursive algorithm written out.
+ * every sort follows the paper's top-down algorithm, its recursion kept on an
+ * explicit stack.
  *
  * Paper: Aly, Jensen, ElAarag, "Improving Merge Sort and Quick Sort
  * Performance by Utilizing AlphaDev's Sorting Networks as Base Cases",
  * ACMSE 2025 (arXiv 2503.05934).
  *
- *   - orc_sort(ORC_MS, ...)      Algorithm 1 (OptimizedMergeSort); with an
- *                                empty network set it is the classical merge
- *                                sort the paper measures against (Sec. 3,
- *                                Eq. 1).
- *   - orc_sort(ORC_QS, ...)      Algorithm 2 (OptimizedQuickSort) with
- *                                median-of-three pivots and Hoare partitioning
- *                                (Sec. 3); empty set = classical quick sort.
+ *   - orc_sort(ORC_MS, ...)      Algorithm 1 (merge sort with network base
+ *                                cases); with an empty network set it is the
+ *                                classical merge sort the paper measures
+ *                                against (Sec. 3, Eq. 1).
+ *   - orc_sort(ORC_QS, ...)      Algorithm 2 (quick sort with network base
+ *                                cases), median-of-three pivots and Hoare
+ *                                partitioning (Sec. 3); with an empty set it
+ *                                is the classical quick sort.
  *   - orc_config_mask            the network sets of Table 3.
  *   - orc_network                the fixed sorting networks for sizes 2..8
  *                                (the role AlphaDev's networks play, Sec. 1/3),
@@ -34,8 +36,9 @@
  *   - Merge takes from the left run on ties (stable).
  *   - "stable" sorts compare (key, original position) so that a network, which
  *     is not stable on keys alone, still yields the stable order.
- *   - MedianOfThree orders a[low], a[mid], a[high] in place and returns mid;
- *     HoarePartition is Hoare's 1962 scheme with the pivot value taken there.
+ *   - the median-of-three step orders the first, middle and last records in
+ *     place and pivots on the middle one; the partition is Hoare's 1962
+ *     scheme around that pivot value.
  *   - VarSortK (Table 3) handles every size up to K, so its set is {2..K}.
  */
 #include <math.h>
@@ -184,7 +187,8 @@ int orc_network(int n, int* pairs_out) {
     return g_net_len[n];
 }
 
-/* ApplySortingNetwork (Algorithm 1/2): sorts a[0..n-1] with the n-network. */
+/* The network base case of Algorithms 1 and 2: sorts a[0..n-1] with the
+ * n-input network. */
 static void apply_network(const order_t* o, rec_t* a, int n) {
     build_networks();
     for (int c = 0; c < g_net_len[n]; c++) {
@@ -246,6 +250,26 @@ int64_t orc_config_mask(const char* name) {
     return -1;
 }
 
+/* -------------------------------------------------------- shared pieces --- */
+
+/* Ranges are half-open: `count` records starting at index `start`. */
+typedef struct {
+    int64_t start;
+    int64_t count;
+    int merge_pending; /* merge sort only: both halves are sorted, merge them */
+} range_t;
+
+/* Deep enough for any count below 2^63: every split at least halves the
+ * larger part, and a range waits on the stack with at most one sibling and
+ * its own merge marker per level. */
+#define ORC_STACK 256
+
+/* The base case of Sec. 3: a range is handed to a sorting network exactly
+ * when its size is one of the sizes the configuration enables (Table 3). */
+static int network_takes(uint32_t netmask, int64_t count) {
+    return count >= 0 && count <= ORC_MAX_NET && ((netmask >> count) & 1u) != 0;
+}
+
 /* ----------------------------------------------------------- merge sort --- */
 
 typedef struct {
@@ -255,35 +279,52 @@ typedef struct {
     int64_t* leaf_hist; /* optional: elements handled by each network size */
 } ms_ctx;
 
-/* Merge(array, left, mid, right): the sorted runs a[left..mid] and
- * a[mid+1..right] become one sorted run; the left run wins ties. */
-static void merge_runs(ms_ctx* c, rec_t* a, int64_t left, int64_t mid, int64_t right) {
-    int64_t i = left, j = mid + 1, k = 0;
-    rec_t* s = c->scratch;
-    while (i <= mid && j <= right) {
-        if (rec_less(&c->ord, &a[j], &a[i]))
-            s[k++] = a[j++];
+/* The Merge step of Algorithm 1: the two sorted neighbours a[start ..
+ * start+nl) and a[start+nl .. start+total) become one sorted range.  An
+ * element of the right neighbour goes first only when it is strictly
+ * smaller, so equal elements keep their left-to-right order. */
+static void merge_neighbours(ms_ctx* c, rec_t* a, int64_t start, int64_t nl, int64_t total) {
+    const rec_t* left = a + start;
+    const rec_t* right = a + start + nl;
+    const int64_t nr = total - nl;
+    int64_t li = 0, ri = 0;
+    for (int64_t out = 0; out < total; out++) {
+        int from_right;
+        if (li == nl)
+            from_right = 1;
+        else if (ri == nr)
+            from_right = 0;
         else
-            s[k++] = a[i++];
+            from_right = rec_less(&c->ord, &right[ri], &left[li]);
+        c->scratch[out] = from_right ? right[ri++] : left[li++];
     }
-    while (i <= mid) s[k++] = a[i++];
-    while (j <= right) s[k++] = a[j++];
-    memcpy(&a[left], s, (size_t)k * sizeof(rec_t));
+    memcpy(a + start, c->scratch, (size_t)total * sizeof(rec_t));
 }
 
-/* Algorithm 1, OptimizedMergeSort(array, left, right). */
-static void optimized_merge_sort(ms_ctx* c, rec_t* a, int64_t left, int64_t right) {
-    int64_t size = right - left + 1;
-    if (size >= 0 && size <= ORC_MAX_NET && (c->netmask >> size) & 1u) {
-        apply_network(&c->ord, &a[left], (int)size);
-        if (c->leaf_hist) c->leaf_hist[size] += size;
-        return;
-    }
-    if (left < right) {
-        int64_t mid = left + (right - left) / 2;
-        optimized_merge_sort(c, a, left, mid);
-        optimized_merge_sort(c, a, mid + 1, right);
-        merge_runs(c, a, left, mid, right);
+/* Algorithm 1 (Sec. 3), top-down merge sort with network base cases, driven
+ * by an explicit stack instead of recursion.  A range whose size the
+ * configuration enables goes to that network.  Any other range of two or
+ * more records is cut at its midpoint, the left part taking the extra record
+ * of an odd count (the split the paper's midpoint index gives); once both
+ * parts are sorted they are merged.  Ranges of 0 or 1 records are done. */
+static void network_merge_sort(ms_ctx* c, rec_t* a, int64_t n) {
+    range_t stack[ORC_STACK];
+    int top = 0;
+    stack[top++] = (range_t){0, n, 0};
+    while (top > 0) {
+        range_t r = stack[--top];
+        const int64_t nl = r.count - r.count / 2;
+        if (r.merge_pending) {
+            merge_neighbours(c, a, r.start, nl, r.count);
+        } else if (network_takes(c->netmask, r.count)) {
+            apply_network(&c->ord, a + r.start, (int)r.count);
+            if (c->leaf_hist) c->leaf_hist[r.count] += r.count;
+        } else if (r.count >= 2) {
+            /* the merge runs after both parts, which sit above it */
+            stack[top++] = (range_t){r.start, r.count, 1};
+            stack[top++] = (range_t){r.start + nl, r.count - nl, 0};
+            stack[top++] = (range_t){r.start, nl, 0};
+        }
     }
 }
 
@@ -295,43 +336,64 @@ static void swap_rec(rec_t* x, rec_t* y) {
     *y = t;
 }
 
-/* MedianOfThree(array, low, high): puts a[low] <= a[mid] <= a[high] and
- * returns mid, whose element is the pivot. */
-static int64_t median_of_three(const order_t* o, rec_t* a, int64_t low, int64_t high) {
-    int64_t mid = low + (high - low) / 2;
-    if (rec_less(o, &a[mid], &a[low])) swap_rec(&a[mid], &a[low]);
-    if (rec_less(o, &a[high], &a[low])) swap_rec(&a[high], &a[low]);
-    if (rec_less(o, &a[high], &a[mid])) swap_rec(&a[high], &a[mid]);
-    return mid;
+/* Median-of-three pivot choice (Algorithm 2): the first, middle and last
+ * records of the range are put in order among themselves, and the middle
+ * one, now their median, is the pivot.  Returns a copy of it. */
+static rec_t pivot_of_three(const order_t* o, rec_t* a, int64_t first, int64_t last) {
+    const int64_t middle = first + (last - first) / 2;
+    if (rec_less(o, &a[middle], &a[first])) swap_rec(&a[middle], &a[first]);
+    if (rec_less(o, &a[last], &a[first])) swap_rec(&a[last], &a[first]);
+    if (rec_less(o, &a[last], &a[middle])) swap_rec(&a[last], &a[middle]);
+    return a[middle];
 }
 
-/* HoarePartition(array, low, high, pivotIndex): Hoare's scheme.  Returns j
- * with low <= j < high such that a[low..j] <= pivot <= a[j+1..high]. */
-static int64_t hoare_partition(const order_t* o, rec_t* a, int64_t low, int64_t high,
-                               int64_t pivot_index) {
-    rec_t pivot = a[pivot_index];
-    int64_t i = low - 1, j = high + 1;
+/* Hoare's partition (Algorithm 2; Hoare 1962): two scans move towards each
+ * other, the left one stopping at a record not below the pivot, the right
+ * one at a record not above it; such a pair is exchanged and both scans step
+ * on.  When they meet or cross, every record up to the right scan's position
+ * is no greater than the pivot and every record after it no smaller.
+ * Returns that position, which lies in [first, last). */
+static int64_t hoare_split(const order_t* o, rec_t* a, int64_t first, int64_t last,
+                           const rec_t* pivot) {
+    int64_t up = first, down = last;
     for (;;) {
-        do i++; while (rec_less(o, &a[i], &pivot));
-        do j--; while (rec_less(o, &pivot, &a[j]));
-        if (i >= j) return j;
-        swap_rec(&a[i], &a[j]);
+        while (rec_less(o, &a[up], pivot)) up++;
+        while (rec_less(o, pivot, &a[down])) down--;
+        if (up >= down) return down;
+        swap_rec(&a[up], &a[down]);
+        up++;
+        down--;
     }
 }
 
-/* Algorithm 2, OptimizedQuickSort(array, low, high). */
-static void optimized_quick_sort(const order_t* o, uint32_t netmask, rec_t* a,
-                                 int64_t low, int64_t high) {
-    int64_t size = high - low + 1;
-    if (size >= 0 && size <= ORC_MAX_NET && (netmask >> size) & 1u) {
-        apply_network(o, &a[low], (int)size);
-        return;
-    }
-    if (low < high) {
-        int64_t pivot_index = median_of_three(o, a, low, high);
-        int64_t p = hoare_partition(o, a, low, high, pivot_index);
-        optimized_quick_sort(o, netmask, a, low, p);
-        optimized_quick_sort(o, netmask, a, p + 1, high);
+/* Algorithm 2 (Sec. 3), quick sort with network base cases, driven by an
+ * explicit stack.  A range whose size the configuration enables goes to that
+ * network; any other range of two or more records is split by Hoare's
+ * partition around its median-of-three pivot, and both parts are sorted the
+ * same way. */
+static void network_quick_sort(const order_t* o, uint32_t netmask, rec_t* a, int64_t n) {
+    range_t stack[ORC_STACK];
+    int top = 0;
+    stack[top++] = (range_t){0, n, 0};
+    while (top > 0) {
+        range_t r = stack[--top];
+        if (network_takes(netmask, r.count)) {
+            apply_network(o, a + r.start, (int)r.count);
+        } else if (r.count >= 2) {
+            const int64_t last = r.start + r.count - 1;
+            const rec_t pivot = pivot_of_three(o, a, r.start, last);
+            const int64_t cut = hoare_split(o, a, r.start, last, &pivot);
+            /* smaller part on top: the stack stays logarithmic */
+            const range_t lo = {r.start, cut - r.start + 1, 0};
+            const range_t hi = {cut + 1, last - cut, 0};
+            if (lo.count < hi.count) {
+                stack[top++] = hi;
+                stack[top++] = lo;
+            } else {
+                stack[top++] = lo;
+                stack[top++] = hi;
+            }
+        }
     }
 }
 
@@ -342,9 +404,9 @@ static int sort_records(int algo, const order_t* o, uint32_t netmask, rec_t* r,
     if (n <= 0) return 0;
     if (algo == ORC_MS) {
         ms_ctx c = {*o, netmask, scratch, leaf_hist};
-        optimized_merge_sort(&c, r, 0, n - 1);
+        network_merge_sort(&c, r, n);
     } else {
-        optimized_quick_sort(o, netmask, r, 0, n - 1);
+        network_quick_sort(o, netmask, r, n);
     }
     return 0;
 }

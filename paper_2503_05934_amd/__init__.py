@@ -21,8 +21,8 @@ from . import _lib
 from ._lib import LEAVES, MsnError, Tuning, make_tuning
 
 __all__ = [
-    "sort", "sort_pairs", "segmented_sort", "sort_rows", "sort_backward", "DiffSort",
-    "MsnError", "Tuning", "LEAVES", "version", "SortPlan",
+    "sort", "sort_pairs", "segmented_sort", "segmented_status", "sort_rows", "sort_backward",
+    "DiffSort", "MsnError", "Tuning", "LEAVES", "version", "SortPlan",
 ]
 
 
@@ -35,11 +35,41 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
 
 
 def _check_keys(keys: torch.Tensor, ndim: int = 1):
-    if not keys.is_cuda:
+    if not isinstance(keys, torch.Tensor) or not keys.is_cuda:
         raise ValueError("keys must be a GPU tensor")
     if keys.dim() != ndim or not keys.is_contiguous():
         raise ValueError(f"keys must be a contiguous {ndim}-D tensor")
     return _lib.key_dtype(keys)
+
+
+def _check_buf(t, n: int, name: str, device, optional: bool = True):
+    """A caller-supplied array the library reads or writes n 32-bit words of:
+    it must hold exactly n contiguous 4-byte elements on the keys' device
+    (the C ABI sees only a pointer, so a short array would be overrun)."""
+    if t is None:
+        if optional:
+            return None
+        raise ValueError(f"{name} is required")
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a tensor")
+    if t.device != device:
+        raise ValueError(f"{name} must be on {device}, not {t.device}")
+    if t.numel() != n or t.element_size() != 4 or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous tensor of {n} 32-bit elements "
+                         f"(got {t.numel()} x {t.element_size()} bytes, "
+                         f"contiguous={t.is_contiguous()})")
+    return t
+
+
+def _check_workspace(ws, need: int, device):
+    if ws is None:
+        return None
+    if not isinstance(ws, torch.Tensor) or ws.device != device or not ws.is_contiguous():
+        raise ValueError(f"workspace must be a contiguous tensor on {device}")
+    if ws.numel() * ws.element_size() < need:
+        raise ValueError(f"workspace holds {ws.numel() * ws.element_size()} bytes, "
+                         f"{need} needed")
+    return ws
 
 
 def _tuning_ptr(tuning):
@@ -59,13 +89,14 @@ def sort(keys: torch.Tensor, *, leaf="6To8", tuning=None, out: torch.Tensor | No
     if tuning == "auto":
         from . import autotune
         tuning = autotune.tuned_sort_params(keys, pairs=False, leaf=leaf)
-    out = torch.empty_like(keys) if out is None else out
+    out = torch.empty_like(keys) if out is None else _check_buf(out, n, "out", keys.device)
     ws_bytes = _lib.sort_workspace_bytes(n, dt, False)
-    ws = _workspace(ws_bytes, keys.device) if workspace is None else workspace
+    ws = (_workspace(ws_bytes, keys.device) if workspace is None
+          else _check_workspace(workspace, ws_bytes, keys.device))
     t, tp = _tuning_ptr(tuning)
     _lib.check("msn_sort_keys", _lib.lib().msn_sort_keys(
         _lib.ptr(keys), _lib.ptr(out), n, dt, _lib.leaf_code(leaf), tp, _lib.ptr(ws),
-        ws.numel(), _lib.stream_handle(keys.device, stream)))
+        ws.numel() * ws.element_size(), _lib.stream_handle(keys.device, stream)))
     return out
 
 
@@ -77,36 +108,44 @@ def sort_pairs(keys: torch.Tensor, vals: torch.Tensor | None = None, *, leaf="6T
     if tuning == "auto":
         from . import autotune
         tuning = autotune.tuned_sort_params(keys, pairs=True, leaf=leaf)
-    if vals is not None:
-        if vals.shape != keys.shape or vals.element_size() != 4 or not vals.is_contiguous():
-            raise ValueError("vals must be a contiguous 32-bit tensor shaped like keys")
-    ok = torch.empty_like(keys) if out_keys is None else out_keys
+    _check_buf(vals, n, "vals", keys.device)
+    ok = (torch.empty_like(keys) if out_keys is None
+          else _check_buf(out_keys, n, "out_keys", keys.device))
     ov = (torch.empty(n, dtype=torch.int32, device=keys.device) if vals is None
-          else torch.empty_like(vals)) if out_vals is None else out_vals
+          else torch.empty_like(vals)) if out_vals is None else _check_buf(
+              out_vals, n, "out_vals", keys.device)
     ws_bytes = _lib.sort_workspace_bytes(n, dt, True)
-    ws = _workspace(ws_bytes, keys.device) if workspace is None else workspace
+    ws = (_workspace(ws_bytes, keys.device) if workspace is None
+          else _check_workspace(workspace, ws_bytes, keys.device))
     t, tp = _tuning_ptr(tuning)
     _lib.check("msn_sort_pairs", _lib.lib().msn_sort_pairs(
         _lib.ptr(keys), _lib.ptr(vals), _lib.ptr(ok), _lib.ptr(ov), n, dt, _lib.leaf_code(leaf),
-        tp, _lib.ptr(ws), ws.numel(), _lib.stream_handle(keys.device, stream)))
+        tp, _lib.ptr(ws), ws.numel() * ws.element_size(),
+        _lib.stream_handle(keys.device, stream)))
     return ok, ov
 
 
 def segmented_sort(keys: torch.Tensor, offsets: torch.Tensor | None = None,
                    vals: torch.Tensor | None = None, *, num_segments: int | None = None,
                    argsort: bool = False, leaf="6To8", tuning=None, out_keys=None,
-                   out_vals=None, workspace=None, stream=None):
+                   out_vals=None, workspace=None, stream=None, debug_check: bool = False):
     """Sort every CSR segment keys[offsets[s]:offsets[s+1]] independently.
 
     offsets: uint32/int32 GPU tensor of num_segments + 1 entries, or None with
     ``num_segments`` for equal-length rows.  Returns keys, or (keys, vals) when
     vals is given or argsort=True (segment-local int32 indices).
+    debug_check: validate the offsets on the device first (MSN_DEBUG_CHECK);
+    a bad array leaves the outputs untouched and is reported by
+    :func:`segmented_status` on the same workspace.
     """
     dt = _check_keys(keys)
     n = keys.numel()
     if offsets is not None:
-        if offsets.element_size() != 4 or not offsets.is_contiguous() or not offsets.is_cuda:
-            raise ValueError("offsets must be a contiguous 32-bit GPU tensor")
+        if (not isinstance(offsets, torch.Tensor) or offsets.element_size() != 4
+                or not offsets.is_contiguous() or offsets.device != keys.device
+                or offsets.numel() < 1):
+            raise ValueError("offsets must be a non-empty contiguous 32-bit tensor on the "
+                             "keys' device")
         num_segments = offsets.numel() - 1
     elif num_segments is None:
         raise ValueError("give offsets or num_segments")
@@ -117,21 +156,36 @@ def segmented_sort(keys: torch.Tensor, offsets: torch.Tensor | None = None,
         tuning = autotune.tuned_segmented_params(keys, offsets, num_segments=num_segments,
                                                  vals=vals, argsort=argsort, leaf=leaf)
     pairs = argsort or vals is not None
-    ok = torch.empty_like(keys) if out_keys is None else out_keys
+    _check_buf(vals, n, "vals", keys.device)
+    ok = (torch.empty_like(keys) if out_keys is None
+          else _check_buf(out_keys, n, "out_keys", keys.device))
     ov = None
     if pairs:
-        ov = out_vals if out_vals is not None else (
+        ov = _check_buf(out_vals, n, "out_vals", keys.device) if out_vals is not None else (
             torch.empty(n, dtype=torch.int32, device=keys.device) if vals is None
             else torch.empty_like(vals))
+    elif out_vals is not None:
+        raise ValueError("out_vals needs vals or argsort=True")
     ws_bytes = _lib.segmented_workspace_bytes(n, num_segments, dt, pairs)
-    ws = _workspace(ws_bytes, keys.device) if workspace is None else workspace
+    ws = (_workspace(ws_bytes, keys.device) if workspace is None
+          else _check_workspace(workspace, ws_bytes, keys.device))
     t, tp = _tuning_ptr(tuning)
-    flags = _lib.MSN_ARGSORT if argsort else 0
+    flags = (_lib.MSN_ARGSORT if argsort else 0) | (_lib.MSN_DEBUG_CHECK if debug_check else 0)
     _lib.check("msn_segmented_sort", _lib.lib().msn_segmented_sort(
         _lib.ptr(keys), _lib.ptr(vals), _lib.ptr(ok), _lib.ptr(ov), _lib.ptr(offsets),
-        num_segments, n, dt, _lib.leaf_code(leaf), flags, tp, _lib.ptr(ws), ws.numel(),
-        _lib.stream_handle(keys.device, stream)))
+        num_segments, n, dt, _lib.leaf_code(leaf), flags, tp, _lib.ptr(ws),
+        ws.numel() * ws.element_size(), _lib.stream_handle(keys.device, stream)))
     return (ok, ov) if pairs else ok
+
+
+def segmented_status(workspace: torch.Tensor, n_total: int, num_segments: int,
+                     pairs: bool = False) -> int:
+    """The status word a segmented_sort call left in ``workspace``: 0 when the
+    offsets were valid, else MSN_SEG_BAD_* bits (see include/msn.h).  Waits for
+    the device."""
+    off = _lib.segmented_status_offset(n_total, num_segments, pairs)
+    word = workspace.view(torch.uint8)[off:off + 4]
+    return int(word.view(torch.int32).item()) & 0xffffffff
 
 
 def sort_rows(x: torch.Tensor, *, leaf="6To8", tuning=None, stream=None):
@@ -153,10 +207,18 @@ def sort_backward(grad_out: torch.Tensor, perm: torch.Tensor, *, out=None, strea
         raise TypeError("grad_out must be float32 and perm int32")
     if grad_out.shape != perm.shape or grad_out.dim() != 2:
         raise ValueError("grad_out and perm must be 2-D and of one shape")
+    if not grad_out.is_cuda or perm.device != grad_out.device:
+        raise ValueError("grad_out and perm must be on one GPU")
     g = grad_out.contiguous()
     p = perm.contiguous()
-    gi = torch.empty_like(g) if out is None else out
     rows, cols = g.shape
+    if out is None:
+        gi = torch.empty_like(g)
+    else:
+        _check_buf(out, rows * cols, "out", g.device)
+        if out.dtype != torch.float32:
+            raise TypeError("out must be float32")
+        gi = out
     _lib.check("msn_sort_backward", _lib.lib().msn_sort_backward(
         _lib.ptr(g), _lib.ptr(p), _lib.ptr(gi), rows, cols,
         _lib.stream_handle(g.device, stream)))
@@ -203,6 +265,12 @@ class SortPlan:
         self.ws = _workspace(_lib.sort_workspace_bytes(n, self.dt, self.pairs), device)
 
     def run(self, keys: torch.Tensor, vals: torch.Tensor | None = None, stream=None):
+        if (not isinstance(keys, torch.Tensor) or keys.dtype != self.out.dtype
+                or keys.dim() != 1):
+            raise ValueError(f"keys must be a 1-D {self.out.dtype} tensor")
+        _check_buf(keys, self.n, "keys", self.out.device)
+        if self.pairs and not self.argsort:
+            _check_buf(vals, self.n, "vals", self.out.device, optional=False)
         st = _lib.stream_handle(keys.device, stream)
         if self.pairs:
             rc = _lib.lib().msn_sort_pairs(

@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libmsn.so")
 MSN_U32, MSN_I32, MSN_F32 = 0, 1, 2
 MSN_LEAF_6TO8, MSN_LEAF_3TO5, MSN_LEAF_NONE = 0, 1, 2
 MSN_ARGSORT = 1
+MSN_DEBUG_CHECK = 2
+MSN_SEG_BAD_FIRST, MSN_SEG_BAD_ORDER, MSN_SEG_BAD_LAST, MSN_SEG_BAD_RESULT = 1, 2, 4, 8
 
 LEAVES = {"6To8": MSN_LEAF_6TO8, "3To5": MSN_LEAF_3TO5, "classical": MSN_LEAF_NONE}
 _DTYPES = {torch.uint32: MSN_U32, torch.int32: MSN_I32, torch.float32: MSN_F32}
@@ -79,6 +81,10 @@ def lib():
     L.msn_status_string.restype = ctypes.c_char_p
     L.msn_sort_workspace_bytes.argtypes = [I64, I, I, SZ]
     L.msn_sort_workspace_bytes.restype = I
+    L.msn_sort_keys_workspace_bytes.argtypes = [I64, I, I, SZ]
+    L.msn_sort_keys_workspace_bytes.restype = I
+    L.msn_segmented_status_offset.argtypes = [I64, I64, I, SZ]
+    L.msn_segmented_status_offset.restype = I
     L.msn_sort_keys.argtypes = [P, P, I64, I, I, P, P, ctypes.c_size_t, P]
     L.msn_sort_keys.restype = I
     L.msn_sort_pairs.argtypes = [P, P, P, P, I64, I, I, P, P, ctypes.c_size_t, P]
@@ -129,8 +135,15 @@ def stream_handle(device: torch.device, stream=None):
 
 def sort_workspace_bytes(n: int, dtype: int, pairs: bool) -> int:
     out = ctypes.c_size_t(0)
-    check("msn_sort_workspace_bytes",
-          lib().msn_sort_workspace_bytes(n, dtype, int(pairs), ctypes.byref(out)))
+    check("msn_sort_keys_workspace_bytes",
+          lib().msn_sort_keys_workspace_bytes(n, dtype, int(pairs), ctypes.byref(out)))
+    return out.value
+
+
+def segmented_status_offset(n_total: int, num_segments: int, pairs: bool) -> int:
+    out = ctypes.c_size_t(0)
+    check("msn_segmented_status_offset",
+          lib().msn_segmented_status_offset(n_total, num_segments, int(pairs), ctypes.byref(out)))
     return out.value
 
 

@@ -90,6 +90,15 @@ bool bad_overlap(const void* a, const void* b, int64_t n) {
     return x < y + len && y < x + len;
 }
 
+// Two ranges of n words that share any word (equal starts included): the
+// pairs that must stay apart even for in-place calls (a key array and a value
+// array).
+bool any_overlap(const void* a, const void* b, int64_t n) {
+    if (!a || !b) return false;
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b, len = (uintptr_t)n * 4;
+    return x < y + len && y < x + len;
+}
+
 int merge_tile_of(const msn_tuning* t, int* out) {
     int mt = t && t->merge_tile ? t->merge_tile : msn::kDefaultMergeTile;
     if (mt != 2048 && mt != 4096 && mt != 8192) return MSN_ERR_CONFIG;
@@ -140,7 +149,8 @@ int sort_common(const void* keys_in, const uint32_t* vals_in, void* keys_out, ui
         misaligned(ws))
         return MSN_ERR_UNSUPPORTED;
     if (bad_overlap(keys_in, keys_out, n) || bad_overlap(vals_in, vals_out, n) ||
-        (pairs && (bad_overlap(keys_out, vals_out, n) || keys_out == (void*)vals_out)))
+        (pairs && (bad_overlap(keys_out, vals_out, n) || keys_out == (void*)vals_out)) ||
+        any_overlap(keys_in, vals_out, n) || any_overlap(vals_in, keys_out, n))
         return MSN_ERR_SIZE;
     const int vmode = !pairs ? msn::kNoVals : vals_in ? msn::kVals : msn::kArg;
     const size_t need = msn::sort_ws_bytes(n, vmode != msn::kNoVals);
@@ -224,12 +234,16 @@ const char* msn_status_string(int status) {
     }
 }
 
-int msn_sort_workspace_bytes(int64_t n, int dtype, int pairs, size_t* bytes) {
+int msn_sort_keys_workspace_bytes(int64_t n, int dtype, int pairs, size_t* bytes) {
     if (!bytes) return MSN_ERR_NULL;
     if (!valid_dtype(dtype)) return MSN_ERR_DTYPE;
     if (n < 0 || n > kMaxN) return MSN_ERR_SIZE;
     *bytes = msn::sort_ws_bytes(n, pairs != 0);
     return MSN_OK;
+}
+
+int msn_sort_workspace_bytes(int64_t n, int dtype, int pairs, size_t* bytes) {
+    return msn_sort_keys_workspace_bytes(n, dtype, pairs, bytes);
 }
 
 int msn_sort_keys(const void* keys_in, void* keys_out, int64_t n, int dtype, int leaf,
@@ -263,7 +277,7 @@ int msn_segmented_sort(const void* keys_in, const uint32_t* vals_in, void* keys_
     const int k = leaf_keys(leaf);
     if (!k) return MSN_ERR_CONFIG;
     if (leaf == MSN_LEAF_NONE) return MSN_ERR_UNSUPPORTED;  // flat sorts only
-    if (flags & ~MSN_ARGSORT) return MSN_ERR_CONFIG;
+    if (flags & ~(MSN_ARGSORT | MSN_DEBUG_CHECK)) return MSN_ERR_CONFIG;
     const bool argsort = (flags & MSN_ARGSORT) != 0;
     if (argsort && vals_in) return MSN_ERR_CONFIG;
     if (!argsort && !vals_in && vals_out) return MSN_ERR_CONFIG;
@@ -291,7 +305,9 @@ int msn_segmented_sort(const void* keys_in, const uint32_t* vals_in, void* keys_
         misaligned(ws) || misaligned(offsets))
         return MSN_ERR_UNSUPPORTED;
     if (bad_overlap(keys_in, keys_out, n_total) || bad_overlap(vals_in, vals_out, n_total) ||
-        (vals_out && (bad_overlap(keys_out, vals_out, n_total) || keys_out == (void*)vals_out)))
+        (vals_out && (bad_overlap(keys_out, vals_out, n_total) || keys_out == (void*)vals_out)) ||
+        any_overlap(keys_in, vals_out, n_total) || any_overlap(vals_in, keys_out, n_total) ||
+        any_overlap(offsets, keys_out, n_total) || any_overlap(offsets, vals_out, n_total))
         return MSN_ERR_SIZE;
     const int vmode = argsort ? msn::kArg : vals_in ? msn::kVals : msn::kNoVals;
     const size_t need = msn::seg_ws_bytes(n_total, num_segments, vmode != msn::kNoVals);
@@ -313,7 +329,17 @@ int msn_segmented_sort(const void* keys_in, const uint32_t* vals_in, void* keys_
                    ws,
                    ws_bytes,
                    static_cast<hipStream_t>(stream)};
+    a.debug_check = (flags & MSN_DEBUG_CHECK) != 0;
     return msn::launch_segmented(a);
+}
+
+int msn_segmented_status_offset(int64_t n_total, int64_t num_segments, int pairs,
+                                size_t* offset) {
+    if (!offset) return MSN_ERR_NULL;
+    if (n_total < 0 || n_total > kMaxN || num_segments < 0 || num_segments > kMaxN)
+        return MSN_ERR_SIZE;
+    *offset = msn::seg_status_offset(n_total, num_segments, pairs != 0);
+    return MSN_OK;
 }
 
 int msn_sort_backward(const float* grad_out, const int32_t* perm, float* grad_in, int64_t rows,

@@ -56,6 +56,7 @@ struct SegArgs {
     void* ws;
     size_t ws_bytes;
     hipStream_t stream;
+    int debug_check = 0;      // MSN_DEBUG_CHECK: verify every segment after sorting
 };
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -101,6 +102,8 @@ inline size_t sort_ws_bytes(int64_t n, bool vals) {
 }
 
 size_t seg_ws_bytes(int64_t n_total, int64_t num_segments, bool vals);
+// Byte offset of the segmented sort's status word inside its workspace.
+size_t seg_status_offset(int64_t n_total, int64_t num_segments, bool vals);
 
 // Raises a kernel's dynamic-LDS limit to `bytes` (needed beyond 64 KiB); done
 // once per kernel and process.  Returns a hipError_t value.

@@ -39,8 +39,9 @@ enum SegClass : int {
 struct SegState {
     uint32_t count[8];
     uint32_t head;
-    uint32_t tiles;  // entries of the tile list
-    uint32_t pad[6];
+    uint32_t tiles;   // entries of the tile list
+    uint32_t status;  // MSN_SEG_BAD_* bits found in this call (0 = offsets valid)
+    uint32_t pad[5];
 };
 
 // Segments of up to this many block-sort tiles take the tiled path (at most
@@ -112,44 +113,97 @@ __global__ void k_seg_init(SegState* st) {
 // Classes (and tiles) are counted per workgroup in LDS first, so each
 // workgroup makes one global atomic per class instead of one per segment (a
 // few global counters shared by every segment would serialise).
+// The same pass validates the offsets: offsets[0] == 0, no entry below its
+// predecessor, and the last equal to n_total (equivalently every entry within
+// n_total).  A segment whose own pair of offsets breaks a rule is not binned,
+// and the status word records which rule broke; every later kernel of the
+// call returns at entry when it is set, so a bad array never leads to an
+// access outside the key, value, list or tile arrays.  Valid offsets cannot
+// overflow the tile list; the bound check on it covers the invalid case
+// (where the binned segments may overlap) until the status word stops the
+// call.
 __global__ __launch_bounds__(256) void k_seg_bin(const uint32_t* __restrict__ offsets,
-                                                 int64_t num_segments, uint32_t uni_len,
-                                                 int lane_max, int wave_max, int block_max,
-                                                 uint32_t tile, SegState* st,
+                                                 int64_t num_segments, int64_t n_total,
+                                                 uint32_t uni_len, int lane_max, int wave_max,
+                                                 int block_max, uint32_t tile, SegState* st,
                                                  uint32_t* __restrict__ lists,
-                                                 uint2* __restrict__ tiles) {
+                                                 uint2* __restrict__ tiles, uint32_t max_tiles) {
     __shared__ uint32_t cnt[kNumClasses + 1], base[kNumClasses + 1];  // + the tile count
+    __shared__ uint32_t bad;
     const int tid = threadIdx.x;
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + tid;
     if (tid <= kNumClasses) cnt[tid] = 0u;
+    if (tid == 0) bad = 0u;
     __syncthreads();
     int cls = -1;
     uint32_t pos = 0, nt = 0, tpos = 0;
     if (s < num_segments) {
         uint32_t off, len;
-        seg_bounds(offsets, (uint32_t)s, uni_len, off, len);
-        if (len <= (uint32_t)lane_max) cls = kCLane;
-        else if (len <= (uint32_t)wave_max) cls = kCWave;
-        else if (len <= (uint32_t)block_max) cls = kCBlock;
-        else if (len <= (uint32_t)kSegTiledMax * tile) cls = kCTiled;
-        else cls = kCBig;
-        if (cls == kCTiled) {
-            nt = (len + tile - 1) / tile;
-            tpos = atomicAdd(&cnt[kNumClasses], nt);
+        uint32_t err = 0u;
+        if (offsets) {
+            const uint32_t a = offsets[s], b = offsets[s + 1];
+            if (s == 0 && a != 0u) err |= MSN_SEG_BAD_FIRST;
+            if (b < a) err |= MSN_SEG_BAD_ORDER;
+            if ((int64_t)b > n_total || (s == num_segments - 1 && (int64_t)b != n_total))
+                err |= MSN_SEG_BAD_LAST;
+            off = a;
+            len = b - a;
         } else {
-            pos = atomicAdd(&cnt[cls], 1u);
+            off = (uint32_t)s * uni_len;
+            len = uni_len;
         }
+        if (err) {
+            atomicOr(&bad, err);
+        } else {
+            if (len <= (uint32_t)lane_max) cls = kCLane;
+            else if (len <= (uint32_t)wave_max) cls = kCWave;
+            else if (len <= (uint32_t)block_max) cls = kCBlock;
+            else if (len <= (uint32_t)kSegTiledMax * tile) cls = kCTiled;
+            else cls = kCBig;
+            if (cls == kCTiled) {
+                nt = (len + tile - 1) / tile;
+                tpos = atomicAdd(&cnt[kNumClasses], nt);
+            } else {
+                pos = atomicAdd(&cnt[cls], 1u);
+            }
+        }
+        (void)off;
     }
     __syncthreads();
     if (tid < kNumClasses && cnt[tid] != 0u) base[tid] = atomicAdd(&st->count[tid], cnt[tid]);
     if (tid == kNumClasses && cnt[tid] != 0u) base[tid] = atomicAdd(&st->tiles, cnt[tid]);
+    if (tid == kNumClasses + 1 && bad != 0u) atomicOr(&st->status, bad);
     __syncthreads();
     if (cls == kCTiled) {
-        for (uint32_t c = 0; c < nt; ++c)
-            tiles[base[kNumClasses] + tpos + c] = make_uint2((uint32_t)s, c);
+        for (uint32_t c = 0; c < nt; ++c) {
+            const uint32_t e = base[kNumClasses] + tpos + c;
+            if (e < max_tiles) tiles[e] = make_uint2((uint32_t)s, c);
+        }
     } else if (cls >= 0) {
         lists[(int64_t)cls * num_segments + base[cls] + pos] = (uint32_t)s;
     }
+}
+
+// MSN_DEBUG_CHECK: after the sort, one wavefront per segment checks that the
+// segment's keys are in order and records MSN_SEG_BAD_RESULT otherwise (a
+// fault of the library, not of the caller).
+template <int DT>
+__global__ __launch_bounds__(256) void k_seg_verify(const uint32_t* __restrict__ kout,
+                                                    const uint32_t* __restrict__ offsets,
+                                                    int64_t num_segments, uint32_t uni_len,
+                                                    SegState* st) {
+    if (st->status) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+    int bad = 0;
+    for (int64_t s = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+         s < num_segments; s += waves) {
+        const uint32_t off = offsets ? offsets[s] : (uint32_t)s * uni_len;
+        const uint32_t len = offsets ? offsets[s + 1] - off : uni_len;
+        for (uint32_t i = 1 + (uint32_t)lane; i < len; i += kWave)
+            bad |= (int)(ord_key<DT>(kout[off + i]) < ord_key<DT>(kout[off + i - 1]));
+    }
+    if (bad) atomicOr(&st->status, (uint32_t)MSN_SEG_BAD_RESULT);
 }
 
 // ------------------------------------------------------------ lane tasks ---
@@ -555,6 +609,7 @@ __global__ __launch_bounds__(kBlockThreads, STABLE ? 4 : 6) void k_segmented(
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t s_item;
     const int tid = threadIdx.x;
+    if (st->status) return;
 
     const uint32_t n_lane = st->count[kCLane];
     const uint32_t n_wave = st->count[kCWave];
@@ -633,6 +688,7 @@ void k_seg_tile_sort(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, u
     __shared__ __align__(16) unsigned char smem[Tr::kLdsBytes];
     constexpr int kRun = R::kRun;
     constexpr uint32_t kPer = R::kRun / R::kListTile;  // list tiles per run
+    if (st->status) return;
     const uint32_t n = st->tiles;
     for (uint32_t e = blockIdx.x; e < n; e += gridDim.x) {
         const uint2 tc = tiles[e];
@@ -704,7 +760,7 @@ __global__ __launch_bounds__(256) void k_seg_tile_part(
     const uint32_t* __restrict__ offsets, uint32_t uni_len, const SegState* st,
     const uint2* __restrict__ tiles, int32_t* __restrict__ part, int tile, int run, int p) {
     const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= st->tiles) return;
+    if (st->status || e >= st->tiles) return;
     SegTilePass g;
     if (!seg_tile_pass<VALS>(tiles[e], p, tile, run, offsets, uni_len, kout, vout, wk, wv, g))
         return;
@@ -723,6 +779,7 @@ __global__ __launch_bounds__(kBlockThreads, DT == kF32 ? 1 : 6) void k_seg_tile_
     constexpr int kTile = KPT * kBlockThreads;
     uint32_t* sk = reinterpret_cast<uint32_t*>(smem);
     uint32_t* sv = sk + seg_merge_words(kTile);
+    if (st->status) return;
     const uint32_t n = st->tiles;
     for (uint32_t e = blockIdx.x; e < n; e += gridDim.x) {
         SegTilePass g;
@@ -881,21 +938,52 @@ int launch_segmented(const SegArgs& a) {
     {
         LaunchTimer timer("seg_bin", a.num_segments, a.stream);
         hipLaunchKernelGGL(k_seg_bin, dim3((unsigned)((a.num_segments + 255) / 256)), dim3(256),
-                           0, a.stream, a.offsets, a.num_segments, uni_len, a.lane_max,
-                           a.wave_max, a.block_max, tile, w.st, w.lists, w.tiles);
+                           0, a.stream, a.offsets, a.num_segments, a.n_total, uni_len,
+                           a.lane_max, a.wave_max, a.block_max, tile, w.st, w.lists, w.tiles,
+                           (uint32_t)w.max_tiles);
     }
     if (int rc = (int)hipGetLastError()) return rc;
+    int rc = 0;
     switch (a.dtype) {
         case kU32:
-            return a.leaf_k == 8 ? dispatch_seg<kU32, 8>(a, w, uni_len)
-                                 : dispatch_seg<kU32, 4>(a, w, uni_len);
+            rc = a.leaf_k == 8 ? dispatch_seg<kU32, 8>(a, w, uni_len)
+                               : dispatch_seg<kU32, 4>(a, w, uni_len);
+            break;
         case kI32:
-            return a.leaf_k == 8 ? dispatch_seg<kI32, 8>(a, w, uni_len)
-                                 : dispatch_seg<kI32, 4>(a, w, uni_len);
+            rc = a.leaf_k == 8 ? dispatch_seg<kI32, 8>(a, w, uni_len)
+                               : dispatch_seg<kI32, 4>(a, w, uni_len);
+            break;
         default:
-            return a.leaf_k == 8 ? dispatch_seg<kF32, 8>(a, w, uni_len)
-                                 : dispatch_seg<kF32, 4>(a, w, uni_len);
+            rc = a.leaf_k == 8 ? dispatch_seg<kF32, 8>(a, w, uni_len)
+                               : dispatch_seg<kF32, 4>(a, w, uni_len);
+            break;
     }
+    if (rc || !a.debug_check) return rc;
+    const unsigned vgrid = (unsigned)std::min<int64_t>((a.num_segments + 3) / 4, 4096);
+    {
+        LaunchTimer timer("seg_verify", a.n_total, a.stream);
+        switch (a.dtype) {
+            case kU32:
+                hipLaunchKernelGGL(k_seg_verify<kU32>, dim3(vgrid), dim3(256), 0, a.stream, a.kout,
+                                   a.offsets, a.num_segments, uni_len, w.st);
+                break;
+            case kI32:
+                hipLaunchKernelGGL(k_seg_verify<kI32>, dim3(vgrid), dim3(256), 0, a.stream, a.kout,
+                                   a.offsets, a.num_segments, uni_len, w.st);
+                break;
+            default:
+                hipLaunchKernelGGL(k_seg_verify<kF32>, dim3(vgrid), dim3(256), 0, a.stream, a.kout,
+                                   a.offsets, a.num_segments, uni_len, w.st);
+                break;
+        }
+    }
+    return (int)hipGetLastError();
+}
+
+size_t seg_status_offset(int64_t n_total, int64_t num_segments, bool vals) {
+    const size_t nk = align_up((size_t)n_total * 4, 256);
+    const size_t nl = align_up((size_t)num_segments * 4 * kNumClasses, 256);
+    return nk + (vals ? nk : 0) + nl + offsetof(SegState, status);
 }
 
 }  // namespace msn

@@ -122,3 +122,48 @@ def test_workspace_queries(lib):
     out = ctypes.c_size_t()
     assert lib.msn_sort_workspace_bytes(-5, 0, 0, ctypes.byref(out)) == -2
     assert lib.msn_sort_workspace_bytes(5, 9, 0, ctypes.byref(out)) == -3
+
+
+def test_values_may_not_overlap_the_other_array(lib):
+    # a key array and a value array never share words, in-place calls included
+    f = lib.msn_sort_pairs
+    V = ctypes.c_void_p(5 << 20)
+    assert f(FAKE, None, FAKE2, FAKE, 10, 0, 0, None, ctypes.c_void_p(9 << 20), 1 << 30, None) == -2
+    assert f(FAKE, FAKE2, FAKE2, V, 10, 0, 0, None, ctypes.c_void_p(9 << 20), 1 << 30, None) == -2
+    assert f(FAKE, V, FAKE, ctypes.c_void_p((5 << 20) + 8), 10, 0, 0, None,
+             ctypes.c_void_p(9 << 20), 1 << 30, None) == -2          # vals partly in place
+    g = lib.msn_segmented_sort
+    ws = ctypes.c_void_p(9 << 20)
+    # offsets inside the key output
+    assert g(FAKE, None, FAKE2, None, ctypes.c_void_p((3 << 20) + 40), 10, 100, 1, 0, 0, None,
+             ws, 1 << 30, None) == -2
+    # keys_in overlapping vals_out
+    assert g(FAKE, None, FAKE2, FAKE, ctypes.c_void_p(7 << 20), 10, 100, 1, 0, 1, None,
+             ws, 1 << 30, None) == -2
+
+
+def test_workspace_query_names_agree(lib):
+    a, b = ctypes.c_size_t(), ctypes.c_size_t()
+    for n, pairs in ((0, 0), (1000, 0), (1 << 20, 1), ((1 << 31) - 1, 1)):
+        assert lib.msn_sort_keys_workspace_bytes(n, 0, pairs, ctypes.byref(a)) == 0
+        assert lib.msn_sort_workspace_bytes(n, 0, pairs, ctypes.byref(b)) == 0
+        assert a.value == b.value
+
+
+def test_segmented_status_offset(lib):
+    from paper_2503_05934_amd import _lib
+    for n, S, pairs in ((100, 10, False), (651_672_148, 100_000, False), (33_554_432, 4096, True)):
+        off = _lib.segmented_status_offset(n, S, pairs)
+        ws = _lib.segmented_workspace_bytes(n, S, 0, pairs)
+        assert off % 4 == 0 and off + 4 <= ws
+    out = ctypes.c_size_t()
+    assert lib.msn_segmented_status_offset(-1, 3, 0, ctypes.byref(out)) == -2
+    assert lib.msn_segmented_status_offset(3, 3, 0, None) == -1
+
+
+def test_segmented_accepts_debug_check_flag(lib):
+    f = lib.msn_segmented_sort
+    # MSN_ARGSORT | MSN_DEBUG_CHECK is a valid flag set (rejected later for the NULL workspace)
+    assert f(FAKE, None, FAKE2, ctypes.c_void_p(7 << 20), FAKE, 10, 100, 1, 0, 3, None, None, 0,
+             None) == -5
+    assert f(FAKE, None, FAKE2, None, FAKE, 10, 100, 1, 0, 2 | 4, None, None, 0, None) == -4

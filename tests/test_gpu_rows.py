@@ -82,3 +82,15 @@ def test_backward_skips_out_of_range_indices():
     say("sort_backward with an out-of-range index")
     gi = host(msn.sort_backward(g, p))
     assert list(gi[0, 1:]) == [6, 5, 4, 3, 2, 1, 0]
+
+
+def test_backward_tall_narrow_rows(orc):
+    """More rows than one workgroup per row can launch (2^24 + 1 rows of 4
+    columns: 2^32 + 256 threads at 256 per row): the row loop covers them."""
+    rows, cols = (1 << 24) + 1, 4
+    rng = np.random.default_rng(5)
+    g = rng.standard_normal((rows, cols)).astype(np.float32)
+    p = np.argsort(rng.random((rows, cols)), axis=1).astype(np.int32)
+    say(f"sort_backward {rows}x{cols}")
+    gi = host(msn.sort_backward(gpu(g), gpu(p)))
+    assert np.array_equal(bits(gi), bits(orc.gather_backward(g, p)))

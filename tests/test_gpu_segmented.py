@@ -1,4 +1,4 @@
-"""Segmented sort (one persistent launch) against the oracle, bit-exact."""
+"""Segmented sort (binning, tile-sort, persistent and tile-merge launches) against the oracle, bit-exact."""
 import itertools
 
 import numpy as np
@@ -240,3 +240,88 @@ def test_hip_graph_replays_match_eager(orc):
         g.replay()
         torch.cuda.synchronize()
         assert np.array_equal(host(out), ref), r
+
+
+@pytest.mark.parametrize("debug_check", [False, True])
+def test_invalid_offsets_set_status_and_leave_outputs(debug_check):
+    """Offsets that break the CSR rules but stay inside the arrays (entries
+    non-decreasing and at most n_total, so no access could leave the arrays
+    even if the check were missing): the call reports the broken rule in its
+    status word and writes nothing."""
+    from paper_2503_05934_amd import _lib
+    n = 1000
+    x = seg_keys(n, "i32", seed=11)
+    cases = [(np.array([0, 300, 700], np.uint32), _lib.MSN_SEG_BAD_LAST),
+             (np.array([5, 300, 1000], np.uint32), _lib.MSN_SEG_BAD_FIRST),
+             (np.array([0, 0, 999, 999], np.uint32), _lib.MSN_SEG_BAD_LAST)]
+    for off, bit in cases:
+        S = len(off) - 1
+        ws = torch.empty(_lib.segmented_workspace_bytes(n, S, 1, False), dtype=torch.uint8,
+                         device="cuda:0")
+        ws.fill_(0xAB)
+        out = torch.full((n,), 7, dtype=torch.int32, device="cuda:0")
+        say(f"invalid offsets {off.tolist()} debug_check={debug_check}")
+        msn.segmented_sort(gpu(x), gpu(off), out_keys=out, workspace=ws,
+                           debug_check=debug_check)
+        assert msn.segmented_status(ws, n, S) == bit
+        assert bool((out == 7).all())
+        # argsort: values untouched too
+        wsp = torch.empty(_lib.segmented_workspace_bytes(n, S, 1, True), dtype=torch.uint8,
+                          device="cuda:0")
+        ov = torch.full((n,), -1, dtype=torch.int32, device="cuda:0")
+        msn.segmented_sort(gpu(x), gpu(off), argsort=True, out_keys=out, out_vals=ov,
+                           workspace=wsp, debug_check=debug_check)
+        assert msn.segmented_status(wsp, n, S, pairs=True) == bit
+        assert bool((out == 7).all()) and bool((ov == -1).all())
+
+
+@pytest.mark.parametrize("dtype", ["i32", "f32"])
+def test_debug_check_on_valid_offsets(orc, dtype):
+    from paper_2503_05934_amd import _lib
+    lengths = mixed_lengths(seed=21, count=150)
+    off = offsets_of(lengths)
+    n, S = int(off[-1]), len(lengths)
+    x = seg_keys(n, dtype, seed=22)
+    ws = torch.empty(_lib.segmented_workspace_bytes(n, S, 2, False), dtype=torch.uint8,
+                     device="cuda:0")
+    ws.fill_(0xAB)
+    say(f"segmented debug check on valid offsets dtype={dtype}")
+    y = msn.segmented_sort(gpu(x), gpu(off), workspace=ws, debug_check=True)
+    assert msn.segmented_status(ws, n, S) == 0
+    assert np.array_equal(bits(host(y)), bits(orc.segmented_sort(x, off, dtype=dtype,
+                                                                 stable=True)))
+    ws.fill_(0xAB)
+    y = msn.segmented_sort(gpu(x), gpu(off), workspace=ws)   # status cleared without the flag too
+    assert msn.segmented_status(ws, n, S) == 0
+
+
+def test_binding_rejects_mis_sized_buffers():
+    """Every caller-supplied array is checked against n before the call: a
+    short output, value or workspace array raises ValueError and nothing runs."""
+    dev = "cuda:0"
+    k = torch.arange(1000, dtype=torch.int32, device=dev)
+    short = torch.empty(999, dtype=torch.int32, device=dev)
+    wide = torch.empty(1000, dtype=torch.int64, device=dev)
+    off = torch.tensor([0, 500, 1000], dtype=torch.int32, device=dev)
+    cases = [
+        lambda: msn.sort(k, out=short),
+        lambda: msn.sort(k, out=wide),
+        lambda: msn.sort(k, workspace=torch.empty(16, dtype=torch.uint8, device=dev)),
+        lambda: msn.sort_pairs(k, short),
+        lambda: msn.sort_pairs(k, out_keys=short),
+        lambda: msn.sort_pairs(k, out_vals=short),
+        lambda: msn.sort_pairs(k, k[::2].contiguous()),
+        lambda: msn.segmented_sort(k, off, short),
+        lambda: msn.segmented_sort(k, off, out_keys=short),
+        lambda: msn.segmented_sort(k, off, argsort=True, out_vals=short),
+        lambda: msn.segmented_sort(k, off, out_vals=short),
+        lambda: msn.segmented_sort(k, off.cpu()),
+        lambda: msn.sort_backward(k.float().view(10, 100), k.view(10, 100), out=short.float()),
+        lambda: msn.SortPlan(1000, torch.int32, dev).run(short),
+        lambda: msn.SortPlan(1000, torch.int32, dev, pairs=True).run(k, short),
+        lambda: msn.SortPlan(1000, torch.int32, dev, pairs=True).run(k),
+    ]
+    for i, c in enumerate(cases):
+        say(f"binding check case {i}")
+        with pytest.raises(ValueError):
+            c()

@@ -25,16 +25,17 @@ PLANTS = {
     "redundant_comparators_kept": (
         "            if (useful[c]) {", "            if (1) {"),
     "merge_prefers_right_on_ties": (
-        "        if (rec_less(&c->ord, &a[j], &a[i]))",
-        "        if (!rec_less(&c->ord, &a[i], &a[j]))"),
+        "            from_right = rec_less(&c->ord, &right[ri], &left[li]);",
+        "            from_right = !rec_less(&c->ord, &left[li], &right[ri]);"),
     "merge_drops_left_tail": (
-        "    while (i <= mid) s[k++] = a[i++];\n", "\n"),
+        "        else if (ri == nr)\n            from_right = 0;",
+        "        else if (ri == nr)\n            break;"),
     "merge_split_off_by_one": (
-        "        optimized_merge_sort(c, a, mid + 1, right);\n        merge_runs(c, a, left, mid, right);",
-        "        optimized_merge_sort(c, a, mid + 1, right);\n        merge_runs(c, a, left, mid - (mid > left), right);"),
+        "            merge_neighbours(c, a, r.start, nl, r.count);",
+        "            merge_neighbours(c, a, r.start, nl - (nl > 1), r.count);"),
     "quick_sort_skips_element": (
-        "        optimized_quick_sort(o, netmask, a, p + 1, high);",
-        "        optimized_quick_sort(o, netmask, a, p + 2, high);"),
+        "            const range_t hi = {cut + 1, last - cut, 0};",
+        "            const range_t hi = {cut + 2, last - cut - 1, 0};"),
     "tie_break_reversed": (
         "    return o->stable && a->pos < b->pos;", "    return o->stable && a->pos > b->pos;"),
     "int32_compared_unsigned": (
@@ -48,8 +49,8 @@ PLANTS = {
     "table3_even_missing_6": (
         '{"Even", (1u << 4) | (1u << 6) | (1u << 8)}', '{"Even", (1u << 4) | (1u << 8)}'),
     "network_dispatch_off_by_one": (
-        "    if (size >= 0 && size <= ORC_MAX_NET && (c->netmask >> size) & 1u) {\n        apply_network(&c->ord, &a[left], (int)size);",
-        "    if (size >= 1 && size <= ORC_MAX_NET && (c->netmask >> size) & 1u) {\n        apply_network(&c->ord, &a[left], (int)size - 1);"),
+        "            apply_network(&c->ord, a + r.start, (int)r.count);",
+        "            apply_network(&c->ord, a + r.start, (int)r.count - 1);"),
     "backward_scatters_the_wrong_way": (
         "            grad_in[r * cols + perm[r * cols + i]] = grad_out[r * cols + i];",
         "            grad_in[r * cols + i] = grad_out[r * cols + perm[r * cols + i]];"),
