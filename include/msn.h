@@ -136,6 +136,31 @@ int msn_sort_workspace_bytes(int64_t n, int dtype, int pairs, size_t* bytes);
 int msn_sort_keys(const void* keys_in, void* keys_out, int64_t n, int dtype, int leaf,
                   const msn_tuning* tuning, void* ws, size_t ws_bytes, void* stream);
 
+/* Largest n msn_sort_keys_noalloc accepts (2^22 keys). */
+#define MSN_NOALLOC_MAX_KEYS 4194304
+
+/*
+ * msn_sort_keys with no workspace argument and no allocation, for callers
+ * that cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  The workspace is a fixed
+ * array inside the library's code object (about 16.2 MiB, the keys-only
+ * workspace of MSN_NOALLOC_MAX_KEYS keys); each device the library runs on
+ * holds its own copy until the process ends.  Its device address is looked
+ * up on the first call for each device (the device of `stream`, or the
+ * current device for the null stream).
+ *   keys_in, keys_out, dtype, leaf, tuning, stream: as msn_sort_keys.
+ *   n  0 .. MSN_NOALLOC_MAX_KEYS; larger n returns MSN_ERR_SIZE before
+ *      anything is enqueued.
+ * The call never allocates or frees device memory and never synchronises.
+ * Every call on one device shares that device's array, and nothing in it
+ * needs clearing between calls (each call writes what it later reads).
+ * Calls that may overlap in time on one device -- on different streams, or
+ * from different threads -- race on the array and give undefined results;
+ * calls in order on one stream are safe.
+ */
+int msn_sort_keys_noalloc(const void* keys_in, void* keys_out, int64_t n, int dtype, int leaf,
+                          const msn_tuning* tuning, void* stream);
+
 /*
  * Stable key-value sort of n pairs: the keys as msn_sort_keys, and
  * vals_out[i] = vals_in[p(i)] where p(i) is the input position of the i-th

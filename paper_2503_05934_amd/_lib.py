@@ -20,6 +20,7 @@ MSN_LEAF_6TO8, MSN_LEAF_3TO5, MSN_LEAF_NONE = 0, 1, 2
 MSN_ARGSORT = 1
 MSN_DEBUG_CHECK = 2
 MSN_SEG_BAD_FIRST, MSN_SEG_BAD_ORDER, MSN_SEG_BAD_LAST, MSN_SEG_BAD_RESULT = 1, 2, 4, 8
+MSN_NOALLOC_MAX_KEYS = 4194304
 
 LEAVES = {"6To8": MSN_LEAF_6TO8, "3To5": MSN_LEAF_3TO5, "classical": MSN_LEAF_NONE}
 _DTYPES = {torch.uint32: MSN_U32, torch.int32: MSN_I32, torch.float32: MSN_F32}
@@ -87,6 +88,8 @@ def lib():
     L.msn_segmented_status_offset.restype = I
     L.msn_sort_keys.argtypes = [P, P, I64, I, I, P, P, ctypes.c_size_t, P]
     L.msn_sort_keys.restype = I
+    L.msn_sort_keys_noalloc.argtypes = [P, P, I64, I, I, P, P]
+    L.msn_sort_keys_noalloc.restype = I
     L.msn_sort_pairs.argtypes = [P, P, P, P, I64, I, I, P, P, ctypes.c_size_t, P]
     L.msn_sort_pairs.restype = I
     L.msn_segmented_sort_workspace_bytes.argtypes = [I64, I64, I, I, SZ]

@@ -252,6 +252,19 @@ int msn_sort_keys(const void* keys_in, void* keys_out, int64_t n, int dtype, int
                        stream, false);
 }
 
+int msn_sort_keys_noalloc(const void* keys_in, void* keys_out, int64_t n, int dtype, int leaf,
+                          const msn_tuning* tuning, void* stream) {
+    if (n < 0 || n > msn::kNoAllocMaxKeys) return MSN_ERR_SIZE;
+    if (n == 0) return sort_common(keys_in, nullptr, keys_out, nullptr, 0, dtype, leaf, tuning,
+                                   nullptr, 0, stream, false);
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    if (int rc = msn::noalloc_scratch(static_cast<hipStream_t>(stream), &ws, &ws_bytes))
+        return rc;
+    return sort_common(keys_in, nullptr, keys_out, nullptr, n, dtype, leaf, tuning, ws, ws_bytes,
+                       stream, false);
+}
+
 int msn_sort_pairs(const void* keys_in, const uint32_t* vals_in, void* keys_out,
                    uint32_t* vals_out, int64_t n, int dtype, int leaf, const msn_tuning* tuning,
                    void* ws, size_t ws_bytes, void* stream) {

@@ -59,7 +59,7 @@ struct SegArgs {
     int debug_check = 0;      // MSN_DEBUG_CHECK: verify every segment after sorting
 };
 
-inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+constexpr size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 constexpr int kMinMergeTile = 2048;
 // Chunk size of the key samples every sweep of a flat sort leaves behind
@@ -80,19 +80,19 @@ constexpr int kM4SamplesPerTile = 27;
 
 // Upper bound on the tile boundaries of any four-way pass (runs of at least
 // 4096 keys): chunks / kM4SamplesPerTile + 2 per group + slack.
-inline size_t m4_max_bounds(int64_t n) {
+constexpr size_t m4_max_bounds(int64_t n) {
     const size_t chunks = (size_t)((n + kSampleChunk - 1) / kSampleChunk);
     return chunks / kM4SamplesPerTile + (size_t)(n / 8192) + 8;
 }
 
 // Workspace of the four-way passes: the boundary table (four splits per
 // tile boundary).
-inline size_t m4_ws_bytes(int64_t n) { return align_up(m4_max_bounds(n) * 16, 256); }
+constexpr size_t m4_ws_bytes(int64_t n) { return align_up(m4_max_bounds(n) * 16, 256); }
 
 // Workspace of the flat sort: ping-pong keys (+ values), one merge-path split
 // per merge tile, the two chunk-sample arrays, the four-way passes' boundary
 // table, and the presorted-input flag.
-inline size_t sort_ws_bytes(int64_t n, bool vals) {
+constexpr size_t sort_ws_bytes(int64_t n, bool vals) {
     const size_t nk = align_up((size_t)n * 4, 256);
     const size_t nv = vals ? nk : 0;
     const size_t tiles = (size_t)((n + kMinMergeTile - 1) / kMinMergeTile) + 1;
@@ -124,6 +124,15 @@ class LaunchTimer {
 };
 
 int launch_sort(const SortArgs& a);
+
+// Keys accepted by msn_sort_keys_noalloc, and the bytes of its device-resident
+// scratch (the flat keys-only workspace at that size).
+constexpr int64_t kNoAllocMaxKeys = MSN_NOALLOC_MAX_KEYS;
+constexpr size_t kNoAllocScratchBytes = sort_ws_bytes(kNoAllocMaxKeys, false);
+// Address of this library's scratch array on the device that `stream`
+// belongs to (the current device for the null stream), looked up once per
+// device; *bytes receives its size.  Returns a hipError_t value.
+int noalloc_scratch(hipStream_t stream, void** ptr, size_t* bytes);
 int launch_segmented(const SegArgs& a);
 int launch_backward(const float* grad_out, const int32_t* perm, float* grad_in, int64_t rows,
                     int64_t cols, hipStream_t stream);

@@ -2,6 +2,7 @@
 // then global merge-path passes that double the run length until one run
 // remains (paper Sec. 3, Algorithm 1, run bottom-up).
 #include <algorithm>
+#include <mutex>
 
 #include "block_tile.hpp"
 #include "merge4.hpp"
@@ -484,6 +485,45 @@ int run_sort(const SortArgs& a) {
 }
 
 }  // namespace
+
+// ------------------------------------------------ allocation-free scratch ---
+// The workspace of msn_sort_keys_noalloc: a fixed array in the code object,
+// which every device the library runs on holds until the process ends.  In
+// host code `scratch` names a host-side stand-in, never the device array: its
+// device address comes from hipGetSymbolAddress, looked up once per device
+// with that device current, and only that address is passed to kernels.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void* scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+int noalloc_scratch(hipStream_t stream, void** ptr, size_t* bytes) {
+    int dev = 0;
+    if (int rc = (int)hipGetDevice(&dev)) return rc;
+    int sdev = dev;
+    if (stream) {
+        if (int rc = (int)hipStreamGetDevice(stream, &sdev)) return rc;
+    }
+    if (sdev < 0 || sdev >= kMaxDevices) return (int)hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_ptr[sdev]) {
+        if (sdev != dev) {
+            if (int rc = (int)hipSetDevice(sdev)) return rc;
+        }
+        void* p = nullptr;
+        const int rc = (int)hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (sdev != dev) (void)hipSetDevice(dev);
+        if (rc) return rc;
+        if (!p) return (int)hipErrorInvalidSymbol;
+        scratch_ptr[sdev] = p;
+    }
+    *ptr = scratch_ptr[sdev];
+    *bytes = kNoAllocScratchBytes;
+    return 0;
+}
 
 int launch_sort(const SortArgs& a) {
     if (a.n == 0) return 0;
