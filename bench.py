@@ -101,24 +101,51 @@ def check_sorted_u32(out, inp) -> bool:
     return ok and s_in == s_out
 
 
-def cpu_baseline(keys_np: np.ndarray, sample_n: int):
+def cpu_baseline_start(keys_np: np.ndarray, sample_n: int):
+    """Starts the CPU oracle on the first sample_n keys in two threads: the
+    paper's Algorithm 1 with 6-to-8 networks, and the classical merge sort
+    (its empty network set, Eq. 1's baseline).  Each sort is single-threaded;
+    ctypes releases the GIL, so they run while the GPU workloads go on.
+    Returns a function that waits and builds the cpu_baseline record."""
+    import threading
+
     import oracle
 
     orc = oracle.load()
     sample = keys_np[:sample_n]
-    t0 = time.perf_counter()
-    orc.sort(sample, dtype="u32", algo="ms", config="6To8")
-    dt = time.perf_counter() - t0
-    return {
-        "value": sample_n / dt / 1e9,
-        "unit": "Gkeys/s",
-        "cores": 1,
-        "kind": "oracle",
-        "sample": f"first 2^{int(np.log2(sample_n))} keys of the random 2^28 uint32 input; "
-                  f"oracle Algorithm 1 with 6-to-8 networks, single thread, {dt:.2f} s",
-        "host_cpu": _cpu_model(),
-        "host_threads": os.cpu_count(),
-    }
+    times = {}
+
+    def run(config):
+        t0 = time.perf_counter()
+        orc.sort(sample, dtype="u32", algo="ms", config=config)
+        times[config] = time.perf_counter() - t0
+
+    threads = [threading.Thread(target=run, args=(c,), daemon=True)
+               for c in ("6To8", "Classical")]
+    for t in threads:
+        t.start()
+
+    def finish():
+        for t in threads:
+            t.join()
+        t1, t0 = times["6To8"], times["Classical"]
+        whole = sample_n == keys_np.shape[0]
+        what = ("the whole" if whole else f"the first 2^{int(np.log2(sample_n))} keys of the")
+        return {
+            "value": sample_n / t1 / 1e9,
+            "unit": "Gkeys/s",
+            "cores": 1,
+            "kind": "oracle",
+            "sample": f"{what} random 2^28 uint32 input; oracle Algorithm 1 with 6-to-8 "
+                      f"networks, one thread, {t1:.2f} s; the classical merge sort ran at the "
+                      f"same time on a second thread, {t0:.2f} s, while the GPU workloads ran",
+            "classical": {"value": sample_n / t0 / 1e9, "seconds": t0},
+            "eq1_speedup": t0 / t1,
+            "host_cpu": _cpu_model(),
+            "host_threads": os.cpu_count(),
+        }
+
+    return finish
 
 
 def _cpu_model():
@@ -129,6 +156,50 @@ def _cpu_model():
     except OSError:
         pass
     return "unknown"
+
+
+def _graph_time(fn, steps, warmup):
+    """fn captured once in a HIP graph and replayed: (ms per replay, wall s)."""
+    import torch
+
+    fn()
+    torch.cuda.synchronize()
+    gstream = torch.cuda.Stream()
+    gstream.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=gstream):
+        fn()
+    ms, wall = time_steps(graph.replay, steps, warmup)
+    del graph
+    return ms, wall
+
+
+def copy_ceiling(steps: int, warmup: int, words: int = 1 << 29):
+    """The library's own 16-byte copy kernel (msn_copy_words) over 2 GiB:
+    the rate a read-once write-once sweep reaches on this device."""
+    import torch
+
+    from paper_2503_05934_amd import _lib
+
+    dev = torch.device("cuda:0")
+    src = torch.arange(words, dtype=torch.int32, device=dev)
+    dst = torch.empty_like(src)
+    L = _lib.lib()
+
+    def run():
+        # the current stream: the capturing stream while a graph is recorded
+        _lib.check("msn_copy_words", L.msn_copy_words(_lib.ptr(src), _lib.ptr(dst), words,
+                                                      _lib.stream_handle(dev)))
+
+    ms, _ = _graph_time(run, steps, warmup)
+    if not torch.equal(src, dst):
+        raise SystemExit("[bench] copy check failed")
+    gbps = 8.0 * words / (ms / 1e3) / 1e9
+    del src, dst
+    return {"gbps": gbps, "frac_of_peak": gbps / HBM_PEAK_GBPS, "ms": ms,
+            "bytes_per_launch": 8 * words,
+            "kernel": "k_copy_words (msn_copy_words: 2 GiB read + 2 GiB written, 16-byte "
+                      "accesses, graph replay)"}
 
 
 def bench_keys(args):
@@ -147,13 +218,17 @@ def bench_keys(args):
     plan = msn.SortPlan(n, torch.uint32, dev, leaf=leaf, tuning=tuning or None)
     results = {}
     roof = None
-    keys_random = None
+    cpu_finish = None
+    qws = None
     for dist in args.dists:
         log(f"[bench] generating {n} uint32 keys, {dist}")
         x_np = workloads.keys(n, dist, "u32", seed=0)
-        if dist == "random":
-            keys_random = x_np
+        if dist == "random" and not args.no_cpu:
+            log(f"[bench] CPU oracle baseline on 2^{int(np.log2(args.cpu_sample))} keys "
+                "(two threads, in the background)")
+            cpu_finish = cpu_baseline_start(x_np, args.cpu_sample)
         x = torch.from_numpy(x_np).to(dev)
+        del x_np
         steps = args.steps if dist == "random" else max(2, args.steps // 4)
         log(f"[bench] {dist}: warmup {args.warmup}, timing {steps} steps")
         stats = {}
@@ -174,13 +249,7 @@ def bench_keys(args):
         if args.eager:
             ms = ms_eager
         else:
-            gstream = torch.cuda.Stream()
-            gstream.wait_stream(torch.cuda.current_stream())
-            graph = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(graph, stream=gstream):
-                plan.run(x)
-            ms, wall = time_steps(graph.replay, steps, args.warmup)
-            del graph
+            ms, wall = _graph_time(lambda: plan.run(x), steps, args.warmup)
         ok = check_sorted_u32(plan.out, x)
         if not ok:
             raise SystemExit(f"[bench] output check failed for {dist}")
@@ -204,12 +273,28 @@ def bench_keys(args):
                         "kernel": ("k_merge4 (four-way merge pass)" if mkind == "merge4"
                                    else "k_merge_keys (binary merge-path pass)"),
                         "avg_launch_ms": m["avg_ms"], "launches": m["launches"],
-                        "algorithmic_bytes_per_launch": bytes_per_launch}
+                        "algorithmic_bytes_per_launch": bytes_per_launch,
+                        "timing": "HIP events around each launch of the timed eager steps"}
             results[dist]["kernels_ms_per_step"] = {
                 k: v["total_ms"] / steps for k, v in stats.items()}
+        if not args.no_quick and leaf != "classical":
+            # the paper's Algorithm 2 on the same input: quick sort, network leaves
+            if qws is None:
+                qws = torch.empty(_lib.quick_workspace_bytes(n, _lib.MSN_U32), dtype=torch.uint8,
+                                  device=dev)
+            qout = torch.empty_like(x)
+            qms, _ = _graph_time(lambda: msn.quick_sort(x, leaf=leaf, out=qout, workspace=qws),
+                                 steps, args.warmup)
+            if not torch.equal(qout, plan.out):
+                raise SystemExit(f"[bench] quick sort disagrees with the merge sort ({dist})")
+            results[dist]["quick"] = {"gkeys_per_s": n / (qms / 1e3) / 1e9, "ms_per_step": qms}
+            log(f"[bench] {dist}: quick sort {qms:.3f} ms/step")
+            del qout
         del x
+    del qws
     head = results[args.dists[0]]
     sched = reference_schedule_bytes(n, 4)
+    moved = 8 * (1 + plan_passes(n, leaf, plan))
     out = {
         "metric": METRIC,
         "value": head["gkeys_per_s"],
@@ -227,11 +312,16 @@ def bench_keys(args):
                                f"over [0, 2^32), seed 0, {leaf} leaves",
                    "n": n, "leaf": leaf, "dist": args.dists[0],
                    "merge_tile": args.merge_tile or 8192,
-                   "block_tile": args.block_tile or 2048 * (8 if leaf == "6To8" else 4)},
+                   "block_tile": args.block_tile or 2048 * (8 if leaf != "3To5" else 4)},
         "roofline": roof,
         "hbm_schedule": {"bytes_per_key": sched,
                          "implied_gkeys_at_peak": HBM_PEAK_GBPS / sched,
                          "frac": head["gkeys_per_s"] / (HBM_PEAK_GBPS / sched)},
+        "whole_sort": {"bytes_per_key_moved": moved,
+                       "gbps": head["gkeys_per_s"] * moved,
+                       "frac": head["gkeys_per_s"] * moved / HBM_PEAK_GBPS,
+                       "how": "the sweeps this build runs (first sweep + global passes), "
+                              "8 B per key each, over the whole sort's time"},
         "timing": "graph replay of one msn_sort_keys call per step" if not args.eager
                   else "eager msn_sort_keys call per step",
         "eager_ms_per_step": head["eager_ms_per_step"],
@@ -240,10 +330,52 @@ def bench_keys(args):
                             for d, r in results.items()},
         "kernels_ms_per_step": results.get("random", {}).get("kernels_ms_per_step"),
     }
-    if not args.no_cpu and keys_random is not None:
-        log(f"[bench] CPU oracle baseline on 2^{int(np.log2(args.cpu_sample))} keys")
-        out["cpu_baseline"] = cpu_baseline(keys_random, args.cpu_sample)
+    if any("quick" in r for r in results.values()):
+        out["quick_sort"] = {d: r["quick"] for d, r in results.items() if "quick" in r}
+    if not args.no_copy:
+        log("[bench] copy ceiling (msn_copy_words, 2 GiB)")
+        out["copy_ceiling"] = copy_ceiling(args.steps, args.warmup)
+        if roof:
+            roof["frac_of_copy_ceiling"] = roof["achieved"] / out["copy_ceiling"]["gbps"]
+    if not args.no_extras:
+        out.update(side_workloads(args))
+    if cpu_finish is not None:
+        log("[bench] waiting for the CPU oracle baseline")
+        out["cpu_baseline"] = cpu_finish()
     return out
+
+
+def plan_passes(n: int, leaf: str, plan) -> int:
+    """Global merge passes of the default plan: four-way while at least three
+    runs remain, then binary (first-sweep runs of 2048 x leaf keys)."""
+    runs = -(-n // (2048 * (4 if leaf == "3To5" else 8)))
+    p = 0
+    while runs > 1:
+        runs = -(-runs // (4 if runs >= 3 else 2))
+        p += 1
+    return p
+
+
+def side_workloads(args):
+    """The other workloads, condensed into keys of the default line."""
+    import copy
+
+    import torch
+
+    extra = {}
+    a = copy.copy(args)
+    a.steps, a.warmup = max(4, args.steps // 2), 2
+    for name, fn in (("pairs", bench_pairs), ("segmented", bench_segmented),
+                     ("rows", bench_rows)):
+        log(f"[bench] side workload: {name}")
+        r = fn(a)
+        keep = {k: r[k] for k in ("metric", "value", "unit", "ms_per_step", "roofline",
+                                  "config", "per_array_baseline", "speedup_vs_per_array",
+                                  "backward", "eager_ms_per_step", "kernels_ms_per_step")
+                if k in r}
+        extra[name] = keep
+        torch.cuda.empty_cache()
+    return extra
 
 
 def _roof(stats, kind, bytes_per_launch_fn, peak=HBM_PEAK_GBPS):
@@ -615,8 +747,12 @@ def main():
     ap.add_argument("--merge4-kpt", type=int, default=0,
                     help="keys per thread of the four-way merge kernel (16 or 32)")
     ap.add_argument("--dists", default="random,sorted,nearly")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 27)
+    ap.add_argument("--cpu-sample", type=int, default=1 << 28)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-quick", action="store_true", help="keys: skip the quick sort")
+    ap.add_argument("--no-copy", action="store_true", help="keys: skip the copy ceiling")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="keys: skip the pairs, segmented and rows workloads")
     ap.add_argument("--eager", action="store_true",
                     help="time eager calls instead of replays of a captured HIP graph")
     ap.add_argument("--segments", type=int, default=100_000)

@@ -105,6 +105,10 @@ extern "C" {
  *                   values; float keys always merge pairs of runs.
  *   merge4_kpt      keys per thread of the four-way merge kernel: 16 (512
  *                   threads per tile) or 32 (256 threads); default 16.
+ *   quick_rounds    partition rounds of msn_quick_sort_keys, 1..96; a
+ *                   subarray still longer than one block-sort tile in the
+ *                   last round is merge-sorted by one workgroup (default
+ *                   2 ceil(log2(n / tile)) + 16, capped at 96).
  */
 typedef struct {
     int32_t merge_tile;
@@ -115,6 +119,7 @@ typedef struct {
     int32_t block_tile;
     int32_t merge_ways;
     int32_t merge4_kpt;
+    int32_t quick_rounds;
 } msn_tuning;
 
 /*
@@ -160,6 +165,34 @@ int msn_sort_keys(const void* keys_in, void* keys_out, int64_t n, int dtype, int
  */
 int msn_sort_keys_noalloc(const void* keys_in, void* keys_out, int64_t n, int dtype, int leaf,
                           const msn_tuning* tuning, void* stream);
+
+/*
+ * Bytes of workspace msn_quick_sort_keys needs for n keys (integer dtypes;
+ * MSN_F32 returns MSN_ERR_UNSUPPORTED).
+ */
+int msn_quick_sort_workspace_bytes(int64_t n, int dtype, size_t* bytes);
+
+/*
+ * Sorts n integer keys ascending by quick sort with network base cases:
+ * keys_out = sorted(keys_in), the same bits as msn_sort_keys.
+ *   keys_in, keys_out  device arrays of n MSN_U32 or MSN_I32 keys (may be
+ *                      equal); MSN_F32 returns MSN_ERR_UNSUPPORTED, because
+ *                      the partition is not stable and float keys that
+ *                      compare equal must keep their order.
+ *   leaf               MSN_LEAF_6TO8 / MSN_LEAF_3TO5: subarrays of at most
+ *                      8 (4) keys take one network, subarrays of at most one
+ *                      block-sort tile (8192 / 4096 keys) the block sort;
+ *                      MSN_LEAF_NONE: the same without any network.
+ *   tuning             NULL, or quick_rounds (other fields are ignored).
+ *   ws, ws_bytes       at least msn_quick_sort_workspace_bytes(n, dtype).
+ * The pivot of every subarray is the median of its first, middle and last
+ * keys; each partition round is one launch, and the number of launches
+ * depends only on n and the tuning.
+ * Paper: Sec. 3, Algorithm 2 (MedianOfThree, HoarePartition, network base
+ * cases).
+ */
+int msn_quick_sort_keys(const void* keys_in, void* keys_out, int64_t n, int dtype, int leaf,
+                        const msn_tuning* tuning, void* ws, size_t ws_bytes, void* stream);
 
 /*
  * Stable key-value sort of n pairs: the keys as msn_sort_keys, and
@@ -236,6 +269,14 @@ int msn_segmented_status_offset(int64_t n_total, int64_t num_segments, int pairs
  */
 int msn_sort_backward(const float* grad_out, const int32_t* perm, float* grad_in,
                       int64_t rows, int64_t cols, void* stream);
+
+/*
+ * Copies n 32-bit words, dst[i] = src[i] (diagnostics): the library's own
+ * streaming kernel, 16-byte loads and stores when both pointers are 16-byte
+ * aligned, which measures the HBM rate a sweep can reach on this device next
+ * to the sorts.  src and dst must not overlap.  Kernel kind "copy_words".
+ */
+int msn_copy_words(const void* src, void* dst, int64_t n, void* stream);
 
 /*
  * Kernel timing (diagnostics, for benchmarks and profiling).  While enabled,

@@ -7,6 +7,7 @@ of ``libmsn.so`` (C ABI in ``include/msn.h``); these functions only allocate
 outputs and workspace with torch and pass pointers and the current stream.
 
     sort(keys)                        ascending sort of 1-D uint32/int32/float32
+    quick_sort(keys)                  the same by quick sort (Algorithm 2), integer keys
     sort_pairs(keys, vals=None)       stable key-value sort / argsort
     segmented_sort(keys, offsets)     many arrays in one persistent launch
     sort_rows(x)                      stable row-wise sort -> (values, perm)
@@ -21,7 +22,8 @@ from . import _lib
 from ._lib import LEAVES, MsnError, Tuning, make_tuning
 
 __all__ = [
-    "sort", "sort_pairs", "segmented_sort", "segmented_status", "sort_rows", "sort_backward",
+    "sort", "quick_sort", "sort_pairs", "segmented_sort", "segmented_status", "sort_rows",
+    "sort_backward",
     "DiffSort", "MsnError", "Tuning", "LEAVES", "version", "SortPlan",
 ]
 
@@ -95,6 +97,23 @@ def sort(keys: torch.Tensor, *, leaf="6To8", tuning=None, out: torch.Tensor | No
           else _check_workspace(workspace, ws_bytes, keys.device))
     t, tp = _tuning_ptr(tuning)
     _lib.check("msn_sort_keys", _lib.lib().msn_sort_keys(
+        _lib.ptr(keys), _lib.ptr(out), n, dt, _lib.leaf_code(leaf), tp, _lib.ptr(ws),
+        ws.numel() * ws.element_size(), _lib.stream_handle(keys.device, stream)))
+    return out
+
+
+def quick_sort(keys: torch.Tensor, *, leaf="6To8", tuning=None, out: torch.Tensor | None = None,
+               workspace: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Ascending sort of a 1-D uint32/int32 GPU tensor by the quick sort with
+    network leaves (the paper's Algorithm 2); the same result as sort()."""
+    dt = _check_keys(keys)
+    n = keys.numel()
+    out = torch.empty_like(keys) if out is None else _check_buf(out, n, "out", keys.device)
+    ws_bytes = _lib.quick_workspace_bytes(n, dt)
+    ws = (_workspace(ws_bytes, keys.device) if workspace is None
+          else _check_workspace(workspace, ws_bytes, keys.device))
+    t, tp = _tuning_ptr(tuning)
+    _lib.check("msn_quick_sort_keys", _lib.lib().msn_quick_sort_keys(
         _lib.ptr(keys), _lib.ptr(out), n, dt, _lib.leaf_code(leaf), tp, _lib.ptr(ws),
         ws.numel() * ws.element_size(), _lib.stream_handle(keys.device, stream)))
     return out

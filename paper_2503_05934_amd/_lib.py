@@ -46,6 +46,7 @@ class Tuning(ctypes.Structure):
         ("block_tile", ctypes.c_int32),
         ("merge_ways", ctypes.c_int32),
         ("merge4_kpt", ctypes.c_int32),
+        ("quick_rounds", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -90,12 +91,18 @@ def lib():
     L.msn_sort_keys.restype = I
     L.msn_sort_keys_noalloc.argtypes = [P, P, I64, I, I, P, P]
     L.msn_sort_keys_noalloc.restype = I
+    L.msn_quick_sort_workspace_bytes.argtypes = [I64, I, SZ]
+    L.msn_quick_sort_workspace_bytes.restype = I
+    L.msn_quick_sort_keys.argtypes = [P, P, I64, I, I, P, P, ctypes.c_size_t, P]
+    L.msn_quick_sort_keys.restype = I
     L.msn_sort_pairs.argtypes = [P, P, P, P, I64, I, I, P, P, ctypes.c_size_t, P]
     L.msn_sort_pairs.restype = I
     L.msn_segmented_sort_workspace_bytes.argtypes = [I64, I64, I, I, SZ]
     L.msn_segmented_sort_workspace_bytes.restype = I
     L.msn_segmented_sort.argtypes = [P, P, P, P, P, I64, I64, I, I, U, P, P, ctypes.c_size_t, P]
     L.msn_segmented_sort.restype = I
+    L.msn_copy_words.argtypes = [P, P, I64, P]
+    L.msn_copy_words.restype = I
     L.msn_sort_backward.argtypes = [P, P, P, I64, I64, P]
     L.msn_sort_backward.restype = I
     _lib = L
@@ -143,6 +150,13 @@ def sort_workspace_bytes(n: int, dtype: int, pairs: bool) -> int:
     return out.value
 
 
+def quick_workspace_bytes(n: int, dtype: int) -> int:
+    out = ctypes.c_size_t(0)
+    check("msn_quick_sort_workspace_bytes",
+          lib().msn_quick_sort_workspace_bytes(n, dtype, ctypes.byref(out)))
+    return out.value
+
+
 def segmented_status_offset(n_total: int, num_segments: int, pairs: bool) -> int:
     out = ctypes.c_size_t(0)
     check("msn_segmented_status_offset",
@@ -181,12 +195,13 @@ def timing_read() -> dict:
     L = lib()
     L.msn_timing_read.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     L.msn_timing_read.restype = ctypes.c_int
-    arr = (KernelStats * 32)()
+    cap = 512
+    arr = (KernelStats * cap)()
     count = ctypes.c_int(0)
-    check("msn_timing_read", L.msn_timing_read(ctypes.cast(arr, ctypes.c_void_p), 32,
+    check("msn_timing_read", L.msn_timing_read(ctypes.cast(arr, ctypes.c_void_p), cap,
                                                ctypes.byref(count)))
     out = {}
-    for i in range(min(count.value, 32)):
+    for i in range(min(count.value, cap)):
         s = arr[i]
         out[s.kind.decode()] = {"launches": s.launches, "elements": s.elements,
                                 "total_ms": s.total_ms,

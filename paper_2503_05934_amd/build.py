@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(PKG, "libmsn.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["sort.hip", "segmented.hip", "backward.hip", "api.cpp"]
+SOURCES = ["sort.hip", "segmented.hip", "quick.hip", "backward.hip", "api.cpp"]
 ARCH = os.environ.get("MSN_OFFLOAD_ARCH", "gfx950")
 
 

@@ -272,6 +272,36 @@ int msn_sort_pairs(const void* keys_in, const uint32_t* vals_in, void* keys_out,
                        stream, true);
 }
 
+int msn_quick_sort_workspace_bytes(int64_t n, int dtype, size_t* bytes) {
+    if (!bytes) return MSN_ERR_NULL;
+    if (!valid_dtype(dtype)) return MSN_ERR_DTYPE;
+    if (dtype == MSN_F32) return MSN_ERR_UNSUPPORTED;
+    if (n < 0 || n > kMaxN) return MSN_ERR_SIZE;
+    *bytes = msn::quick_ws_bytes(n);
+    return MSN_OK;
+}
+
+int msn_quick_sort_keys(const void* keys_in, void* keys_out, int64_t n, int dtype, int leaf,
+                        const msn_tuning* tuning, void* ws, size_t ws_bytes, void* stream) {
+    if (!valid_dtype(dtype)) return MSN_ERR_DTYPE;
+    if (dtype == MSN_F32) return MSN_ERR_UNSUPPORTED;  // the partition is not stable
+    const int k = leaf_keys(leaf);
+    if (!k) return MSN_ERR_CONFIG;
+    const int rounds = tuning ? tuning->quick_rounds : 0;
+    if (rounds < 0 || rounds > msn::kQuickMaxRounds) return MSN_ERR_CONFIG;
+    if (n < 0 || n > kMaxN) return MSN_ERR_SIZE;
+    if (n == 0) return MSN_OK;
+    if (!keys_in || !keys_out) return MSN_ERR_NULL;
+    if (misaligned(keys_in) || misaligned(keys_out) || misaligned(ws)) return MSN_ERR_UNSUPPORTED;
+    if (bad_overlap(keys_in, keys_out, n)) return MSN_ERR_SIZE;
+    const size_t need = msn::quick_ws_bytes(n);
+    if (!ws || ws_bytes < need) return MSN_ERR_WORKSPACE;
+    msn::QuickArgs a{static_cast<const uint32_t*>(keys_in), static_cast<uint32_t*>(keys_out), n,
+                     dtype, k, leaf != MSN_LEAF_NONE, rounds, ws, ws_bytes,
+                     static_cast<hipStream_t>(stream)};
+    return msn::launch_quick(a);
+}
+
 int msn_segmented_sort_workspace_bytes(int64_t n_total, int64_t num_segments, int dtype,
                                        int pairs, size_t* bytes) {
     if (!bytes) return MSN_ERR_NULL;
@@ -353,6 +383,16 @@ int msn_segmented_status_offset(int64_t n_total, int64_t num_segments, int pairs
         return MSN_ERR_SIZE;
     *offset = msn::seg_status_offset(n_total, num_segments, pairs != 0);
     return MSN_OK;
+}
+
+int msn_copy_words(const void* src, void* dst, int64_t n, void* stream) {
+    if (n < 0) return MSN_ERR_SIZE;
+    if (n == 0) return MSN_OK;
+    if (!src || !dst) return MSN_ERR_NULL;
+    if (misaligned(src) || misaligned(dst)) return MSN_ERR_UNSUPPORTED;
+    if (any_overlap(src, dst, n)) return MSN_ERR_SIZE;
+    return msn::launch_copy(static_cast<const uint32_t*>(src), static_cast<uint32_t*>(dst), n,
+                            static_cast<hipStream_t>(stream));
 }
 
 int msn_sort_backward(const float* grad_out, const int32_t* perm, float* grad_in, int64_t rows,

@@ -124,6 +124,7 @@ class LaunchTimer {
 };
 
 int launch_sort(const SortArgs& a);
+int launch_copy(const uint32_t* src, uint32_t* dst, int64_t n, hipStream_t stream);
 
 // Keys accepted by msn_sort_keys_noalloc, and the bytes of its device-resident
 // scratch (the flat keys-only workspace at that size).
@@ -134,6 +135,26 @@ constexpr size_t kNoAllocScratchBytes = sort_ws_bytes(kNoAllocMaxKeys, false);
 // device; *bytes receives its size.  Returns a hipError_t value.
 int noalloc_scratch(hipStream_t stream, void** ptr, size_t* bytes);
 int launch_segmented(const SegArgs& a);
+
+struct QuickArgs {
+    const uint32_t* kin;
+    uint32_t* kout;
+    int64_t n;
+    int dtype;       // kU32 or kI32
+    int leaf_k;      // keys of the leaf network: 8 or 4
+    int nets;        // 0: no networks anywhere (the classical quick sort), tiles of leaf_k = 8
+    int rounds;      // partition rounds (0 = quick_rounds(n, leaf tile))
+    void* ws;
+    size_t ws_bytes;
+    hipStream_t stream;
+};
+// Rounds (launches of the round kernel) of a quick sort of n keys whose
+// leaves hold up to leaf_max keys, by default.
+constexpr int kQuickMaxRounds = 96;
+int quick_rounds(int64_t n, int64_t leaf_max);
+// Workspace of the quick sort: the partition buffer and three item lists.
+size_t quick_ws_bytes(int64_t n);
+int launch_quick(const QuickArgs& a);
 int launch_backward(const float* grad_out, const int32_t* perm, float* grad_in, int64_t rows,
                     int64_t cols, hipStream_t stream);
 

@@ -365,3 +365,66 @@ def test_sort_is_deterministic():
     b = msn.sort_pairs(x)
     assert torch.equal(a[0].view(torch.int32), b[0].view(torch.int32))
     assert torch.equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("pairs", [False, True])
+def test_flat_sort_graph_replay(orc, pairs):
+    # the benchmark's launch configuration: one call captured in a HIP graph,
+    # replayed several times with eager work and synchronisations between
+    n = 3_000_017
+    x = workloads.keys(n, "random", "u32", seed=31)
+    v = np.arange(n, dtype=np.uint32)[::-1].copy()
+    if pairs:
+        rk, rv = orc.sort(x, vals=v, dtype="u32", stable=True)
+    else:
+        rk = orc.sort(x, dtype="u32")
+    plan = msn.SortPlan(n, torch.uint32, "cuda:0", pairs=pairs)
+    xs, vs = gpu(x), gpu(v)
+    run = (lambda: plan.run(xs, vs)) if pairs else (lambda: plan.run(xs))
+    run()
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        run()
+    for rep in range(3):
+        plan.out.fill_(0)
+        if pairs:
+            plan.out_vals.fill_(0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        say(f"flat graph replay {rep} pairs={pairs}")
+        assert np.array_equal(host(plan.out), rk), rep
+        if pairs:
+            assert np.array_equal(host(plan.out_vals), rv), rep
+
+
+def test_packed_composite_edges(orc):
+    # Stable tiles of 8192 pairs whose keys all fit 19 bits sort 32-bit
+    # (key << 13 | position) composites.  Key 2^19 - 1 at tile position 8191
+    # makes the composite all ones, the value that pads short tiles; a single
+    # key of 2^19 must keep its tile on 64-bit composites.
+    tile = 8192
+    rng = np.random.default_rng(77)
+    n = 4 * tile + 123
+    k = rng.integers(0, 1 << 19, n, dtype=np.uint32)
+    top = (1 << 19) - 1
+    k[tile - 1] = top                       # tile 0: the all-ones composite
+    k[tile + 4000] = 1 << 19                # tile 1: one key too wide to pack
+    k[2 * tile: 3 * tile: 7] = top          # tile 2: many ties at the top key ...
+    k[3 * tile - 1] = top                   # ... and the all-ones composite
+    k[3 * tile + 50] = top                  # the short last tile also holds it
+    k[-1] = top
+    v = rng.integers(0, 2**32, n, dtype=np.uint32)
+    rk, rv = orc.sort(k, vals=v, dtype="u32", stable=True)
+    for dtype in ("u32", "i32"):
+        kk = k if dtype == "u32" else k.view(np.int32)
+        rkk = rk if dtype == "u32" else rk.view(np.int32)
+        ko, vo = msn.sort_pairs(gpu(kk), gpu(v))
+        assert np.array_equal(host(ko), rkk), dtype
+        assert np.array_equal(host(vo), rv), dtype
+        ko, po = msn.sort_pairs(gpu(kk))
+        _, rp = orc.sort(kk, dtype=dtype, stable=True, want_perm=True)
+        assert np.array_equal(host(po).view(np.uint32), rp), dtype

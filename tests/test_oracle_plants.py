@@ -75,3 +75,29 @@ def test_planted_mistake_is_caught(tmp_path, name):
     r = subprocess.run([sys.executable, os.path.join(HERE, "plant_runner.py"), so],
                        capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"{name} passed every pin:\n{r.stdout}{r.stderr}"
+
+
+def _runtime(name):
+    out = subprocess.run(["gcc", f"-print-file-name={name}"], capture_output=True, text=True)
+    path = out.stdout.strip()
+    return path if os.path.isabs(path) and os.path.exists(path) else None
+
+
+def test_oracle_under_address_and_undefined_sanitizers(tmp_path):
+    # every pin against the oracle built with AddressSanitizer and
+    # UndefinedBehaviorSanitizer; any finding aborts the child process
+    asan = _runtime("libasan.so")
+    if asan is None:
+        pytest.skip("gcc has no AddressSanitizer runtime here")
+    so = oracle.build(SRC, str(tmp_path / "sanitized.so"),
+                      extra=("-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                             "-fno-sanitize-recover=all"))
+    env = dict(os.environ)
+    env["LD_PRELOAD"] = " ".join(p for p in (asan, _runtime("libubsan.so")) if p)
+    # Python's own allocations are not instrumented; leaks at exit are not the oracle's
+    env["ASAN_OPTIONS"] = "detect_leaks=0:abort_on_error=1"
+    env["UBSAN_OPTIONS"] = "halt_on_error=1:print_stacktrace=1"
+    r = subprocess.run([sys.executable, os.path.join(HERE, "plant_runner.py"), so],
+                       capture_output=True, text=True, timeout=900, env=env)
+    assert r.returncode == 0, (r.stdout + r.stderr)[-4000:]
+    assert "failed: none" in r.stdout
