@@ -312,7 +312,7 @@ def bench_keys(args):
                                f"over [0, 2^32), seed 0, {leaf} leaves",
                    "n": n, "leaf": leaf, "dist": args.dists[0],
                    "merge_tile": args.merge_tile or 8192,
-                   "block_tile": args.block_tile or 2048 * (8 if leaf != "3To5" else 4)},
+                   "block_tile": args.block_tile or 2048 * _lib.GROUP_KEYS[leaf]},
         "roofline": roof,
         "hbm_schedule": {"bytes_per_key": sched,
                          "implied_gkeys_at_peak": HBM_PEAK_GBPS / sched,
@@ -348,7 +348,9 @@ def bench_keys(args):
 def plan_passes(n: int, leaf: str, plan) -> int:
     """Global merge passes of the default plan: four-way while at least three
     runs remain, then binary (first-sweep runs of 2048 x leaf keys)."""
-    runs = -(-n // (2048 * (4 if leaf == "3To5" else 8)))
+    from paper_2503_05934_amd import _lib
+
+    runs = -(-n // (2048 * _lib.GROUP_KEYS[leaf]))
     p = 0
     while runs > 1:
         runs = -(-runs // (4 if runs >= 3 else 2))
@@ -508,7 +510,7 @@ def bench_segmented(args):
     # the dominant kernel: the block sort of every tile of the segments that
     # take the tiled path (longer than seg_block_max, at most 8 tiles)
     lens = (off_np[1:] - off_np[:-1]).astype(np.int64)
-    kk_ = 8 if args.leaf == "6To8" else 4
+    kk_ = _lib.GROUP_KEYS[args.leaf]
     bmax = (tuning or {}).get("seg_block_max") or 1024 * kk_
     tiled = int(lens[(lens > bmax) & (lens <= 8 * 1024 * kk_)].sum())
     seg_roof = _roof(stats, "seg_tile_sort", lambda m: 8.0 * tiled) if tiled else None
@@ -654,47 +656,60 @@ def bench_small(args):
 
 
 def bench_leaves(args):
-    """The paper's merge sort measurement (Figs. 1-3) replayed on the GPU:
-    the speedup of network leaves (6-to-8, 3-to-5) over the same sort with no
-    network (merges from single keys, the classical merge sort), Eq. 1:
-    t_classical / t_leaves, over the paper's sizes (10,000 to 1,000,000 int32
-    keys) and 2^28 uint32 keys, for random, sorted and nearly sorted inputs.
-    One graph replay per timed step; inputs up to 1,000,000 keys fit in the
-    Infinity Cache, so those numbers are cache-resident."""
+    """The paper's measurements (Figs. 1-3 for merge sort, 4-6 for quick sort)
+    replayed on the GPU for every network set of Table 3: the speedup of each
+    set over the same sort with no network at all (merges from single keys;
+    for the quick sort, block-sort leaves that merge from single keys),
+    Eq. 1: t_classical / t_set, over the paper's sizes (10,000 to 1,000,000
+    int32 keys) and 2^28 uint32 keys, for random, sorted and nearly sorted
+    inputs.  One graph replay per timed step; inputs up to 1,000,000 keys fit
+    in the Infinity Cache, so those numbers are cache-resident."""
     import torch
 
     import paper_2503_05934_amd as msn
-    from paper_2503_05934_amd import workloads
+    from paper_2503_05934_amd import _lib, workloads
 
     dev = torch.device("cuda:0")
     sizes = [10_000, 25_000, 50_000, 100_000, 250_000, 500_000, 1_000_000, 1 << 28]
+    sets = ["classical", "6To8", "3To5", "PowerOf2", "Even", "Odd", "3", "3To4", "3To8",
+            "VarSort3", "VarSort4", "VarSort5"]
     table = {}
     for n in sizes:
         dtype, tdt = ("u32", torch.uint32) if n == 1 << 28 else ("i32", torch.int32)
         steps = max(args.steps, 20) if n < 1 << 28 else max(2, args.steps // 4)
+        qws = torch.empty(_lib.quick_workspace_bytes(n, _lib.key_dtype(torch.empty(0, dtype=tdt))),
+                          dtype=torch.uint8, device=dev)
         for dist in workloads.DISTRIBUTIONS:
             x = torch.from_numpy(workloads.keys(n, dist, dtype, seed=0)).to(dev)
-            row = {}
-            for leaf in ("classical", "6To8", "3To5"):
+            ms_row, qs_row = {}, {}
+            ref = None
+            for leaf in sets:
                 plan = msn.SortPlan(n, tdt, dev, leaf=leaf)
-                plan.run(x)
-                torch.cuda.synchronize()
-                s = torch.cuda.Stream()
-                s.wait_stream(torch.cuda.current_stream())
-                gph = torch.cuda.CUDAGraph()
-                with torch.cuda.graph(gph, stream=s):
-                    plan.run(x)
-                ms, _ = time_steps(gph.replay, steps, args.warmup)
-                if n == 1 << 28 and not check_sorted_u32(plan.out, x):
-                    raise SystemExit(f"[bench] {leaf} output check failed")
-                row[leaf] = {"us": ms * 1e3, "gkeys_per_s": n / (ms / 1e3) / 1e9}
-                del plan, gph
-            for leaf in ("6To8", "3To5"):
-                row[leaf]["speedup"] = row["classical"]["us"] / row[leaf]["us"]
-            table[f"n={n} {dist}"] = row
-            log(f"[bench] n={n} {dist}: classical {row['classical']['us']:.1f} us, "
-                f"6To8 x{row['6To8']['speedup']:.2f}, 3To5 x{row['3To5']['speedup']:.2f}")
-    head = table[f"n={1 << 28} random"]
+                ms, _ = _graph_time(lambda: plan.run(x), steps, args.warmup)
+                if ref is None:
+                    ref = plan.out.clone()
+                elif not torch.equal(plan.out, ref):
+                    raise SystemExit(f"[bench] {leaf} merge sort output differs")
+                ms_row[leaf] = {"us": ms * 1e3}
+                del plan
+                qout = torch.empty_like(x)
+                qms, _ = _graph_time(lambda: msn.quick_sort(x, leaf=leaf, out=qout, workspace=qws),
+                                     steps, args.warmup)
+                if not torch.equal(qout, ref):
+                    raise SystemExit(f"[bench] {leaf} quick sort output differs")
+                qs_row[leaf] = {"us": qms * 1e3}
+                del qout
+            for row in (ms_row, qs_row):
+                for leaf in sets:
+                    row[leaf]["speedup"] = row["classical"]["us"] / row[leaf]["us"]
+            table[f"n={n} {dist}"] = {"merge_sort": ms_row, "quick_sort": qs_row}
+            log(f"[bench] n={n} {dist}: merge classical {ms_row['classical']['us']:.1f} us, "
+                + " ".join(f"{l} x{ms_row[l]['speedup']:.2f}" for l in sets[1:])
+                + f"; quick classical {qs_row['classical']['us']:.1f} us, "
+                + " ".join(f"{l} x{qs_row[l]['speedup']:.2f}" for l in sets[1:]))
+            del x
+        del qws
+    head = table[f"n={1 << 28} random"]["merge_sort"]
     return {
         "metric": "speedup of 6-to-8 network leaves over the network-free merge sort (Eq. 1), "
                   "2^28 uint32 keys random, 1 GPU",
@@ -702,9 +717,9 @@ def bench_leaves(args):
         "steps": max(2, args.steps // 4), "warmup": args.warmup,
         "ms_per_step": head["6To8"]["us"] / 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u32", "data": "synthetic",
-        "config": {"workload": "sort_keys with 6-to-8, 3-to-5 and no networks; 10,000 to "
-                               "1,000,000 int32 keys and 2^28 uint32 keys; random, sorted, "
-                               "nearly sorted; graph replay"},
+        "config": {"workload": "sort_keys and quick sort under every Table 3 set and with no "
+                               "networks; 10,000 to 1,000,000 int32 keys and 2^28 uint32 keys; "
+                               "random, sorted, nearly sorted; graph replay"},
         "table": table,
     }
 
@@ -750,7 +765,9 @@ def main():
     ap.add_argument("--workload", default="keys",
                     choices=["keys", "pairs", "segmented", "rows", "small", "leaves", "copy"])
     ap.add_argument("--n", type=int, default=1 << 28)
-    ap.add_argument("--leaf", default="6To8", choices=["6To8", "3To5", "classical"])
+    ap.add_argument("--leaf", default="6To8",
+                    choices=["6To8", "3To5", "classical", "PowerOf2", "Even", "Odd", "3", "3To4",
+                             "3To8", "VarSort3", "VarSort4", "VarSort5"])
     ap.add_argument("--merge-tile", type=int, default=0)
     ap.add_argument("--block-tile", type=int, default=0)
     ap.add_argument("--merge-ways", type=int, default=0)

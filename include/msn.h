@@ -53,13 +53,40 @@ extern "C" {
 #define MSN_I32 1
 #define MSN_F32 2
 
-/* base-case network sets (Table 3): the network size each lane applies */
-#define MSN_LEAF_6TO8 0 /* 8-key networks (6- and 7-key tails by padding) */
-#define MSN_LEAF_3TO5 1 /* 4-key networks (3-key tails by padding)        */
+/* Base-case network sets (Table 3).  Each lane sorts groups of 8 or 4 keys:
+   with the 8- or 4-key network when the set holds that size, else with two
+   member networks and one merge (5 + 3 keys, or 3 + 1).  A subarray of at
+   most one group (a short segment, a quick sort leaf) takes the network of
+   its own size when the set holds it.  Every set yields the same sorted
+   bits; only the work per key differs.
+       code              set          group of  group sorted by          short subarrays
+       MSN_LEAF_6TO8     {6,7,8}      8 keys    8-key network            up to 8 keys
+       MSN_LEAF_3TO5     {3,4,5}      4 keys    4-key network            up to 4 keys
+       MSN_LEAF_POW2     {4,8}        8 keys    8-key network            up to 8 keys
+       MSN_LEAF_EVEN     {4,6,8}      8 keys    8-key network            up to 8 keys
+       MSN_LEAF_ODD      {3,5,7}      8 keys    5- and 3-key networks    up to 8 keys
+       MSN_LEAF_3        {3}          4 keys    3-key network + 1 key    up to 4 keys
+       MSN_LEAF_3TO4     {3,4}        4 keys    4-key network            up to 4 keys
+       MSN_LEAF_3TO8     {3..8}       8 keys    8-key network            up to 8 keys
+       MSN_LEAF_VARSORT3 {2,3}        4 keys    3-key network + 1 key    up to 3 keys
+       MSN_LEAF_VARSORT4 {2,3,4}      4 keys    4-key network            up to 4 keys
+       MSN_LEAF_VARSORT5 {2..5}       8 keys    5- and 3-key networks    up to 5 keys
+   ("short subarrays": the default seg_lane_max of msn_segmented_sort.) */
+#define MSN_LEAF_6TO8 0
+#define MSN_LEAF_3TO5 1
 /* no network at all: merges from runs of one key, the classical merge sort
    the paper measures against (its empty network set); flat sorts only
    (msn_segmented_sort returns MSN_ERR_UNSUPPORTED), tiles as for 6-to-8 */
 #define MSN_LEAF_NONE 2
+#define MSN_LEAF_POW2 3
+#define MSN_LEAF_EVEN 4
+#define MSN_LEAF_ODD 5
+#define MSN_LEAF_3 6
+#define MSN_LEAF_3TO4 7
+#define MSN_LEAF_3TO8 8
+#define MSN_LEAF_VARSORT3 9
+#define MSN_LEAF_VARSORT4 10
+#define MSN_LEAF_VARSORT5 11
 
 /* status codes */
 #define MSN_OK 0
@@ -88,7 +115,8 @@ extern "C" {
  *   merge_tile      outputs per workgroup in a global merge pass:
  *                   2048, 4096 or 8192 (default 8192).
  *   seg_lane_max    segments of at most this many keys are sorted by one lane
- *                   with one network: 0..8 (default: the leaf size).
+ *                   with one network: 0 .. the group size (8 or 4; default:
+ *                   the leaf set's short-subarray limit above).
  *   seg_wave_max    segments up to this length are sorted by one wavefront:
  *                   up to 128 x leaf size (default 128 x leaf size).
  *   seg_block_max   segments up to this length are sorted by one workgroup

@@ -17,12 +17,21 @@ LIB_PATH = os.path.join(_HERE, "libmsn.so")
 # include/msn.h constants
 MSN_U32, MSN_I32, MSN_F32 = 0, 1, 2
 MSN_LEAF_6TO8, MSN_LEAF_3TO5, MSN_LEAF_NONE = 0, 1, 2
+MSN_LEAF_POW2, MSN_LEAF_EVEN, MSN_LEAF_ODD, MSN_LEAF_3, MSN_LEAF_3TO4, MSN_LEAF_3TO8 = 3, 4, 5, 6, 7, 8
+MSN_LEAF_VARSORT3, MSN_LEAF_VARSORT4, MSN_LEAF_VARSORT5 = 9, 10, 11
 MSN_ARGSORT = 1
 MSN_DEBUG_CHECK = 2
 MSN_SEG_BAD_FIRST, MSN_SEG_BAD_ORDER, MSN_SEG_BAD_LAST, MSN_SEG_BAD_RESULT = 1, 2, 4, 8
 MSN_NOALLOC_MAX_KEYS = 4194304
 
-LEAVES = {"6To8": MSN_LEAF_6TO8, "3To5": MSN_LEAF_3TO5, "classical": MSN_LEAF_NONE}
+# Table 3's names (and "classical" for the empty set)
+LEAVES = {"6To8": MSN_LEAF_6TO8, "3To5": MSN_LEAF_3TO5, "classical": MSN_LEAF_NONE,
+          "PowerOf2": MSN_LEAF_POW2, "Even": MSN_LEAF_EVEN, "Odd": MSN_LEAF_ODD, "3": MSN_LEAF_3,
+          "3To4": MSN_LEAF_3TO4, "3To8": MSN_LEAF_3TO8, "VarSort3": MSN_LEAF_VARSORT3,
+          "VarSort4": MSN_LEAF_VARSORT4, "VarSort5": MSN_LEAF_VARSORT5}
+# keys of a lane's group under each set (8 or 4): the tile shapes follow it
+GROUP_KEYS = {"6To8": 8, "3To5": 4, "classical": 8, "PowerOf2": 8, "Even": 8, "Odd": 8, "3": 4,
+              "3To4": 4, "3To8": 8, "VarSort3": 4, "VarSort4": 4, "VarSort5": 8}
 _DTYPES = {torch.uint32: MSN_U32, torch.int32: MSN_I32, torch.float32: MSN_F32}
 
 
@@ -132,6 +141,15 @@ def leaf_code(leaf) -> int:
         return LEAVES[leaf]
     except KeyError:
         raise ValueError(f"leaf must be one of {sorted(LEAVES)}, not {leaf!r}") from None
+
+
+def group_keys(leaf) -> int:
+    """Keys of a lane's group (8 or 4) under a leaf set given by name or code."""
+    code = leaf_code(leaf)
+    for name, c in LEAVES.items():
+        if c == code:
+            return GROUP_KEYS[name]
+    raise ValueError(f"unknown leaf code {leaf!r}")
 
 
 def ptr(t: torch.Tensor | None):

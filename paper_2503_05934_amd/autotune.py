@@ -158,7 +158,7 @@ def tuned_sort_params(keys: torch.Tensor, *, pairs: bool, leaf, reps: int = 3,
             return sort_pairs(keys, None, leaf=leaf, tuning=t)
         return (sort(keys, leaf=leaf, tuning=t),)
 
-    k = 4 if lc == _lib.MSN_LEAF_3TO5 else 8
+    k = _lib.group_keys(lc)
     best, _ = tune(run, sort_candidates(k, not pairs and dt != _lib.MSN_F32), reps)
     store(key, best)
     return best
@@ -177,7 +177,7 @@ def tuned_segmented_params(keys: torch.Tensor, offsets, *, num_segments: int, va
     hit = None if force else lookup(key)
     if hit is not None:
         return hit
-    k = 4 if lc == _lib.MSN_LEAF_3TO5 else 8
+    k = _lib.group_keys(lc)
 
     def run(t):
         out = segmented_sort(keys, offsets, vals, num_segments=num_segments, argsort=argsort,

@@ -4,6 +4,7 @@
 // touches the GPU.
 #include <string.h>
 
+#include <initializer_list>
 #include <map>
 #include <mutex>
 #include <string>
@@ -75,10 +76,48 @@ namespace {
 constexpr int64_t kMaxN = 0x7fffffffLL;
 
 bool valid_dtype(int d) { return d == MSN_U32 || d == MSN_I32 || d == MSN_F32; }
-// Keys of the base-case network (the network-free sort keeps the 6-to-8
-// tile shapes).
+// A network set of Table 3 on the GPU: the keys of a lane's group, how the
+// group is sorted (msn::kNet*), the set's network sizes (bit k = size k) and
+// the longest subarray one lane sorts by default in the batched sort.
+struct LeafSet {
+    int group;
+    int net;
+    uint32_t sizes;
+    int lane_max;
+};
+
+constexpr uint32_t bits(std::initializer_list<int> l) {
+    uint32_t m = 0;
+    for (int x : l) m |= 1u << x;
+    return m;
+}
+
+// Returns false for an unknown code.  The network-free sort keeps the 6-to-8
+// tile shapes.
+bool leaf_set(int leaf, LeafSet* out) {
+    using msn::kNetNone;
+    using msn::kNetPlain;
+    using msn::kNetSplit;
+    switch (leaf) {
+        case MSN_LEAF_6TO8: *out = {8, kNetPlain, bits({6, 7, 8}), 8}; return true;
+        case MSN_LEAF_3TO5: *out = {4, kNetPlain, bits({3, 4, 5}), 4}; return true;
+        case MSN_LEAF_NONE: *out = {8, kNetNone, 0u, 0}; return true;
+        case MSN_LEAF_POW2: *out = {8, kNetPlain, bits({4, 8}), 8}; return true;
+        case MSN_LEAF_EVEN: *out = {8, kNetPlain, bits({4, 6, 8}), 8}; return true;
+        case MSN_LEAF_ODD: *out = {8, kNetSplit, bits({3, 5, 7}), 8}; return true;
+        case MSN_LEAF_3: *out = {4, kNetSplit, bits({3}), 4}; return true;
+        case MSN_LEAF_3TO4: *out = {4, kNetPlain, bits({3, 4}), 4}; return true;
+        case MSN_LEAF_3TO8: *out = {8, kNetPlain, bits({3, 4, 5, 6, 7, 8}), 8}; return true;
+        case MSN_LEAF_VARSORT3: *out = {4, kNetSplit, bits({2, 3}), 3}; return true;
+        case MSN_LEAF_VARSORT4: *out = {4, kNetPlain, bits({2, 3, 4}), 4}; return true;
+        case MSN_LEAF_VARSORT5: *out = {8, kNetSplit, bits({2, 3, 4, 5}), 5}; return true;
+        default: return false;
+    }
+}
+
 int leaf_keys(int leaf) {
-    return leaf == MSN_LEAF_6TO8 || leaf == MSN_LEAF_NONE ? 8 : leaf == MSN_LEAF_3TO5 ? 4 : 0;
+    LeafSet ls;
+    return leaf_set(leaf, &ls) ? ls.group : 0;
 }
 
 bool misaligned(const void* p) { return p && ((uintptr_t)p & 3u) != 0; }
@@ -90,14 +129,15 @@ bool bad_overlap(const void* a, const void* b, int64_t n) {
     return x < y + len && y < x + len;
 }
 
-// Two ranges of n words that share any word (equal starts included): the
-// pairs that must stay apart even for in-place calls (a key array and a value
-// array).
-bool any_overlap(const void* a, const void* b, int64_t n) {
-    if (!a || !b) return false;
-    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b, len = (uintptr_t)n * 4;
-    return x < y + len && y < x + len;
+// Ranges of na and nb words that share any word (equal starts included):
+// the pairs that must stay apart even for in-place calls (a key array and a
+// value array, the offsets and an output).
+bool ranges_overlap(const void* a, int64_t na, const void* b, int64_t nb) {
+    if (!a || !b || na <= 0 || nb <= 0) return false;
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + (uintptr_t)nb * 4 && y < x + (uintptr_t)na * 4;
 }
+bool any_overlap(const void* a, const void* b, int64_t n) { return ranges_overlap(a, n, b, n); }
 
 int merge_tile_of(const msn_tuning* t, int* out) {
     int mt = t && t->merge_tile ? t->merge_tile : msn::kDefaultMergeTile;
@@ -158,7 +198,9 @@ int sort_common(const void* keys_in, const uint32_t* vals_in, void* keys_out, ui
     msn::SortArgs a{static_cast<const uint32_t*>(keys_in), vals_in,
                     static_cast<uint32_t*>(keys_out), vals_out, n, dtype, k, vmode, mt, bt, mw, m4k, ws,
                     ws_bytes, static_cast<hipStream_t>(stream)};
-    a.nets = leaf != MSN_LEAF_NONE;
+    LeafSet ls;
+    leaf_set(leaf, &ls);
+    a.nets = ls.net;
     return msn::launch_sort(a);
 }
 
@@ -296,8 +338,10 @@ int msn_quick_sort_keys(const void* keys_in, void* keys_out, int64_t n, int dtyp
     if (bad_overlap(keys_in, keys_out, n)) return MSN_ERR_SIZE;
     const size_t need = msn::quick_ws_bytes(n);
     if (!ws || ws_bytes < need) return MSN_ERR_WORKSPACE;
+    LeafSet ls;
+    leaf_set(leaf, &ls);
     msn::QuickArgs a{static_cast<const uint32_t*>(keys_in), static_cast<uint32_t*>(keys_out), n,
-                     dtype, k, leaf != MSN_LEAF_NONE, rounds, ws, ws_bytes,
+                     dtype, k, ls.net, ls.sizes, rounds, ws, ws_bytes,
                      static_cast<hipStream_t>(stream)};
     return msn::launch_quick(a);
 }
@@ -330,9 +374,11 @@ int msn_segmented_sort(const void* keys_in, const uint32_t* vals_in, void* keys_
     if (num_segments == 0) return n_total == 0 ? MSN_OK : MSN_ERR_SIZE;
     if (!offsets && n_total % num_segments != 0) return MSN_ERR_SIZE;
 
+    LeafSet ls;
+    leaf_set(leaf, &ls);
     const int tile = 2 * k * msn::kBlockThreads;    // 2k keys per lane in a workgroup
     const int wave_tile = 2 * k * msn::kWave;
-    int lane_max = k, wave_max = wave_tile, block_max = tile, grid = 0;
+    int lane_max = ls.lane_max, wave_max = wave_tile, block_max = tile, grid = 0;
     if (tuning) {
         if (tuning->seg_lane_max) lane_max = tuning->seg_lane_max;
         if (tuning->seg_wave_max) wave_max = tuning->seg_wave_max;
@@ -350,7 +396,8 @@ int msn_segmented_sort(const void* keys_in, const uint32_t* vals_in, void* keys_
     if (bad_overlap(keys_in, keys_out, n_total) || bad_overlap(vals_in, vals_out, n_total) ||
         (vals_out && (bad_overlap(keys_out, vals_out, n_total) || keys_out == (void*)vals_out)) ||
         any_overlap(keys_in, vals_out, n_total) || any_overlap(vals_in, keys_out, n_total) ||
-        any_overlap(offsets, keys_out, n_total) || any_overlap(offsets, vals_out, n_total))
+        ranges_overlap(offsets, num_segments + 1, keys_out, n_total) ||
+        ranges_overlap(offsets, num_segments + 1, vals_out, n_total))
         return MSN_ERR_SIZE;
     const int vmode = argsort ? msn::kArg : vals_in ? msn::kVals : msn::kNoVals;
     const size_t need = msn::seg_ws_bytes(n_total, num_segments, vmode != msn::kNoVals);
@@ -373,6 +420,8 @@ int msn_segmented_sort(const void* keys_in, const uint32_t* vals_in, void* keys_
                    ws_bytes,
                    static_cast<hipStream_t>(stream)};
     a.debug_check = (flags & MSN_DEBUG_CHECK) != 0;
+    a.net = ls.net;
+    a.set_mask = ls.sizes;
     return msn::launch_segmented(a);
 }
 

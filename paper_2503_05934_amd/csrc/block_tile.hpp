@@ -72,7 +72,7 @@ __device__ __forceinline__ void write_samples(const Samples& samp, int first, in
 // 32 - kPackPosBits bits sort 32-bit (key, position) composites instead of
 // 64-bit ones (a run-time choice per tile).
 template <int DT, int K, bool STABLE, int VM, int SHAPE = 0, bool WIDE = false,
-          bool PACK = false, bool NETS = true>
+          bool PACK = false, int NETS = kNetPlain>
 __device__ __forceinline__ void block_sort_tile(const uint32_t* kin, const uint32_t* vin,
                                                 uint32_t* kout, uint32_t* vout, int nv,
                                                 uint32_t val_base, void* smem,
@@ -80,7 +80,8 @@ __device__ __forceinline__ void block_sort_tile(const uint32_t* kin, const uint3
     using Tr = TileTraits<DT, K, STABLE, SHAPE>;
     using T = typename Tr::T;
     static_assert(STABLE || (DT != kF32 && VM == kNoVals), "float keys and pairs sort stably");
-    static_assert(NETS || (!WIDE && !PACK), "the network-free tile takes the plain paths");
+    static_assert(NETS != kNetNone || (!WIDE && !PACK),
+                  "the network-free tile takes the plain paths");
     T* s = reinterpret_cast<T*>(smem);
     const int tid = threadIdx.x;
     constexpr int KPL = Tr::kKPL;
@@ -116,7 +117,7 @@ __device__ __forceinline__ void block_sort_tile(const uint32_t* kin, const uint3
     if constexpr (WIDE && Tr::kWideOk) {
         constexpr int MK = 2 * KPL;
         T o[MK];
-        block_sort_regs2<T, K, KPL, MK>(v, o, s, span);
+        block_sort_regs2<T, K, KPL, MK, NETS>(v, o, s, span);
         const int first2 = tid * MK;
         if (first2 < span) {
             uint32_t y[MK];
@@ -135,8 +136,8 @@ __device__ __forceinline__ void block_sort_tile(const uint32_t* kin, const uint3
             }
         }
     } else if constexpr (!STABLE) {
-        if constexpr (NETS)
-            block_sort_regs<T, K, KPL>(v, s, span);
+        if constexpr (NETS != kNetNone)
+            block_sort_regs<T, K, KPL, NETS>(v, s, span);
         else
             block_merge_only<T, KPL>(v, s, span);
 #pragma unroll
@@ -173,7 +174,7 @@ __device__ __forceinline__ void block_sort_tile(const uint32_t* kin, const uint3
                     w[j] = (first + j < nv)
                                ? (ord_key<DT>(x[j]) << kPackPosBits) | (uint32_t)(first + j)
                                : 0xffffffffu;
-                block_sort_regs2<uint32_t, K, KPL, MK>(w, o, reinterpret_cast<uint32_t*>(smem),
+                block_sort_regs2<uint32_t, K, KPL, MK, NETS>(w, o, reinterpret_cast<uint32_t*>(smem),
                                                        span);
                 if constexpr (kNeedBits || kNeedVals) {
                     for (int i = tid; i < nv; i += Tr::kThreads) {
@@ -216,8 +217,8 @@ __device__ __forceinline__ void block_sort_tile(const uint32_t* kin, const uint3
                 return;
             }
         }
-        if constexpr (NETS)
-            block_sort_regs<T, K, KPL>(v, s, span);
+        if constexpr (NETS != kNetNone)
+            block_sort_regs<T, K, KPL, NETS>(v, s, span);
         else
             block_merge_only<T, KPL>(v, s, span);
         // Stage what must be gathered by position (float bits, payload).

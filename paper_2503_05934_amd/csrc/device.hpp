@@ -149,6 +149,85 @@ __device__ __forceinline__ void leaf_network(T (&v)[K]) {
     if constexpr (K == 8) network8(v); else network4(v);
 }
 
+// Largest value of a register key: the padding of short runs and the
+// sentinel that closes every LDS run.
+template <typename T>
+__device__ __forceinline__ constexpr T key_max() {
+    return sizeof(T) == 8 ? (T)~0ull : (T)0xffffffffu;
+}
+
+// The N-input network (2 <= N <= K) on v[0..N): the K-input network with
+// inputs N..K-1 fixed at the largest value.  Those inputs are compile-time
+// constants here, so every comparator that touches them folds away and what
+// remains is the pruned N-key network (Batcher's construction restricted to
+// N wires).
+template <typename T, int K, int N>
+__device__ __forceinline__ void pruned_network(T (&v)[K]) {
+    static_assert(N >= 1 && N <= K, "network size");
+#pragma unroll
+    for (int j = N; j < K; ++j) v[j] = key_max<T>();
+    leaf_network<T, K>(v);
+}
+
+// Network families (kNetNone / kNetPlain / kNetSplit, internal.hpp): how a
+// lane sorts one group of K keys.
+//   kNetPlain: the K-key network (sets that hold K: 6-to-8, PowerOf2, Even,
+//     3-to-8 for K = 8; 3-to-5, 3-to-4, VarSort4 for K = 4);
+//   kNetSplit: two member networks and one merge, for sets without a
+//     K-key member: K = 8 sorts keys 0..4 with the 5-key network and keys
+//     5..7 with the 3-key network (Odd = {3, 5, 7}, VarSort5 = {2..5});
+//     K = 4 sorts keys 0..2 with the 3-key network and takes key 3 alone
+//     (the set {3}, VarSort3).  The two sorted pieces, the second reversed,
+//     form a bitonic sequence that half-cleaners at distances K/2 .. 1 sort.
+template <typename T, int K, int NET>
+__device__ __forceinline__ void leaf_group(T (&v)[K]) {
+    static_assert(NET == kNetPlain || NET == kNetSplit, "network family");
+    if constexpr (NET == kNetPlain) {
+        leaf_network<T, K>(v);
+    } else {
+        constexpr int A = K == 8 ? 5 : 3;  // keys of the first piece
+        T a[K], b[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            a[j] = j < A ? v[j] : key_max<T>();
+            b[j] = j < K - A ? v[A + j] : key_max<T>();
+        }
+        if constexpr (A > 1) pruned_network<T, K, A>(a);
+        if constexpr (K - A > 1) pruned_network<T, K, K - A>(b);
+        // ascending first piece, then the second piece descending
+#pragma unroll
+        for (int j = 0; j < A; ++j) v[j] = a[j];
+#pragma unroll
+        for (int j = 0; j < K - A; ++j) v[K - 1 - j] = b[j];
+#pragma unroll
+        for (int d = K / 2; d >= 1; d >>= 1) {
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+                if ((j & d) == 0) cx(v[j], v[j + d]);
+        }
+    }
+}
+
+// A lane's whole subarray of len <= K keys (v[len..K) hold the largest
+// value): the network of that size when the configured set holds it (bit
+// len of set_mask), else the family's group procedure on the padded keys --
+// the role of the paper's variable-size networks (VarSort, Table 3).
+template <typename T, int K, int NET>
+__device__ __forceinline__ void lane_networks(T (&v)[K], int len, uint32_t set_mask) {
+    if (len < K && ((set_mask >> len) & 1u)) {
+        switch (len) {
+            case 2: pruned_network<T, K, 2>(v); return;
+            case 3: pruned_network<T, K, 3>(v); return;
+            case 4: if constexpr (K > 4) { pruned_network<T, K, 4>(v); return; } break;
+            case 5: if constexpr (K > 5) { pruned_network<T, K, 5>(v); return; } break;
+            case 6: if constexpr (K > 6) { pruned_network<T, K, 6>(v); return; } break;
+            case 7: if constexpr (K > 7) { pruned_network<T, K, 7>(v); return; } break;
+            default: break;
+        }
+    }
+    leaf_group<T, K, NET>(v);
+}
+
 // -------------------------------------------------------- lane exchanges ---
 // Value of x in lane (lane ^ mask).  Patterns that DPP can express inside a
 // row of 16 lanes go through the VALU's data-parallel-primitive moves:
@@ -333,13 +412,6 @@ struct OrdLess {
     }
 };
 
-// Largest value of a register key: the padding of short runs and the
-// sentinel that closes every LDS run.
-template <typename T>
-__device__ __forceinline__ constexpr T key_max() {
-    return sizeof(T) == 8 ? (T)~0ull : (T)0xffffffffu;
-}
-
 // Sequential merge of N outputs from LDS runs that are each followed by at
 // least N copies of key_max(): no bounds checks are needed, because a used-up
 // run offers the maximum, which is taken only when the other run's key is the
@@ -409,14 +481,14 @@ __device__ __forceinline__ void lane_merge_halves(T (&v)[N]) {
 
 // Each group of K keys in v[0..N) sorted by the K-key network, then the
 // groups merged in-lane into one sorted run of N keys.
-template <typename T, int K, int N>
+template <typename T, int K, int N, int NET = kNetPlain>
 __device__ __forceinline__ void lane_sort(T (&v)[N]) {
 #pragma unroll
     for (int g = 0; g < N; g += K) {
         T w[K];
 #pragma unroll
         for (int j = 0; j < K; ++j) w[j] = v[g + j];
-        leaf_network<T, K>(w);
+        leaf_group<T, K, NET>(w);
 #pragma unroll
         for (int j = 0; j < K; ++j) v[g + j] = w[j];
     }
@@ -446,13 +518,13 @@ __host__ __device__ constexpr int block_lds_words(int n) {
 // two, at least 64*KPL): lanes beyond it still take part in barriers but skip
 // the work.  On return thread t holds outputs t*KPL .. t*KPL+KPL-1 of the
 // sorted span.  s is LDS of block_lds_words<T, KPL>(tile keys) words.
-template <typename T, int K, int KPL>
+template <typename T, int K, int KPL, int NET = kNetPlain>
 __device__ __forceinline__ void block_sort_regs(T (&v)[KPL], T* s, int span) {
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const bool active = tid * KPL < span;
     if (active) {
-        lane_sort<T, K, KPL>(v);
+        lane_sort<T, K, KPL, NET>(v);
         wave_merge<T, KPL>(v, lane);
     }
     for (int L = kWave * KPL; L < span; L <<= 1) {
@@ -544,14 +616,14 @@ __host__ __device__ constexpr int block_lds_words2(int n) {
 // threads at MK = 2 KPL outputs each (one co-rank search per MK outputs): on
 // return thread t < threads/2 holds outputs t*MK .. t*MK+MK-1 of the sorted
 // span in o[].  s is LDS of block_lds_words2<T, KPL, MK>(tile keys) words.
-template <typename T, int K, int KPL, int MK>
+template <typename T, int K, int KPL, int MK, int NET = kNetPlain>
 __device__ __forceinline__ void block_sort_regs2(T (&v)[KPL], T (&o)[MK], T* s, int span) {
     static_assert(MK == 2 * KPL, "two lanes' keys per merger");
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     int L = kWave * KPL;  // wavefront runs
     if (tid * KPL < span) {
-        lane_sort<T, K, KPL>(v);
+        lane_sort<T, K, KPL, NET>(v);
         wave_merge<T, KPL>(v, lane);
         // run r occupies [r*(L+MK), r*(L+MK)+L), then MK sentinels
         const int e = tid * KPL;

@@ -15,6 +15,13 @@ constexpr int kMergeThreads = 256;   // global merge pass
 
 enum KeyType : int { kU32 = 0, kI32 = 1, kF32 = 2 };
 
+// How a lane sorts one group of its keys (the leaf set's network family):
+// no network (merges from single keys), the group-sized network, or two
+// member networks and a merge (sets without a member of the group's size).
+constexpr int kNetNone = 0;
+constexpr int kNetPlain = 1;
+constexpr int kNetSplit = 2;
+
 // Values travelling with the keys.
 enum ValMode : int {
     kNoVals = 0,  // keys only
@@ -38,7 +45,9 @@ struct SortArgs {
     void* ws;
     size_t ws_bytes;
     hipStream_t stream;
-    int nets = 1;         // 0: no networks (the classical merge sort), tiles of leaf_k = 8
+    int nets = 1;         // network family: 0 none (the classical merge sort, tiles of
+                          // leaf_k = 8), 1 the leaf_k-key network, 2 two member
+                          // networks and a merge (sets without a leaf_k-key member)
 };
 
 struct SegArgs {
@@ -57,6 +66,8 @@ struct SegArgs {
     size_t ws_bytes;
     hipStream_t stream;
     int debug_check = 0;      // MSN_DEBUG_CHECK: verify every segment after sorting
+    int net = 1;              // network family of the leaves (kNetPlain / kNetSplit)
+    uint32_t set_mask = ~0u;  // network sizes of the leaf set (bit k = size k)
 };
 
 constexpr size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -142,7 +153,8 @@ struct QuickArgs {
     int64_t n;
     int dtype;       // kU32 or kI32
     int leaf_k;      // keys of the leaf network: 8 or 4
-    int nets;        // 0: no networks anywhere (the classical quick sort), tiles of leaf_k = 8
+    int nets;        // network family as in SortArgs (0: the classical quick sort)
+    uint32_t set_mask;  // network sizes of the leaf set (bit k = size k)
     int rounds;      // partition rounds (0 = quick_rounds(n, leaf tile))
     void* ws;
     size_t ws_bytes;

@@ -348,10 +348,11 @@ struct QLeafRound {
     uint32_t* wk;         // the workspace buffer (scratch of big items)
     QList* lin;           // this round's leaf list
     uint32_t cap;
+    uint32_t set_mask;    // network sizes of the leaf set
 };
 
 // Leaf and big items, one workgroup each.
-template <int DT, int K, bool NETS>
+template <int DT, int K, int NETS>
 __global__ __launch_bounds__(kBlockThreads, 4) void k_qs_leaf(QLeafRound r) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int tid = threadIdx.x;
@@ -361,15 +362,15 @@ __global__ __launch_bounds__(kBlockThreads, 4) void k_qs_leaf(QLeafRound r) {
         const QItem it = items[i];
         if (it.kind == kQLeaf) {
             constexpr int KPL = TileTraits<DT, K, false>::kKPL;
-            if (NETS && it.len <= (uint32_t)K) {
+            if (NETS != kNetNone && it.len <= (uint32_t)K) {
                 if (tid == 0)
-                    lane_task<DT, K, false, kNoVals>(r.cur, nullptr, r.out, nullptr, it.start,
-                                                     (int)it.len);
+                    lane_task<DT, K, false, kNoVals, NETS == kNetNone ? kNetPlain : NETS>(
+                        r.cur, nullptr, r.out, nullptr, it.start, (int)it.len, r.set_mask);
             } else {
                 const bool done = copy_if_in_order<DT, KPL>(r.cur + it.start, r.out + it.start,
                                                             (int)it.len, smem);
                 if (!__builtin_amdgcn_readfirstlane(done))
-                    block_sort_tile<DT, K, false, kNoVals, 0, NETS, false, NETS>(
+                    block_sort_tile<DT, K, false, kNoVals, 0, NETS != kNetNone, false, NETS>(
                         r.cur + it.start, nullptr, r.out + it.start, nullptr, (int)it.len, 0u,
                         smem);
             }
@@ -405,7 +406,7 @@ namespace {
 size_t q_cap(int64_t n) { return 3 * (size_t)(n / 4097) + 3; }
 size_t q_list_bytes(int64_t n) { return align_up(sizeof(QList) + q_cap(n) * sizeof(QItem), 256); }
 
-template <int DT, int K, bool NETS>
+template <int DT, int K, int NETS>
 constexpr size_t q_leaf_lds() {
     return SegTraits<DT, K, false, kNoVals>::kLds;
 }
@@ -439,7 +440,7 @@ int q_grid(Kern kern, size_t lds, int* out) {
     return 0;
 }
 
-template <int DT, int K, bool NETS>
+template <int DT, int K, int NETS>
 int q_run(const QuickArgs& a) {
     constexpr uint32_t kLeafMax = TileTraits<DT, K, false>::kTile;
     auto pkern = &k_qs_part<DT>;
@@ -495,6 +496,7 @@ int q_run(const QuickArgs& a) {
         ql.wk = wk;
         ql.lin = L[r % 3];
         ql.cap = cap;
+        ql.set_mask = a.set_mask;
         LaunchTimer timer(kinds.leaf[r], a.n, a.stream);
         hipLaunchKernelGGL(lkern, dim3(lgrid), dim3(kBlockThreads), llds, a.stream, ql);
         if (int rc = (int)hipGetLastError()) return rc;
@@ -504,8 +506,10 @@ int q_run(const QuickArgs& a) {
 
 template <int DT>
 int q_dispatch(const QuickArgs& a) {
-    if (!a.nets) return q_run<DT, 8, false>(a);
-    return a.leaf_k == 8 ? q_run<DT, 8, true>(a) : q_run<DT, 4, true>(a);
+    if (a.nets == kNetNone) return q_run<DT, 8, kNetNone>(a);
+    if (a.nets == kNetSplit)
+        return a.leaf_k == 8 ? q_run<DT, 8, kNetSplit>(a) : q_run<DT, 4, kNetSplit>(a);
+    return a.leaf_k == 8 ? q_run<DT, 8, kNetPlain>(a) : q_run<DT, 4, kNetPlain>(a);
 }
 
 }  // namespace

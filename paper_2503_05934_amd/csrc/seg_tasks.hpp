@@ -21,10 +21,13 @@ __host__ __device__ constexpr int seg_merge_words(int t) {
 
 
 // ------------------------------------------------------------ lane tasks ---
-template <int DT, int K, bool STABLE, int VM>
+// One lane sorts a subarray of len <= K keys with one network: the network
+// of size len when the configured set holds it (bit len of set_mask), else
+// the family's group procedure on the padded keys.
+template <int DT, int K, bool STABLE, int VM, int NET>
 __device__ __forceinline__ void lane_task(const uint32_t* kin, const uint32_t* vin,
                                           uint32_t* kout, uint32_t* vout, uint32_t off,
-                                          int len) {
+                                          int len, uint32_t set_mask) {
     using T = typename TileTraits<DT, K, STABLE>::T;
     uint32_t raw[K], pv[K];
     T v[K];
@@ -38,7 +41,7 @@ __device__ __forceinline__ void lane_task(const uint32_t* kin, const uint32_t* v
         else
             v[j] = live ? ord_key<DT>(raw[j]) : 0xffffffffu;
     }
-    leaf_network<T, K>(v);
+    lane_networks<T, K, NET>(v, len, set_mask);
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         if (j >= len) break;
@@ -63,7 +66,7 @@ __device__ __forceinline__ void lane_task(const uint32_t* kin, const uint32_t* v
 // One wavefront sorts one segment of at most 64*KPL keys (KPL = 2K keys per
 // lane).  wst: this wave's private LDS staging (2 * 64 * KPL words) for
 // position gathers.
-template <int DT, int K, bool STABLE, int VM>
+template <int DT, int K, bool STABLE, int VM, int NET>
 __device__ __forceinline__ void wave_task(const uint32_t* kin, const uint32_t* vin,
                                           uint32_t* kout, uint32_t* vout, uint32_t off, int len,
                                           uint32_t* wst) {
@@ -88,8 +91,8 @@ __device__ __forceinline__ void wave_task(const uint32_t* kin, const uint32_t* v
             lo[j] = v[j];
             hi[j] = v[K + j];
         }
-        leaf_network<T, K>(lo);
-        leaf_network<T, K>(hi);
+        leaf_group<T, K, NET>(lo);
+        leaf_group<T, K, NET>(hi);
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             v[j] = lo[j];
@@ -368,8 +371,9 @@ __device__ __forceinline__ bool copy_if_in_order(const uint32_t* kin, uint32_t* 
     return true;
 }
 
-// NETS = false sorts the tiles with no network (merges from runs of one key).
-template <int DT, int K, bool STABLE, int VM, bool NETS = true>
+// NETS: the network family of the tiles (kNetNone: merges from runs of one
+// key).
+template <int DT, int K, bool STABLE, int VM, int NETS>
 __device__ void big_task(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
                          uint32_t* wk, uint32_t* wv, uint32_t off, int len, void* smem) {
     constexpr int kTile = TileTraits<DT, K, STABLE>::kTile;

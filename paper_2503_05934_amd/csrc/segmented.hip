@@ -203,11 +203,11 @@ __global__ __launch_bounds__(256) void k_seg_verify(const uint32_t* __restrict__
 // a few hundred bytes for the 8-key stable tiles), and both are faster for
 // it: 4 % on the 100,000-segment workload, 25 % on the fp32 row argsort,
 // where one workgroup per compute unit could not hide its LDS latency.
-template <int DT, int K, bool STABLE, int VM>
+template <int DT, int K, bool STABLE, int VM, int NET>
 __global__ __launch_bounds__(kBlockThreads, STABLE ? 4 : 6) void k_segmented(
     const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, uint32_t* wk,
     uint32_t* wv, const uint32_t* __restrict__ offsets, int64_t num_segments, uint32_t uni_len,
-    SegState* st, const uint32_t* __restrict__ lists) {
+    SegState* st, const uint32_t* __restrict__ lists, uint32_t set_mask) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t s_item;
     const int tid = threadIdx.x;
@@ -238,7 +238,7 @@ __global__ __launch_bounds__(kBlockThreads, STABLE ? 4 : 6) void k_segmented(
         if (item < e0) {
             uint32_t off, len;
             seg_bounds(offsets, L[kCBig * S + item], uni_len, off, len);
-            big_task<DT, K, STABLE, VM>(kin, vin, kout, vout, wk, wv, off, (int)len, smem);
+            big_task<DT, K, STABLE, VM, NET>(kin, vin, kout, vout, wk, wv, off, (int)len, smem);
         } else if (item < e2) {
             uint32_t off, len;
             seg_bounds(offsets, L[kCBlock * S + (item - e0)], uni_len, off, len);
@@ -247,7 +247,8 @@ __global__ __launch_bounds__(kBlockThreads, STABLE ? 4 : 6) void k_segmented(
                 done = copy_if_in_order<DT, keys_per_lane<K>()>(kin + off, kout + off, (int)len,
                                                                 smem);
             if (!__builtin_amdgcn_readfirstlane(done))
-                block_sort_tile<DT, K, STABLE, VM>(kin + off, VM == kVals ? vin + off : nullptr,
+                block_sort_tile<DT, K, STABLE, VM, 0, false, false, NET>(
+                    kin + off, VM == kVals ? vin + off : nullptr,
                                                    kout + off,
                                                    VM != kNoVals ? vout + off : nullptr, (int)len,
                                                    0u, smem);
@@ -259,14 +260,15 @@ __global__ __launch_bounds__(kBlockThreads, STABLE ? 4 : 6) void k_segmented(
                 seg_bounds(offsets, L[kCWave * S + idx], uni_len, off, len);
                 uint32_t* wst = reinterpret_cast<uint32_t*>(smem) +
                                 (size_t)w * 2 * kWave * keys_per_lane<K>();
-                wave_task<DT, K, STABLE, VM>(kin, vin, kout, vout, off, (int)len, wst);
+                wave_task<DT, K, STABLE, VM, NET>(kin, vin, kout, vout, off, (int)len, wst);
             }
         } else {
             const uint32_t idx = (item - e3) * kBlockThreads + (uint32_t)tid;
             if (idx < n_lane) {
                 uint32_t off, len;
                 seg_bounds(offsets, L[kCLane * S + idx], uni_len, off, len);
-                lane_task<DT, K, STABLE, VM>(kin, vin, kout, vout, off, (int)len);
+                lane_task<DT, K, STABLE, VM, NET>(kin, vin, kout, vout, off, (int)len,
+                                                  set_mask);
             }
         }
     }
@@ -279,7 +281,7 @@ __global__ __launch_bounds__(kBlockThreads, STABLE ? 4 : 6) void k_segmented(
 // outputs per thread in its LDS levels, its own register budget), each run
 // written where its segment's first merge pass reads it (the output itself
 // for one run).
-template <int DT, int K, bool STABLE, int VM>
+template <int DT, int K, bool STABLE, int VM, int NET>
 __global__ __launch_bounds__((SegRun<DT, K, STABLE>::Tr::kThreads),
                              (SegRun<DT, K, STABLE>::Tr::kWavesPerSimd))
 void k_seg_tile_sort(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
@@ -307,7 +309,8 @@ void k_seg_tile_sort(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, u
         bool done = false;
         if constexpr (!STABLE) done = copy_if_in_order<DT, Tr::kKPL>(ks, kd, nv, smem);
         if (!__builtin_amdgcn_readfirstlane(done))
-            block_sort_tile<DT, K, STABLE, VM, R::kShape, true>(ks, vs, kd, vd, nv, first, smem);
+            block_sort_tile<DT, K, STABLE, VM, R::kShape, true, false, NET>(ks, vs, kd, vd, nv,
+                                                                            first, smem);
         __syncthreads();  // the next run reuses the LDS
     }
 }
@@ -424,14 +427,14 @@ struct SegWs {
     size_t max_tiles;
 };
 
-template <int DT, int K, bool STABLE, int VM>
+template <int DT, int K, bool STABLE, int VM, int NET>
 int launch_seg_kernel(const SegArgs& a, const SegWs& w, uint32_t uni_len) {
     using Tr = SegTraits<DT, K, STABLE, VM>;
     constexpr bool kVals = VM != kNoVals;
     constexpr int kTile = TileTraits<DT, K, STABLE>::kTile;
     constexpr int kKpt = kTile / kBlockThreads;
     constexpr int kRun = SegRun<DT, K, STABLE>::kRun;
-    auto kern = &k_segmented<DT, K, STABLE, VM>;
+    auto kern = &k_segmented<DT, K, STABLE, VM, NET>;
     if (int rc = set_dynamic_lds(reinterpret_cast<const void*>(kern), Tr::kLds)) return rc;
     int grid = a.grid;
     if (grid <= 0) {
@@ -447,7 +450,7 @@ int launch_seg_kernel(const SegArgs& a, const SegWs& w, uint32_t uni_len) {
         npass = any_tiled ? seg_passes((uint32_t)((len + kRun - 1) / kRun)) : 0;
     }
     if (any_tiled) {
-        auto skern = &k_seg_tile_sort<DT, K, STABLE, VM>;
+        auto skern = &k_seg_tile_sort<DT, K, STABLE, VM, NET>;
         constexpr int kSortThreads = SegRun<DT, K, STABLE>::Tr::kThreads;
         int sgrid = 0;
         static int cached_s = 0;
@@ -467,7 +470,7 @@ int launch_seg_kernel(const SegArgs& a, const SegWs& w, uint32_t uni_len) {
         LaunchTimer timer("segmented", a.n_total, a.stream);
         hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlockThreads), Tr::kLds, a.stream, a.kin,
                            a.vin, a.kout, a.vout, w.wk, w.wv, a.offsets, a.num_segments, uni_len,
-                           w.st, w.lists);
+                           w.st, w.lists, a.set_mask);
     }
     if (int rc = (int)hipGetLastError()) return rc;
     // merge passes of the tiled segments (none of them when the list is empty)
@@ -499,14 +502,20 @@ int launch_seg_kernel(const SegArgs& a, const SegWs& w, uint32_t uni_len) {
     return 0;
 }
 
+template <int DT, int K, int NET>
+int dispatch_seg_net(const SegArgs& a, const SegWs& w, uint32_t uni_len) {
+    if (a.vmode == kVals) return launch_seg_kernel<DT, K, true, kVals, NET>(a, w, uni_len);
+    if (a.vmode == kArg) return launch_seg_kernel<DT, K, true, kArg, NET>(a, w, uni_len);
+    if constexpr (DT == kF32)
+        return launch_seg_kernel<DT, K, true, kNoVals, NET>(a, w, uni_len);
+    else
+        return launch_seg_kernel<DT, K, false, kNoVals, NET>(a, w, uni_len);
+}
+
 template <int DT, int K>
 int dispatch_seg(const SegArgs& a, const SegWs& w, uint32_t uni_len) {
-    if (a.vmode == kVals) return launch_seg_kernel<DT, K, true, kVals>(a, w, uni_len);
-    if (a.vmode == kArg) return launch_seg_kernel<DT, K, true, kArg>(a, w, uni_len);
-    if constexpr (DT == kF32)
-        return launch_seg_kernel<DT, K, true, kNoVals>(a, w, uni_len);
-    else
-        return launch_seg_kernel<DT, K, false, kNoVals>(a, w, uni_len);
+    return a.net == kNetSplit ? dispatch_seg_net<DT, K, kNetSplit>(a, w, uni_len)
+                              : dispatch_seg_net<DT, K, kNetPlain>(a, w, uni_len);
 }
 
 }  // namespace

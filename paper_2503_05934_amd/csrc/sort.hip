@@ -11,7 +11,7 @@
 namespace msn {
 
 // ----------------------------------------------------------- first sweep ---
-template <int DT, int K, bool STABLE, int VM, int SHAPE, bool NETS>
+template <int DT, int K, bool STABLE, int VM, int SHAPE, int NETS>
 __global__ __launch_bounds__((TileTraits<DT, K, STABLE, SHAPE>::kThreads),
                              (TileTraits<DT, K, STABLE, SHAPE>::kWavesPerSimd)) void k_block_sort(
     const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, int64_t n,
@@ -25,7 +25,7 @@ __global__ __launch_bounds__((TileTraits<DT, K, STABLE, SHAPE>::kThreads),
     const int64_t base = (int64_t)blockIdx.x * kTile;
     const int nv = (int)((n - base) < kTile ? (n - base) : kTile);
     // network tiles take the wide LDS levels and packed composites
-    block_sort_tile<DT, K, STABLE, VM, SHAPE, NETS, NETS, NETS>(kin + base,
+    block_sort_tile<DT, K, STABLE, VM, SHAPE, NETS != kNetNone, NETS != kNetNone, NETS>(kin + base,
                                              VM == kVals ? vin + base : nullptr,
                                              kout + base, VM != kNoVals ? vout + base : nullptr,
                                              nv, (uint32_t)base, smem,
@@ -302,7 +302,7 @@ int ensure_lds(Kern kern, size_t bytes) {
     return set_dynamic_lds(reinterpret_cast<const void*>(kern), bytes);
 }
 
-template <int DT, int K, bool STABLE, int VM, int SHAPE, bool NETS>
+template <int DT, int K, bool STABLE, int VM, int SHAPE, int NETS>
 int launch_block_sort(const SortArgs& a, uint32_t* kdst, uint32_t* vdst,
                       const Samples& sm, int* sorted_flag) {
     using Tr = TileTraits<DT, K, STABLE, SHAPE>;
@@ -324,7 +324,7 @@ inline int block_shape(const SortArgs& a) {
     return ratio >= 4 ? 2 : ratio == 2 ? 1 : 0;
 }
 
-template <int DT, int K, bool NETS>
+template <int DT, int K, int NETS>
 int dispatch_block_sort(const SortArgs& a, uint32_t* kdst, uint32_t* vdst,
                         const Samples& sm, int* fl) {
     if (a.vmode == kVals)
@@ -484,9 +484,15 @@ int run_sort(const SortArgs& a) {
                                (a.vmode != kVals || aligned(a.vin))));
 
     int cur = passes & 1;
-    int rc = !a.nets         ? dispatch_block_sort<DT, 8, false>(a, kb[cur], vb[cur], sm, sorted_flag)
-             : a.leaf_k == 8 ? dispatch_block_sort<DT, 8, true>(a, kb[cur], vb[cur], sm, sorted_flag)
-                             : dispatch_block_sort<DT, 4, true>(a, kb[cur], vb[cur], sm, sorted_flag);
+    int rc = 0;
+    if (a.nets == kNetNone)
+        rc = dispatch_block_sort<DT, 8, kNetNone>(a, kb[cur], vb[cur], sm, sorted_flag);
+    else if (a.nets == kNetSplit)
+        rc = a.leaf_k == 8 ? dispatch_block_sort<DT, 8, kNetSplit>(a, kb[cur], vb[cur], sm, sorted_flag)
+                           : dispatch_block_sort<DT, 4, kNetSplit>(a, kb[cur], vb[cur], sm, sorted_flag);
+    else
+        rc = a.leaf_k == 8 ? dispatch_block_sort<DT, 8, kNetPlain>(a, kb[cur], vb[cur], sm, sorted_flag)
+                           : dispatch_block_sort<DT, 4, kNetPlain>(a, kb[cur], vb[cur], sm, sorted_flag);
     if (rc) return rc;
     if (passes > 0) {
         const int64_t runs = (a.n + tile - 1) / tile;

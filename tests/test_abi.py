@@ -53,7 +53,8 @@ def keys(lib, kin=FAKE, kout=FAKE2, n=100, dtype=0, leaf=0, tuning=None, ws=FAKE
 
 def test_sort_keys_argument_errors(lib):
     assert keys(lib, dtype=7) == -3
-    assert keys(lib, leaf=9) == -4
+    assert keys(lib, leaf=12) == -4
+    assert keys(lib, leaf=-1) == -4
     assert keys(lib, n=-1) == -2
     assert keys(lib, n=1 << 31) == -2
     assert keys(lib, kin=None) == -1
@@ -94,7 +95,8 @@ def test_segmented_argument_errors(lib):
     assert call(flags=1) == -1                            # argsort needs vals_out
     assert call(vout=ctypes.c_void_p(7 << 20)) == -4      # vals_out without vals_in or argsort
     assert call(dtype=5) == -3
-    assert call(leaf=3) == -4
+    assert call(leaf=12) == -4
+    assert call(leaf=2) == -6                             # no network: flat sorts only
     assert call(wsb=0) == -5
     from paper_2503_05934_amd import _lib
     for bad in (dict(seg_lane_max=9), dict(seg_wave_max=10000), dict(seg_block_max=9000),
@@ -140,6 +142,16 @@ def test_values_may_not_overlap_the_other_array(lib):
     # keys_in overlapping vals_out
     assert g(FAKE, None, FAKE2, FAKE, ctypes.c_void_p(7 << 20), 10, 100, 1, 0, 1, None,
              ws, 1 << 30, None) == -2
+    # offsets (11 words) ending just before the key output, which is longer: no overlap,
+    # so validation passes and the call goes on to launch (rc 100 without a GPU)
+    if not _gpu_present():
+        assert g(FAKE, None, FAKE2, None, ctypes.c_void_p((3 << 20) - 44), 10, 100, 1, 0, 0,
+                 None, ws, 1 << 30, None) > 0
+
+
+def _gpu_present():
+    import torch
+    return torch.cuda.is_available()
 
 
 def test_workspace_query_names_agree(lib):
@@ -167,3 +179,14 @@ def test_segmented_accepts_debug_check_flag(lib):
     assert f(FAKE, None, FAKE2, ctypes.c_void_p(7 << 20), FAKE, 10, 100, 1, 0, 3, None, None, 0,
              None) == -5
     assert f(FAKE, None, FAKE2, None, FAKE, 10, 100, 1, 0, 2 | 4, None, None, 0, None) == -4
+
+
+def test_every_leaf_set_passes_validation(lib):
+    # each Table 3 code is accepted: with a zero-length array the call returns
+    # before anything could be launched
+    for code in range(12):
+        assert lib.msn_sort_keys(None, None, 0, 0, code, None, None, 0, None) == 0, code
+        assert lib.msn_sort_pairs(None, None, None, None, 0, 0, code, None, None, 0, None) == 0
+        assert lib.msn_quick_sort_keys(None, None, 0, 0, code, None, None, 0, None) == 0
+    for code in (12, 13, 100):
+        assert lib.msn_sort_keys(None, None, 0, 0, code, None, None, 0, None) == -4
