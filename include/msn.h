@@ -33,6 +33,10 @@
  *    corresponding input pointer; any other overlap is an error.
  *  - Sizes: n and every segment hold at most 2^31 - 1 elements.
  *  - Pointers must be 4-byte aligned; 16-byte alignment enables wider loads.
+ *  - Calls may come from several host threads and for several devices (the
+ *    device of `stream`, or the current one): the library's host-side caches
+ *    (kernel attributes, resident grid sizes, scratch addresses) are kept per
+ *    device and guarded by locks.
  *
  * Return codes: 0 = success; < 0 = argument error found on the host before
  * anything is enqueued (see MSN_ERR_*); > 0 = the hipError_t of a failed
@@ -297,6 +301,19 @@ int msn_segmented_status_offset(int64_t n_total, int64_t num_segments, int pairs
  */
 int msn_sort_backward(const float* grad_out, const int32_t* perm, float* grad_in,
                       int64_t rows, int64_t cols, void* stream);
+
+/*
+ * Merge-path split (diagnostics): out[i] = how many elements of a are among
+ * the first diags[i] outputs of the stable merge of the sorted arrays a (la
+ * keys) and b (lb keys), a first on equal keys -- the co-rank search (Green,
+ * McColl, Bader 2012) by which the merge passes split their outputs, run on
+ * the device.  A diagonal outside [0, la + lb] gives -1.  Device arrays;
+ * out must not overlap a, b or diags (unless out == diags).
+ * Paper: Algorithm 1's Merge.
+ */
+int msn_merge_path_split(const void* a, int64_t la, const void* b, int64_t lb,
+                         const int32_t* diags, int32_t* out, int64_t count, int dtype,
+                         void* stream);
 
 /*
  * Copies n 32-bit words, dst[i] = src[i] (diagnostics): the library's own

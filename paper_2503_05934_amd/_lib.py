@@ -110,6 +110,8 @@ def lib():
     L.msn_segmented_sort_workspace_bytes.restype = I
     L.msn_segmented_sort.argtypes = [P, P, P, P, P, I64, I64, I, I, U, P, P, ctypes.c_size_t, P]
     L.msn_segmented_sort.restype = I
+    L.msn_merge_path_split.argtypes = [P, I64, P, I64, P, P, I64, I, P]
+    L.msn_merge_path_split.restype = I
     L.msn_copy_words.argtypes = [P, P, I64, P]
     L.msn_copy_words.restype = I
     L.msn_sort_backward.argtypes = [P, P, P, I64, I64, P]

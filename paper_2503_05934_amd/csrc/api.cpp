@@ -6,6 +6,8 @@
 
 #include <initializer_list>
 #include <map>
+#include <tuple>
+#include <utility>
 #include <mutex>
 #include <string>
 #include <unordered_map>
@@ -16,15 +18,39 @@
 namespace msn {
 
 int set_dynamic_lds(const void* kernel, size_t bytes) {
+    int dev = 0;
+    if (int rc = (int)hipGetDevice(&dev)) return rc;
     static std::mutex mu;
-    static std::unordered_map<const void*, size_t> done;
+    static std::map<std::pair<const void*, int>, size_t> done;  // (kernel, device)
     std::lock_guard<std::mutex> lock(mu);
-    auto it = done.find(kernel);
+    auto it = done.find({kernel, dev});
     if (it != done.end() && it->second >= bytes) return 0;
     const int rc =
         (int)hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    if (rc == 0) done[kernel] = bytes;
+    if (rc == 0) done[{kernel, dev}] = bytes;
     return rc;
+}
+
+int resident_grid(const void* kernel, int threads, size_t lds, int* out) {
+    int dev = 0;
+    if (int rc = (int)hipGetDevice(&dev)) return rc;
+    using Key = std::tuple<const void*, int, int, size_t>;  // kernel, device, threads, LDS
+    static std::mutex mu;
+    static std::map<Key, int> cache;
+    std::lock_guard<std::mutex> lock(mu);
+    const Key key{kernel, dev, threads, lds};
+    auto it = cache.find(key);
+    if (it == cache.end()) {
+        int cus = 0, per_cu = 0;
+        if (int rc = (int)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev))
+            return rc;
+        if (int rc = (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads,
+                                                                       lds))
+            return rc;
+        it = cache.emplace(key, cus * (per_cu > 0 ? per_cu : 1)).first;
+    }
+    *out = it->second;
+    return 0;
 }
 
 namespace {
@@ -432,6 +458,23 @@ int msn_segmented_status_offset(int64_t n_total, int64_t num_segments, int pairs
         return MSN_ERR_SIZE;
     *offset = msn::seg_status_offset(n_total, num_segments, pairs != 0);
     return MSN_OK;
+}
+
+int msn_merge_path_split(const void* a, int64_t la, const void* b, int64_t lb,
+                         const int32_t* diags, int32_t* out, int64_t count, int dtype,
+                         void* stream) {
+    if (!valid_dtype(dtype)) return MSN_ERR_DTYPE;
+    if (la < 0 || lb < 0 || la + lb > kMaxN || count < 0 || count > kMaxN) return MSN_ERR_SIZE;
+    if (count == 0) return MSN_OK;
+    if ((la > 0 && !a) || (lb > 0 && !b) || !diags || !out) return MSN_ERR_NULL;
+    if (misaligned(a) || misaligned(b) || misaligned(diags) || misaligned(out))
+        return MSN_ERR_UNSUPPORTED;
+    if (ranges_overlap(out, count, a, la) || ranges_overlap(out, count, b, lb) ||
+        ranges_overlap(out, count, diags, count) && out != diags)
+        return MSN_ERR_SIZE;
+    return msn::launch_merge_path_split(static_cast<const uint32_t*>(a), la,
+                                        static_cast<const uint32_t*>(b), lb, diags, out, count,
+                                        dtype, static_cast<hipStream_t>(stream));
 }
 
 int msn_copy_words(const void* src, void* dst, int64_t n, void* stream) {

@@ -117,8 +117,13 @@ size_t seg_ws_bytes(int64_t n_total, int64_t num_segments, bool vals);
 size_t seg_status_offset(int64_t n_total, int64_t num_segments, bool vals);
 
 // Raises a kernel's dynamic-LDS limit to `bytes` (needed beyond 64 KiB); done
-// once per kernel and process.  Returns a hipError_t value.
+// once per kernel and device (thread-safe).  Returns a hipError_t value.
 int set_dynamic_lds(const void* kernel, size_t bytes);
+// Workgroups of `threads` threads with `lds` bytes of dynamic LDS that fill
+// every compute unit of the current device with `kernel` (its occupancy
+// times the compute units); cached per kernel, device and shape
+// (thread-safe).  Returns a hipError_t value.
+int resident_grid(const void* kernel, int threads, size_t lds, int* out);
 
 // Brackets one kernel launch with hipEvents when timing is enabled
 // (msn_timing_enable); a no-op otherwise.
@@ -146,6 +151,9 @@ constexpr size_t kNoAllocScratchBytes = sort_ws_bytes(kNoAllocMaxKeys, false);
 // device; *bytes receives its size.  Returns a hipError_t value.
 int noalloc_scratch(hipStream_t stream, void** ptr, size_t* bytes);
 int launch_segmented(const SegArgs& a);
+int launch_merge_path_split(const uint32_t* a, int64_t la, const uint32_t* b, int64_t lb,
+                            const int32_t* diags, int32_t* out, int64_t count, int dtype,
+                            hipStream_t stream);
 
 struct QuickArgs {
     const uint32_t* kin;

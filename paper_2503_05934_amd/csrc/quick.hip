@@ -429,15 +429,7 @@ const QRoundKinds& q_kinds() {
 
 template <typename Kern>
 int q_grid(Kern kern, size_t lds, int* out) {
-    int dev = 0, cus = 0, per_cu = 0;
-    if (int rc = (int)hipGetDevice(&dev)) return rc;
-    if (int rc = (int)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev))
-        return rc;
-    if (int rc = (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void*>(kern), kBlockThreads, lds))
-        return rc;
-    *out = cus * std::max(per_cu, 1);
-    return 0;
+    return resident_grid(reinterpret_cast<const void*>(kern), kBlockThreads, lds, out);
 }
 
 template <int DT, int K, int NETS>

@@ -398,25 +398,49 @@ __global__ __launch_bounds__(kBlockThreads, DT == kF32 ? 1 : 6) void k_seg_tile_
     }
 }
 
+// ------------------------------------------------- merge-path diagnostic ---
+// out[i] = number of elements of A among the first diags[i] outputs of the
+// stable merge of A and B (A first on equal keys), by the co-rank search the
+// merge passes use.  One thread per diagonal.
+template <int DT>
+__global__ __launch_bounds__(256) void k_merge_path_split(const uint32_t* __restrict__ a, int la,
+                                                          const uint32_t* __restrict__ b, int lb,
+                                                          const int32_t* __restrict__ diags,
+                                                          int32_t* __restrict__ out, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const int d = diags[i];
+    out[i] = (d < 0 || d > la + lb) ? -1 : corank_global<DT>(a, la, b, lb, d);
+}
+
+int launch_merge_path_split(const uint32_t* a, int64_t la, const uint32_t* b, int64_t lb,
+                            const int32_t* diags, int32_t* out, int64_t count, int dtype,
+                            hipStream_t stream) {
+    if (count == 0) return 0;
+    const unsigned grid = (unsigned)((count + 255) / 256);
+    switch (dtype) {
+        case kU32:
+            hipLaunchKernelGGL(k_merge_path_split<kU32>, dim3(grid), dim3(256), 0, stream, a,
+                               (int)la, b, (int)lb, diags, out, (int)count);
+            break;
+        case kI32:
+            hipLaunchKernelGGL(k_merge_path_split<kI32>, dim3(grid), dim3(256), 0, stream, a,
+                               (int)la, b, (int)lb, diags, out, (int)count);
+            break;
+        default:
+            hipLaunchKernelGGL(k_merge_path_split<kF32>, dim3(grid), dim3(256), 0, stream, a,
+                               (int)la, b, (int)lb, diags, out, (int)count);
+            break;
+    }
+    return (int)hipGetLastError();
+}
+
 // ------------------------------------------------------------------ host ---
 namespace {
 
-// Workgroups that fill every compute unit with kernel `kern` (cached per
-// kernel: one device per process).
 template <typename Kern>
-int fill_grid(Kern kern, int threads, size_t lds, int* cache, int* out) {
-    if (*cache == 0) {
-        int dev = 0, cus = 0, per_cu = 0;
-        if (int rc = (int)hipGetDevice(&dev)) return rc;
-        if (int rc = (int)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev))
-            return rc;
-        if (int rc = (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &per_cu, reinterpret_cast<const void*>(kern), threads, lds))
-            return rc;
-        *cache = cus * (per_cu > 0 ? per_cu : 1);
-    }
-    *out = *cache;
-    return 0;
+int fill_grid(Kern kern, int threads, size_t lds, int* out) {
+    return resident_grid(reinterpret_cast<const void*>(kern), threads, lds, out);
 }
 
 struct SegWs {
@@ -438,8 +462,7 @@ int launch_seg_kernel(const SegArgs& a, const SegWs& w, uint32_t uni_len) {
     if (int rc = set_dynamic_lds(reinterpret_cast<const void*>(kern), Tr::kLds)) return rc;
     int grid = a.grid;
     if (grid <= 0) {
-        static int cached = 0;
-        if (int rc = fill_grid(kern, kBlockThreads, Tr::kLds, &cached, &grid)) return rc;
+        if (int rc = fill_grid(kern, kBlockThreads, Tr::kLds, &grid)) return rc;
     }
     // equal-length segments: the host knows their class and pass count
     bool any_tiled = true;
@@ -453,8 +476,7 @@ int launch_seg_kernel(const SegArgs& a, const SegWs& w, uint32_t uni_len) {
         auto skern = &k_seg_tile_sort<DT, K, STABLE, VM, NET>;
         constexpr int kSortThreads = SegRun<DT, K, STABLE>::Tr::kThreads;
         int sgrid = 0;
-        static int cached_s = 0;
-        if (int rc = fill_grid(skern, kSortThreads, 0, &cached_s, &sgrid)) return rc;
+        if (int rc = fill_grid(skern, kSortThreads, 0, &sgrid)) return rc;
         // a workgroup per possible run (capped at 256 resident rounds): a
         // persistent loop over the list put each run's setup behind the
         // previous run (2.72 against 2.44 ms on the 100,000-array batch);
@@ -478,10 +500,7 @@ int launch_seg_kernel(const SegArgs& a, const SegWs& w, uint32_t uni_len) {
     const size_t mlds = (size_t)seg_merge_words(kTile) * 4 * (kVals ? 2 : 1);
     if (int rc = set_dynamic_lds(reinterpret_cast<const void*>(mkern), mlds)) return rc;
     int mgrid = 0;
-    {
-        static int cached = 0;
-        if (int rc = fill_grid(mkern, kBlockThreads, mlds, &cached, &mgrid)) return rc;
-    }
+    if (int rc = fill_grid(mkern, kBlockThreads, mlds, &mgrid)) return rc;
     const unsigned pgrid = (unsigned)((w.max_tiles + 255) / 256);
     for (int p = 0; p < npass; ++p) {
         {

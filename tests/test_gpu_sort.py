@@ -428,3 +428,52 @@ def test_packed_composite_edges(orc):
         ko, po = msn.sort_pairs(gpu(kk))
         _, rp = orc.sort(kk, dtype=dtype, stable=True, want_perm=True)
         assert np.array_equal(host(po).view(np.uint32), rp), dtype
+
+
+def _cpu_corank(a, b, d):
+    """Elements of a among the first d outputs of the stable merge of a and b
+    (a first on equal keys): the merge itself, step by step."""
+    i = j = 0
+    for _ in range(d):
+        if j >= len(b) or (i < len(a) and not b[j] < a[i]):
+            i += 1
+        else:
+            j += 1
+    return i
+
+
+@pytest.mark.parametrize("dtype", ["u32", "i32", "f32"])
+def test_merge_path_split_matches_cpu(dtype):
+    from paper_2503_05934_amd import _lib
+
+    rng = np.random.default_rng(5)
+    cases = [(0, 0), (0, 5), (5, 0), (1, 1), (7, 300), (300, 7), (257, 256), (1000, 1000)]
+    for la, lb in cases:
+        for hi in (3, 1000, 2**31):  # heavy ties, some ties, distinct
+            a = np.sort(make_keys(la, dtype, seed=la * 7 + lb)[:la] if dtype == "f32"
+                        else rng.integers(0, min(hi, 2**31), la).astype(NPT[dtype]))
+            b = np.sort(make_keys(lb, dtype, seed=lb * 11 + la)[:lb] if dtype == "f32"
+                        else rng.integers(0, min(hi, 2**31), lb).astype(NPT[dtype]))
+            if dtype == "f32":  # order by the float rule: NaNs last, -0 == +0
+                a = np.sort(a)
+                b = np.sort(b)
+            diags = np.arange(-1, la + lb + 2, dtype=np.int32)
+            out = torch.empty(len(diags), dtype=torch.int32, device="cuda:0")
+            ag, bg, dg = gpu(a), gpu(b), gpu(diags)
+            L = _lib.lib()
+            rc = L.msn_merge_path_split(_lib.ptr(ag) if la else None, la,
+                                        _lib.ptr(bg) if lb else None, lb, _lib.ptr(dg),
+                                        _lib.ptr(out), len(diags), {"u32": 0, "i32": 1, "f32": 2}[dtype],
+                                        _lib.stream_handle(out.device))
+            assert rc == 0
+            got = host(out)
+            # the float order: -0 == +0, every NaN above +inf and all NaNs equal
+            ka = [(1, 0.0) if np.isnan(v) else (0, v) for v in a.tolist()]
+            kb = [(1, 0.0) if np.isnan(v) else (0, v) for v in b.tolist()]
+            want = [-1] + [_cpu_corank(ka, kb, d) for d in range(la + lb + 1)] + [-1]
+            assert got.tolist() == want, (dtype, la, lb, hi)
+            if dtype == "f32":
+                break
+
+
+NPT = {"u32": np.uint32, "i32": np.int32}
