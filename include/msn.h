@@ -140,7 +140,7 @@ extern "C" {
  *   quick_rounds    partition rounds of msn_quick_sort_keys, 1..96; a
  *                   subarray still longer than one block-sort tile in the
  *                   last round is merge-sorted by one workgroup (default
- *                   2 ceil(log2(n / tile)) + 16, capped at 96).
+ *                   2 ceil(log2(n / tile)) + 8, capped at 96).
  */
 typedef struct {
     int32_t merge_tile;

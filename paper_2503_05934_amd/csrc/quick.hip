@@ -510,7 +510,7 @@ int quick_rounds(int64_t n, int64_t leaf_max) {
     if (n <= leaf_max) return 1;
     int lg = 0;
     while ((leaf_max << lg) < n) ++lg;
-    return std::min(2 * lg + 16, kQuickMaxRounds);
+    return std::min(2 * lg + 8, kQuickMaxRounds);
 }
 
 size_t quick_ws_bytes(int64_t n) { return align_up((size_t)n * 4, 256) + 6 * q_list_bytes(n); }
