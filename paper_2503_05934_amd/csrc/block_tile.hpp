@@ -12,15 +12,20 @@
 namespace msn {
 
 // Tile shapes of the block sort (SHAPE): 0 = 512 threads x 2K keys per lane
-// (the default, and the only one for stable sorts); 1 = 1024 threads x 2K;
-// 2 = 1024 threads x 4K (32768-key runs for the 6-to-8 set, 137 KiB of LDS).
-// Shapes 1 and 2 serve the first sweep of flat integer keys-only sorts.
+// (the default); 1 = 1024 threads x 2K; 2 = 1024 threads x 4K (32768-key
+// runs for the 6-to-8 set, 137 KiB of LDS); 3 = 1024 threads x K (the tile
+// of shape 0 spread over twice the threads: one leaf group per lane, half
+// the registers, twice the wavefronts per SIMD).  Shapes 1 and 2 serve the
+// first sweep of flat integer keys-only sorts, shape 3 the stable sort of
+// equal rows of at most one tile.
 template <int DT, int K, bool STABLE, int SHAPE = 0>
 struct TileTraits {
     using T = std::conditional_t<STABLE, uint64_t, uint32_t>;
-    static_assert(SHAPE == 0 || !STABLE, "large tiles hold 32-bit keys only");
+    static_assert(SHAPE == 0 || SHAPE == 3 || !STABLE, "large tiles hold 32-bit keys only");
     static constexpr int kThreads = SHAPE == 0 ? kBlockThreads : 2 * kBlockThreads;
-    static constexpr int kKPL = SHAPE == 2 ? 2 * keys_per_lane<K>() : keys_per_lane<K>();
+    static constexpr int kKPL = SHAPE == 2   ? 2 * keys_per_lane<K>()
+                                : SHAPE == 3 ? K
+                                             : keys_per_lane<K>();
     static constexpr int kTile = kKPL * kThreads;
     // keys-only tiles of 16 keys per lane can merge in LDS at 32 outputs per
     // thread (block_sort_regs2); LDS is sized for either layout

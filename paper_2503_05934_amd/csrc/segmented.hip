@@ -274,6 +274,30 @@ __global__ __launch_bounds__(kBlockThreads, STABLE ? 4 : 6) void k_segmented(
     }
 }
 
+// --------------------------------------------------- equal stable rows ---
+// Equal rows of at most one tile sorted stably (float keys, pairs,
+// argsorts; the differentiable row sort): one 1024-thread workgroup per row
+// with one leaf group of K keys per lane (tile shape 3), rows taken in turn.
+// Against the persistent kernel's 512 threads x 2K keys this halves the
+// registers a lane holds and doubles the wavefronts per SIMD, which keeps the
+// VALU busier through the 64-bit composite exchanges.
+template <int DT, int K, int VM, int NET>
+__global__ __launch_bounds__((TileTraits<DT, K, true, 3>::kThreads),
+                             (TileTraits<DT, K, true, 3>::kWavesPerSimd))
+void k_seg_rows(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
+                int64_t rows, uint32_t len, const SegState* st) {
+    using Tr = TileTraits<DT, K, true, 3>;
+    __shared__ __align__(16) unsigned char smem[Tr::kLdsBytes];
+    if (st->status) return;
+    for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
+        const int64_t off = r * (int64_t)len;
+        block_sort_tile<DT, K, true, VM, 3, false, false, NET>(
+            kin + off, VM == kVals ? vin + off : nullptr, kout + off,
+            VM != kNoVals ? vout + off : nullptr, (int)len, 0u, smem);
+        __syncthreads();  // the next row reuses the LDS
+    }
+}
+
 // ---------------------------------------------- sorts, tiled path ---
 // The runs of the tiled segments, workgroups taking list entries in turn
 // (the entry of a run's first list tile sorts the run; the others pass):
@@ -471,6 +495,24 @@ int launch_seg_kernel(const SegArgs& a, const SegWs& w, uint32_t uni_len) {
         const int64_t len = uni_len;
         any_tiled = len > a.block_max && len <= (int64_t)kSegTiledMax * kTile;
         npass = any_tiled ? seg_passes((uint32_t)((len + kRun - 1) / kRun)) : 0;
+    }
+    // equal stable rows of one workgroup-sized tile: the row kernel
+    if constexpr (STABLE) {
+        constexpr int kRowTile = TileTraits<DT, K, true, 3>::kTile;
+        if (!a.offsets && uni_len > (uint32_t)a.wave_max && uni_len <= (uint32_t)a.block_max &&
+            uni_len <= (uint32_t)kRowTile) {
+            auto rkern = &k_seg_rows<DT, K, VM, NET>;
+            int rgrid = 0;
+            if (int rc = fill_grid(rkern, TileTraits<DT, K, true, 3>::kThreads, 0, &rgrid))
+                return rc;
+            {
+                LaunchTimer timer("seg_rows", a.n_total, a.stream);
+                hipLaunchKernelGGL(rkern, dim3(rgrid), dim3(TileTraits<DT, K, true, 3>::kThreads),
+                                   0, a.stream, a.kin, a.vin, a.kout, a.vout, a.num_segments,
+                                   uni_len, w.st);
+            }
+            return (int)hipGetLastError();
+        }
     }
     if (any_tiled) {
         auto skern = &k_seg_tile_sort<DT, K, STABLE, VM, NET>;
