@@ -7,13 +7,15 @@
 // lists of subarrays ("items") of the whole array, one launch each, and
 // builds the lists of round r + 1:
 //   partition launch:
-//     partition item (longer than one block-sort tile): cut into super-tiles
-//       of kQSuper keys, one workgroup each.  A super-tile counts its keys
-//       below and above the item's pivot, claims room for them with one
-//       64-bit atomic on the item (smaller keys fill the subarray from its
-//       left end, larger keys from its right end), then reads its keys
-//       again chunk by chunk, compacts them in LDS and writes them to the
-//       other buffer.  The super-tile that finishes the item last appends the
+//     partition item (longer than one block-sort tile): cut into claim
+//       tiles, one workgroup each: 8192-key chunks in sorts of at most
+//       kQOnePassMax keys, 65,536-key super-tiles in larger ones.  A tile
+//       counts its keys below and above the item's pivot, claims room for
+//       them with one 64-bit atomic on the item (smaller keys fill the
+//       subarray from its left end, larger keys from its right end),
+//       compacts them in LDS and writes them to the other buffer; a
+//       super-tile counts all its chunks first and reads them again to
+//       scatter them.  The tile that finishes the item last appends the
 //       item's children: the smaller side, the larger side, and the keys
 //       equal to the pivot, which are already in their final place (a
 //       three-way split; the paper splits in two, which for equal keys only
@@ -29,9 +31,9 @@
 //       merge-sorts it through global memory.
 // Partitions alternate between the workspace and the output array, both at
 // the item's own positions, so finished subarrays are never moved again.
-// Claims are per super-tile rather than per workgroup-sized tile: atomics on
-// one item's counters queue behind each other, and a round of a 2^28-key
-// array would otherwise make 65,536 of them on one address.  No launch reads
+// Large sorts claim per super-tile rather than per chunk: the claims queue
+// behind each other, and the first round of a 2^28-key array would otherwise
+// make 65,536 of them on one address.  No launch reads
 // anything on the host.  Integer keys only: the partition is not stable, and
 // float keys that compare equal (-0 and +0, NaNs) must keep their input
 // order.
@@ -67,16 +69,28 @@ static_assert(sizeof(QList) == 256, "list header");
 constexpr int kQKeysPerThread = 16;
 constexpr int kQChunk = kQKeysPerThread * kBlockThreads;  // 8192 keys per pass step
 constexpr int kQChunks = 8;
-constexpr int kQSuper = kQChunk * kQChunks;  // keys per claim: 65,536
+constexpr int kQSuper = kQChunk * kQChunks;  // keys per claim of a large sort: 65,536
+// Sorts of at most this many keys claim room per 8192-key chunk and read
+// their keys once; larger ones per super-tile, counting and scattering in
+// two reads.  Claims are device-scope atomics that queue behind each other:
+// a round of a 2^28-key sort in chunks makes 65,536 of them (claims and
+// completions), about 3 ms, against about 0.6 ms of traffic.
+constexpr int64_t kQOnePassMax = 1ll << 23;
 
 __device__ __forceinline__ QItem* q_items(QList* l) { return reinterpret_cast<QItem*>(l + 1); }
 
-__device__ __forceinline__ uint32_t q_tiles(uint32_t len) { return (len + kQSuper - 1) / kQSuper; }
+// Work units of an item: claim tiles of claim_keys keys for partitions,
+// super-tiles for fills.
+__device__ __forceinline__ uint32_t q_tiles(uint32_t kind, uint32_t len, uint32_t claim_keys) {
+    const uint32_t t = kind == kQPart ? claim_keys : (uint32_t)kQSuper;
+    return (len + t - 1) / t;
+}
 
 // Appends an item (one thread).
 __device__ __forceinline__ void q_append(QList* l, uint32_t cap, uint32_t start, uint32_t len,
-                                         uint32_t kind, uint32_t pivot) {
-    const unsigned long long tiles = (kind == kQPart || kind == kQFill) ? q_tiles(len) : 1u;
+                                         uint32_t kind, uint32_t pivot, uint32_t claim_keys) {
+    const unsigned long long tiles =
+        (kind == kQPart || kind == kQFill) ? q_tiles(kind, len, claim_keys) : 1u;
     const unsigned long long old = atomicAdd(&l->packed, (1ull << 32) | tiles);
     const uint32_t idx = (uint32_t)(old >> 32);
     if (idx >= cap) {  // cannot happen: a list holds three children per partition
@@ -191,14 +205,15 @@ struct QPartRound {
     uint32_t cap;         // items per list
     uint32_t leaf_max;    // longest leaf item
     int final_next;       // the next round is the last: long children become big items
+    uint32_t claim_keys;  // keys per claim tile: kQChunk or kQSuper
 };
 
 // Appends one side of a finished partition to the list its length calls for.
 __device__ __forceinline__ void q_child(const QPartRound& r, uint32_t start, uint32_t len) {
     if (len == 0) return;
-    if (len <= r.leaf_max) q_append(r.lout_l, r.cap, start, len, kQLeaf, 0u);
-    else if (r.final_next) q_append(r.lout_l, r.cap, start, len, kQBig, 0u);
-    else q_append(r.lout_p, r.cap, start, len, kQPart, 0u);
+    if (len <= r.leaf_max) q_append(r.lout_l, r.cap, start, len, kQLeaf, 0u, r.claim_keys);
+    else if (r.final_next) q_append(r.lout_l, r.cap, start, len, kQBig, 0u, r.claim_keys);
+    else q_append(r.lout_p, r.cap, start, len, kQPart, 0u, r.claim_keys);
 }
 
 // One super-tile of partition item `it` (index sub of its super-tiles).
@@ -213,83 +228,125 @@ __device__ void q_partition(const QPartRound& r, QItem* itp, const QItem& it, ui
     const uint32_t kc = ord_key<DT>(src[it.len - 1]);
     const uint32_t p = max(min(ka, kb), min(max(ka, kb), kc));
 
-    const int s0 = (int)(sub * kQSuper);
-    const int ns = min(kQSuper, (int)it.len - s0);
+    const int ck = (int)r.claim_keys;
+    const int s0 = (int)sub * ck;
+    const int ns = min(ck, (int)it.len - s0);
     const int first = tid * kQKeysPerThread;
     uint32_t* sw = smem + kQChunk;
     __shared__ unsigned long long s_base;
 
-    // pass 1: count
-    uint32_t cl = 0, cg = 0;
-    for (int c0 = 0; c0 < ns; c0 += kQChunk) {
+    if (ck == kQChunk) {
+        // one chunk per claim: read once, count, claim, compact, write
         uint32_t x[kQKeysPerThread];
-        const int nv = min(kQChunk, ns - c0);
-        q_load(src + s0 + c0, first, nv, x);
-#pragma unroll
-        for (int j = 0; j < kQKeysPerThread; ++j) {
-            const bool live = first + j < nv;
-            const uint32_t o = ord_key<DT>(x[j]);
-            cl += (live && o < p) ? 1u : 0u;
-            cg += (live && o > p) ? 1u : 0u;
-        }
-    }
-    q_sum2(cl, cg, sw);
-    if (tid == 0)
-        s_base = atomicAdd(&itp->claimed, (unsigned long long)cl | ((unsigned long long)cg << 32));
-    __syncthreads();
-    uint32_t run_l = (uint32_t)s_base;           // smaller keys placed before this chunk
-    uint32_t run_g = (uint32_t)(s_base >> 32);   // larger keys placed after it
-
-    // pass 2: the same keys again (mostly from the caches), compacted and written
-    for (int c0 = 0; c0 < ns; c0 += kQChunk) {
-        uint32_t x[kQKeysPerThread];
-        const int nv = min(kQChunk, ns - c0);
-        q_load(src + s0 + c0, first, nv, x);
+        q_load(src + s0, first, ns, x);
         uint32_t l = 0, g = 0;
 #pragma unroll
         for (int j = 0; j < kQKeysPerThread; ++j) {
-            const bool live = first + j < nv;
+            const bool live = first + j < ns;
             const uint32_t o = ord_key<DT>(x[j]);
             l += (live && o < p) ? 1u : 0u;
             g += (live && o > p) ? 1u : 0u;
         }
-        // chunk counts stay below 2^16: one scan carries both
         uint32_t tot = 0;
         const uint32_t pre = q_scan(l | (g << 16), sw, &tot);
         const uint32_t TL = tot & 0xffffu, TG = tot >> 16;
-        // stage: smaller keys at [0, TL), larger keys at [TL, TL + TG)
+        if (tid == 0)
+            s_base = atomicAdd(&itp->claimed,
+                               (unsigned long long)TL | ((unsigned long long)TG << 32));
         uint32_t pl = pre & 0xffffu, pg = TL + (pre >> 16);
 #pragma unroll
         for (int j = 0; j < kQKeysPerThread; ++j) {
-            const bool live = first + j < nv;
+            const bool live = first + j < ns;
             const uint32_t o = ord_key<DT>(x[j]);
             if (live && o < p) smem[pl++] = x[j];
             if (live && o > p) smem[pg++] = x[j];
         }
         __syncthreads();
-        uint32_t* dl = r.other + it.start + run_l;
-        // dg[TL + j] is larger key j: they end where the previous chunk's began
-        uint32_t* dg = r.other + it.start + it.len - run_g - TG - TL;
+        const uint32_t base_l = (uint32_t)s_base, base_g = (uint32_t)(s_base >> 32);
+        uint32_t* dl = r.other + it.start + base_l;
+        uint32_t* dg = r.other + it.start + it.len - base_g - TG - TL;
         for (uint32_t e = tid; e < TL + TG; e += kBlockThreads) {
             if (e < TL) dl[e] = smem[e];
             else dg[e] = smem[e];
         }
-        run_l += TL;
-        run_g += TG;
         __syncthreads();  // the LDS and the scan words are reused
+    } else {
+        // a super-tile per claim: count, claim, then read again and scatter
+        // pass 1: count
+        uint32_t cl = 0, cg = 0;
+        for (int c0 = 0; c0 < ns; c0 += kQChunk) {
+            uint32_t x[kQKeysPerThread];
+            const int nv = min(kQChunk, ns - c0);
+            q_load(src + s0 + c0, first, nv, x);
+#pragma unroll
+            for (int j = 0; j < kQKeysPerThread; ++j) {
+                const bool live = first + j < nv;
+                const uint32_t o = ord_key<DT>(x[j]);
+                cl += (live && o < p) ? 1u : 0u;
+                cg += (live && o > p) ? 1u : 0u;
+            }
+        }
+        q_sum2(cl, cg, sw);
+        if (tid == 0)
+            s_base = atomicAdd(&itp->claimed,
+                               (unsigned long long)cl | ((unsigned long long)cg << 32));
+        __syncthreads();
+        uint32_t run_l = (uint32_t)s_base;           // smaller keys placed before this chunk
+        uint32_t run_g = (uint32_t)(s_base >> 32);   // larger keys placed after it
+
+        // pass 2: the same keys again (mostly from the caches), compacted and written
+        for (int c0 = 0; c0 < ns; c0 += kQChunk) {
+            uint32_t x[kQKeysPerThread];
+            const int nv = min(kQChunk, ns - c0);
+            q_load(src + s0 + c0, first, nv, x);
+            uint32_t l = 0, g = 0;
+#pragma unroll
+            for (int j = 0; j < kQKeysPerThread; ++j) {
+                const bool live = first + j < nv;
+                const uint32_t o = ord_key<DT>(x[j]);
+                l += (live && o < p) ? 1u : 0u;
+                g += (live && o > p) ? 1u : 0u;
+            }
+            // chunk counts stay below 2^16: one scan carries both
+            uint32_t tot = 0;
+            const uint32_t pre = q_scan(l | (g << 16), sw, &tot);
+            const uint32_t TL = tot & 0xffffu, TG = tot >> 16;
+            // stage: smaller keys at [0, TL), larger keys at [TL, TL + TG)
+            uint32_t pl = pre & 0xffffu, pg = TL + (pre >> 16);
+#pragma unroll
+            for (int j = 0; j < kQKeysPerThread; ++j) {
+                const bool live = first + j < nv;
+                const uint32_t o = ord_key<DT>(x[j]);
+                if (live && o < p) smem[pl++] = x[j];
+                if (live && o > p) smem[pg++] = x[j];
+            }
+            __syncthreads();
+            uint32_t* dl = r.other + it.start + run_l;
+            // dg[TL + j] is larger key j: they end where the previous chunk's began
+            uint32_t* dg = r.other + it.start + it.len - run_g - TG - TL;
+            for (uint32_t e = tid; e < TL + TG; e += kBlockThreads) {
+                if (e < TL) dl[e] = smem[e];
+                else dg[e] = smem[e];
+            }
+            run_l += TL;
+            run_g += TG;
+            __syncthreads();  // the LDS and the scan words are reused
+        }
     }
     if (tid == 0) {
         // No fence: the children are read by later launches only, and a
         // device-scope release here would write back the L2 for every
-        // super-tile.  This super-tile's claim returned before this increment.
-        if (atomicAdd(&itp->done, 1u) + 1u == q_tiles(it.len)) {
-            // every super-tile has claimed its room: the totals are final
+        // claim tile.  This tile's claim returned before this increment.
+        if (atomicAdd(&itp->done, 1u) + 1u == q_tiles(kQPart, it.len, r.claim_keys)) {
+            // every tile has claimed its room: the totals are final
             const unsigned long long c = atomicAdd(&itp->claimed, 0ull);
             const uint32_t nl = (uint32_t)c, ng = (uint32_t)(c >> 32);
             const uint32_t ne = it.len - nl - ng;
             q_child(r, it.start, nl);
             q_child(r, it.start + it.len - ng, ng);
-            if (ne) q_append(r.lout_p, r.cap, it.start + nl, ne, kQFill, unord_key<DT>(p));
+            if (ne)
+                q_append(r.lout_p, r.cap, it.start + nl, ne, kQFill, unord_key<DT>(p),
+                         r.claim_keys);
         }
     }
 }
@@ -385,16 +442,16 @@ __global__ __launch_bounds__(kBlockThreads, 4) void k_qs_leaf(QLeafRound r) {
 // Round 0's lists: the whole array as one item (a partition item, or a leaf
 // or big item when it is short or there is one round); the rest empty.
 __global__ void k_qs_init(QList* p0, QList* p1, QList* p2, QList* l0, QList* l1, QList* l2,
-                          uint32_t n, uint32_t leaf_max, int only_round) {
+                          uint32_t n, uint32_t leaf_max, int only_round, uint32_t claim_keys) {
     if (threadIdx.x != 0) return;
     QList* all[6] = {p0, p1, p2, l0, l1, l2};
     for (QList* l : all) {
         l->packed = 0ull;
         l->status = 0u;
     }
-    if (n <= leaf_max) q_append(l0, 1u, 0u, n, kQLeaf, 0u);
-    else if (only_round) q_append(l0, 1u, 0u, n, kQBig, 0u);
-    else q_append(p0, 1u, 0u, n, kQPart, 0u);
+    if (n <= leaf_max) q_append(l0, 1u, 0u, n, kQLeaf, 0u, claim_keys);
+    else if (only_round) q_append(l0, 1u, 0u, n, kQBig, 0u, claim_keys);
+    else q_append(p0, 1u, 0u, n, kQPart, 0u, claim_keys);
 }
 
 // ------------------------------------------------------------------ host ---
@@ -449,6 +506,7 @@ int q_run(const QuickArgs& a) {
     uint32_t* wk = reinterpret_cast<uint32_t*>(ws);
     uint8_t* lb = ws + align_up((size_t)a.n * 4, 256);
     const size_t lbytes = q_list_bytes(a.n);
+    const uint32_t claim_keys = a.n <= kQOnePassMax ? (uint32_t)kQChunk : (uint32_t)kQSuper;
     QList* P[3];
     QList* L[3];
     for (int i = 0; i < 3; ++i) {
@@ -458,7 +516,8 @@ int q_run(const QuickArgs& a) {
     {
         LaunchTimer timer("qs_init", 1, a.stream);
         hipLaunchKernelGGL(k_qs_init, dim3(1), dim3(64), 0, a.stream, P[0], P[1], P[2], L[0],
-                           L[1], L[2], (uint32_t)a.n, kLeafMax, rounds == 1 ? 1 : 0);
+                           L[1], L[2], (uint32_t)a.n, kLeafMax, rounds == 1 ? 1 : 0,
+                           claim_keys);
     }
     if (int rc = (int)hipGetLastError()) return rc;
     const QRoundKinds& kinds = q_kinds();
@@ -478,6 +537,7 @@ int q_run(const QuickArgs& a) {
             q.cap = cap;
             q.leaf_max = kLeafMax;
             q.final_next = r + 2 == rounds ? 1 : 0;
+            q.claim_keys = claim_keys;
             LaunchTimer timer(kinds.part[r], a.n, a.stream);
             hipLaunchKernelGGL(pkern, dim3(pgrid), dim3(kBlockThreads), 0, a.stream, q);
             if (int rc = (int)hipGetLastError()) return rc;

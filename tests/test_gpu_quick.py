@@ -56,6 +56,19 @@ def test_quick_tricky_inputs(orc, n):
             assert np.array_equal(got, orc.sort(x, dtype="u32", algo="ms")), name
 
 
+@pytest.mark.parametrize("n", [1 << 23, (1 << 23) + 4097])
+def test_quick_claim_sizes(orc, n):
+    # sorts of at most 2^23 keys claim room per 8192-key chunk, larger ones
+    # per 65,536-key super-tile: both sides of the switch, on random keys and
+    # on few distinct values (long runs of keys equal to the pivot)
+    for dist, x in (("random", workloads.keys(n, "random", "u32", seed=n)),
+                    ("four values", _tricky(n, seed=3)["four values"]),
+                    ("organ pipe", _tricky(n, seed=3)["organ pipe"])):
+        say(f"quick_sort claim sizes n={n} {dist}")
+        got = host(msn.quick_sort(gpu(x)))
+        assert np.array_equal(got, orc.sort(x, dtype="u32", algo="qs")), dist
+
+
 @pytest.mark.parametrize("rounds", [1, 2, 3, 5])
 def test_quick_merge_fallback_after_last_round(orc, rounds):
     # with few rounds, subarrays still longer than a tile go to the merge
