@@ -38,6 +38,10 @@ def flags() -> list[str]:
         "-fPIC",
         # packed fp32 instructions are kept out of every kernel on purpose
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+        # no code computes with floating-point values except the double
+        # minimum and maximum of stable composites, which are never NaN: the
+        # compiler need not quiet NaN operands before them
+        "-fno-honor-nans",
         "-Wall",
         "-Wno-unused-function",
         f"-I{INCLUDE}",

@@ -110,9 +110,8 @@ __device__ __forceinline__ void block_sort_tile(const uint32_t* kin, const uint3
 #pragma unroll
     for (int j = 0; j < KPL; ++j) {
         if constexpr (STABLE) {
-            v[j] = (first + j < nv)
-                       ? (((uint64_t)ord_key<DT>(x[j]) << 32) | (uint32_t)(first + j))
-                       : ~0ull;
+            v[j] = (first + j < nv) ? comp_make(ord_key<DT>(x[j]), (uint32_t)(first + j))
+                                    : kCompMax;
         } else {
             v[j] = (first + j < nv) ? ord_key<DT>(x[j]) : 0xffffffffu;
         }
@@ -238,11 +237,11 @@ __device__ __forceinline__ void block_sort_tile(const uint32_t* kin, const uint3
         uint32_t y[KPL];
 #pragma unroll
         for (int j = 0; j < KPL; ++j) {
-            const uint32_t tag = (uint32_t)v[j];
+            const uint32_t tag = comp_pos(v[j]);
             const bool live = first + j < nv;
             const uint32_t t = live ? tag : 0u;
             if constexpr (kNeedBits) x[j] = sbits[t];
-            else x[j] = unord_key<DT>((uint32_t)(v[j] >> 32));
+            else x[j] = unord_key<DT>(comp_ord(v[j]));
             if constexpr (VM == kVals) y[j] = svals[t];
             else y[j] = val_base + t;
         }

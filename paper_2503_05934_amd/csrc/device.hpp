@@ -12,8 +12,8 @@
 //   4. global passes merge pairs of runs until one run remains.
 // Every merge is stable: on equal keys the left run's element goes first, as
 // in the paper's Merge.  Networks and bitonic stages are not stable, so when
-// stability matters the key carries its tile position in its low 32 bits
-// ("composite key") until the first merge-path level.
+// stability matters the key travels with its tile position in one 64-bit
+// word (a "composite", see comp_make) and ties are broken by position.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -84,11 +84,43 @@ __device__ __forceinline__ void st4_stream(uint32_t* p, uint32_t a, uint32_t b, 
     __builtin_nontemporal_store(w, reinterpret_cast<u32x4*>(p));
 }
 
+// ---------------------------------------------------- stable composites ---
+// A stable sort carries each key with its tile position in one 64-bit word,
+// the composite 2^52 + ord(key) * 2^20 + position (positions below 2^20),
+// stored as the bits of that number as a double: the exponent field of 2^52
+// (0x433) on top, ord(key) and the position in the 52 fraction bits.  Every
+// composite has that exponent, so the word's unsigned integer order, its
+// double order and the order (key, position) agree, and a compare-exchange
+// is one v_min_f64 and one v_max_f64 instead of a 64-bit compare and four
+// 32-bit selects.  The padding and sentinel composite is +inf (0x7FF0...),
+// above every composite in both orders.  No composite is a NaN or a
+// denormal, so the double minimum and maximum are exact.
+constexpr int kCompPosBits = 20;
+constexpr uint64_t kCompBase = 0x4330000000000000ull;  // the bits of 2^52
+constexpr uint64_t kCompMax = 0x7FF0000000000000ull;   // the bits of +inf
+
+__device__ __forceinline__ uint64_t comp_make(uint32_t ord, uint32_t pos) {
+    return kCompBase | ((uint64_t)ord << kCompPosBits) | pos;
+}
+__device__ __forceinline__ uint32_t comp_ord(uint64_t c) { return (uint32_t)(c >> kCompPosBits); }
+__device__ __forceinline__ uint32_t comp_pos(uint64_t c) {
+    return (uint32_t)c & ((1u << kCompPosBits) - 1u);
+}
+
 // ------------------------------------------------------ compare-exchange ---
 __device__ __forceinline__ uint32_t kmin(uint32_t a, uint32_t b) { return a < b ? a : b; }
 __device__ __forceinline__ uint32_t kmax(uint32_t a, uint32_t b) { return a < b ? b : a; }
-__device__ __forceinline__ uint64_t kmin(uint64_t a, uint64_t b) { return a < b ? a : b; }
-__device__ __forceinline__ uint64_t kmax(uint64_t a, uint64_t b) { return a < b ? b : a; }
+// 64-bit words are composites (or kCompMax): minimum and maximum as doubles.
+// The library is built without NaN handling (no key is ever a double NaN), so
+// the compiler does not canonicalise the operands first.
+__device__ __forceinline__ uint64_t kmin(uint64_t a, uint64_t b) {
+    return __builtin_bit_cast(
+        uint64_t, __builtin_fmin(__builtin_bit_cast(double, a), __builtin_bit_cast(double, b)));
+}
+__device__ __forceinline__ uint64_t kmax(uint64_t a, uint64_t b) {
+    return __builtin_bit_cast(
+        uint64_t, __builtin_fmax(__builtin_bit_cast(double, a), __builtin_bit_cast(double, b)));
+}
 
 // Half of a compare-exchange between lanes: the lane whose all-ones `upper`
 // mask is set keeps the larger of (mine, theirs), the other the smaller.  For
@@ -153,7 +185,7 @@ __device__ __forceinline__ void leaf_network(T (&v)[K]) {
 // sentinel that closes every LDS run.
 template <typename T>
 __device__ __forceinline__ constexpr T key_max() {
-    return sizeof(T) == 8 ? (T)~0ull : (T)0xffffffffu;
+    return sizeof(T) == 8 ? (T)kCompMax : (T)0xffffffffu;
 }
 
 // The N-input network (2 <= N <= K) on v[0..N): the K-input network with
@@ -439,19 +471,22 @@ __device__ __forceinline__ void serial_merge_closed(const T* s, int pa, int pb, 
             y = hi;
         }
     } else {
-        // 64-bit composites: track both runs' positions (fewer live registers)
-        const int sum0 = pa + pb;  // grows by one per output
-        T a = lds_load(s, (uint32_t)pa);
-        T b = lds_load(s, (uint32_t)pb);
+        // 64-bit composites (unique, so no ties): the output and the head
+        // kept for the next step are the double minimum and maximum, and
+        // only the positions follow the comparison
+        T x = lds_load(s, (uint32_t)pa);
+        T y = lds_load(s, (uint32_t)pb);
+        uint32_t pc = (uint32_t)pa + 1, po = (uint32_t)pb + 1;
 #pragma unroll
         for (int k = 0; k < N; ++k) {
-            const bool take_a = !(b < a);
-            out[k] = take_a ? a : b;
-            pa += take_a ? 1 : 0;
-            const int p = take_a ? pa : sum0 + k + 1 - pa;
-            const T x = lds_load(s, (uint32_t)p);
-            a = take_a ? x : a;
-            b = take_a ? b : x;
+            const bool keep = !(y < x);
+            out[k] = kmin(x, y);
+            const T hi = kmax(x, y);
+            const uint32_t p = keep ? pc : po;
+            po = keep ? po : pc;
+            pc = p + 1;
+            x = lds_load(s, p);
+            y = hi;
         }
     }
 }

@@ -822,7 +822,7 @@ __global__ __launch_bounds__(THREADS) void k_merge4_pairs(
     static_assert(kM4MaxTile <= THREADS * KPT, "tile fits");
     constexpr int MK = m4p_mk(THREADS);
     static_assert(kM4MaxTile / MK + 2 <= THREADS && kM4Gap >= MK, "merge shape");
-    constexpr uint64_t kMaxC = ~0ull;
+    constexpr uint64_t kMaxC = kCompMax;
     __shared__ __align__(16) unsigned char smem[m4p_lds_bytes(THREADS)];
     uint64_t* cs = reinterpret_cast<uint64_t*>(smem);  // composites
     uint32_t* w32 = reinterpret_cast<uint32_t*>(smem);  // values, then staging
@@ -881,7 +881,7 @@ __global__ __launch_bounds__(THREADS) void k_merge4_pairs(
             uint64_t* dst = cs + lds_idx<uint64_t>((uint32_t)(X0 + r0 * kM4Gap)) + lds_idx<uint64_t>(lane);
 #pragma unroll
             for (int q = 0; q < KPT; ++q)
-                dst[68 * q] = ((uint64_t)ord_key<DT>(rk[q]) << 32) | (uint32_t)(X0 + 64 * q + lane);
+                dst[68 * q] = comp_make(ord_key<DT>(rk[q]), (uint32_t)(X0 + 64 * q + lane));
         } else {
             uint32_t src[KPT];
 #pragma unroll
@@ -902,8 +902,7 @@ __global__ __launch_bounds__(THREADS) void k_merge4_pairs(
                 if (x < cnt) {
                     const int gap =
                         x >= p3 ? 3 * kM4Gap : x >= p2 ? 2 * kM4Gap : x >= p1 ? kM4Gap : 0;
-                    cs[lds_idx<uint64_t>(x + gap)] =
-                        ((uint64_t)ord_key<DT>(rk[q]) << 32) | (uint32_t)x;
+                    cs[lds_idx<uint64_t>(x + gap)] = comp_make(ord_key<DT>(rk[q]), (uint32_t)x);
                 }
             }
         }
@@ -960,8 +959,8 @@ __global__ __launch_bounds__(THREADS) void k_merge4_pairs(
     uint32_t ok[MK], ov[MK];
 #pragma unroll
     for (int k = 0; k < MK; ++k) {
-        const uint32_t x = (uint32_t)o[k];
-        ok[k] = unord_key<DT>((uint32_t)(o[k] >> 32));
+        const uint32_t x = comp_pos(o[k]);
+        ok[k] = unord_key<DT>(comp_ord(o[k]));
         ov[k] = d + k < cnt ? w32[x + (x >> 5)] : 0u;
     }
     // stage keys, then values (a spare word every 32), and store rows

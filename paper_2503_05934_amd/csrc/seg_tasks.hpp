@@ -37,7 +37,7 @@ __device__ __forceinline__ void lane_task(const uint32_t* kin, const uint32_t* v
         raw[j] = live ? kin[off + j] : 0u;
         if constexpr (VM == kVals) pv[j] = live ? vin[off + j] : 0u;
         if constexpr (STABLE)
-            v[j] = live ? (((uint64_t)ord_key<DT>(raw[j]) << 32) | (uint32_t)j) : ~0ull;
+            v[j] = live ? comp_make(ord_key<DT>(raw[j]), (uint32_t)j) : kCompMax;
         else
             v[j] = live ? ord_key<DT>(raw[j]) : 0xffffffffu;
     }
@@ -48,8 +48,8 @@ __device__ __forceinline__ void lane_task(const uint32_t* kin, const uint32_t* v
         if constexpr (!STABLE) {
             kout[off + j] = unord_key<DT>(v[j]);
         } else {
-            const uint32_t tag = (uint32_t)v[j];
-            uint32_t key = unord_key<DT>((uint32_t)(v[j] >> 32));
+            const uint32_t tag = comp_pos(v[j]);
+            uint32_t key = unord_key<DT>(comp_ord(v[j]));
             uint32_t val = tag;
 #pragma unroll
             for (int q = 0; q < K; ++q) {
@@ -80,7 +80,7 @@ __device__ __forceinline__ void wave_task(const uint32_t* kin, const uint32_t* v
         const bool live = first + j < len;
         const uint32_t x = live ? kin[off + first + j] : 0u;
         if constexpr (STABLE)
-            v[j] = live ? (((uint64_t)ord_key<DT>(x) << 32) | (uint32_t)(first + j)) : ~0ull;
+            v[j] = live ? comp_make(ord_key<DT>(x), (uint32_t)(first + j)) : kCompMax;
         else
             v[j] = live ? ord_key<DT>(x) : 0xffffffffu;
     }
@@ -122,10 +122,10 @@ __device__ __forceinline__ void wave_task(const uint32_t* kin, const uint32_t* v
 #pragma unroll
         for (int j = 0; j < KPL; ++j) {
             if (first + j < len) {
-                const uint32_t tag = (uint32_t)v[j];
+                const uint32_t tag = comp_pos(v[j]);
                 uint32_t key;
                 if constexpr (kNeedBits) key = sbits[tag];
-                else key = unord_key<DT>((uint32_t)(v[j] >> 32));
+                else key = unord_key<DT>(comp_ord(v[j]));
                 kout[off + first + j] = key;
                 if constexpr (VM == kVals) vout[off + first + j] = svals[tag];
                 if constexpr (VM == kArg) vout[off + first + j] = tag;
