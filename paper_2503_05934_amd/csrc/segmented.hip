@@ -36,12 +36,17 @@ enum SegClass : int {
     kNumClasses = 5
 };
 
+// Work queues of the tile sort: one per XCD (workgroups are dispatched to
+// the eight XCDs in turn), each head on a 128-byte line of its own.
+constexpr int kSegQueues = 8;
+
 struct SegState {
     uint32_t count[8];
     uint32_t head;
     uint32_t tiles;   // entries of the tile list
     uint32_t status;  // MSN_SEG_BAD_* bits found in this call (0 = offsets valid)
     uint32_t pad[5];
+    uint32_t queue[kSegQueues][32];  // tile-sort queue heads (word 0 of each line)
 };
 
 // Segments of up to this many block-sort tiles take the tiled path (at most
@@ -98,7 +103,8 @@ __device__ __forceinline__ void seg_bounds(const uint32_t* offsets, uint32_t s, 
 // Zeroes the class counters and the work-queue head (a kernel, not a memset,
 // so that graph replays reset it reliably).
 __global__ void k_seg_init(SegState* st) {
-    if (threadIdx.x < sizeof(SegState) / 4) reinterpret_cast<uint32_t*>(st)[threadIdx.x] = 0u;
+    for (uint32_t i = threadIdx.x; i < sizeof(SegState) / 4; i += blockDim.x)
+        reinterpret_cast<uint32_t*>(st)[i] = 0u;
 }
 
 // Classes (and tiles) are counted per workgroup in LDS first, so each
@@ -299,12 +305,16 @@ void k_seg_rows(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32
 }
 
 // ---------------------------------------------- sorts, tiled path ---
-// The runs of the tiled segments, workgroups taking list entries in turn
-// (the entry of a run's first list tile sorts the run; the others pass):
-// the flat sort's block sort (for keys-only runs its 1024-thread shape, 32
-// outputs per thread in its LDS levels, its own register budget), each run
-// written where its segment's first merge pass reads it (the output itself
-// for one run).
+// The runs of the tiled segments, sorted by the flat sort's block sort (for
+// keys-only runs its 1024-thread shape, 32 outputs per thread in its LDS
+// levels, its own register budget), each run written where its segment's
+// first merge pass reads it (the output itself for one run).  A resident
+// grid takes slots of two list entries from kSegQueues queues (slot k from
+// queue k % kSegQueues; workgroup b draws from queue b % kSegQueues, the
+// queue of its XCD); the entry of a run's first list tile sorts the run.
+// Runs cost from a copy (already in order) to a whole block sort, so
+// workgroups draw slots as they finish; each draws its next slot before
+// sorting the current one, so the atomic's latency hides behind the loads.
 template <int DT, int K, bool STABLE, int VM, int NET>
 __global__ __launch_bounds__((SegRun<DT, K, STABLE>::Tr::kThreads),
                              (SegRun<DT, K, STABLE>::Tr::kWavesPerSimd))
@@ -316,26 +326,42 @@ void k_seg_tile_sort(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, u
     __shared__ __align__(16) unsigned char smem[Tr::kLdsBytes];
     constexpr int kRun = R::kRun;
     constexpr uint32_t kPer = R::kRun / R::kListTile;  // list tiles per run
+    __shared__ uint32_t s_next;
     if (st->status) return;
     const uint32_t n = st->tiles;
-    for (uint32_t e = blockIdx.x; e < n; e += gridDim.x) {
-        const uint2 tc = tiles[e];
-        if (tc.y % kPer != 0) continue;  // uniform: one entry per workgroup
-        uint32_t off, len;
-        seg_bounds(offsets, tc.x, uni_len, off, len);
-        const int passes = seg_passes((len + kRun - 1) / kRun);
-        const uint32_t first = tc.y * (uint32_t)R::kListTile;
-        const int nv = min(kRun, (int)(len - first));
-        uint32_t* kd = ((passes & 1) ? wk : kout) + off + first;
-        uint32_t* vd = VM != kNoVals ? ((passes & 1) ? wv : vout) + off + first : nullptr;
-        const uint32_t* ks = kin + off + first;
-        const uint32_t* vs = VM == kVals ? vin + off + first : nullptr;
-        bool done = false;
-        if constexpr (!STABLE) done = copy_if_in_order<DT, Tr::kKPL>(ks, kd, nv, smem);
-        if (!__builtin_amdgcn_readfirstlane(done))
-            block_sort_tile<DT, K, STABLE, VM, R::kShape, true, false, NET>(ks, vs, kd, vd, nv,
-                                                                            first, smem);
-        __syncthreads();  // the next run reuses the LDS
+    const uint32_t q = blockIdx.x % kSegQueues;
+    uint32_t* head = const_cast<uint32_t*>(&st->queue[q][0]);
+    if (threadIdx.x == 0) s_next = atomicAdd(head, 1u);
+    __syncthreads();
+    uint32_t slot = s_next * kSegQueues + q;
+    __syncthreads();  // s_next is written again at the end of the first round
+    while (2 * (uint64_t)slot < n) {
+        // the next slot, drawn now and published at the end of this one
+        uint32_t next = 0;
+        if (threadIdx.x == 0) next = atomicAdd(head, 1u);
+        for (uint32_t e = 2 * slot; e < 2 * slot + 2 && e < n; ++e) {
+            const uint2 tc = tiles[e];
+            if (tc.y % kPer != 0) continue;  // uniform: not a run's first list tile
+            uint32_t off, len;
+            seg_bounds(offsets, tc.x, uni_len, off, len);
+            const int passes = seg_passes((len + kRun - 1) / kRun);
+            const uint32_t first = tc.y * (uint32_t)R::kListTile;
+            const int nv = min(kRun, (int)(len - first));
+            uint32_t* kd = ((passes & 1) ? wk : kout) + off + first;
+            uint32_t* vd = VM != kNoVals ? ((passes & 1) ? wv : vout) + off + first : nullptr;
+            const uint32_t* ks = kin + off + first;
+            const uint32_t* vs = VM == kVals ? vin + off + first : nullptr;
+            bool done = false;
+            if constexpr (!STABLE) done = copy_if_in_order<DT, Tr::kKPL>(ks, kd, nv, smem);
+            if (!__builtin_amdgcn_readfirstlane(done))
+                block_sort_tile<DT, K, STABLE, VM, R::kShape, true, false, NET>(
+                    ks, vs, kd, vd, nv, first, smem);
+            __syncthreads();  // the next run reuses the LDS
+        }
+        if (threadIdx.x == 0) s_next = next;
+        __syncthreads();
+        slot = s_next * kSegQueues + q;
+        __syncthreads();  // s_next is written again in the next round
     }
 }
 
@@ -519,12 +545,8 @@ int launch_seg_kernel(const SegArgs& a, const SegWs& w, uint32_t uni_len) {
         constexpr int kSortThreads = SegRun<DT, K, STABLE>::Tr::kThreads;
         int sgrid = 0;
         if (int rc = fill_grid(skern, kSortThreads, 0, &sgrid)) return rc;
-        // a workgroup per possible run (capped at 256 resident rounds): a
-        // persistent loop over the list put each run's setup behind the
-        // previous run (2.72 against 2.44 ms on the 100,000-array batch);
-        // surplus workgroups find no entry and return
-        constexpr size_t kPer = SegRun<DT, K, STABLE>::kRun / kTile;
-        sgrid = (int)std::min<size_t>((w.max_tiles + kPer - 1) / kPer, (size_t)sgrid * 256);
+        // a resident grid, a multiple of the queue count
+        sgrid = std::max(kSegQueues, sgrid - sgrid % kSegQueues);
         LaunchTimer timer("seg_tile_sort", a.n_total, a.stream);
         hipLaunchKernelGGL(skern, dim3(sgrid), dim3(kSortThreads), 0, a.stream, a.kin, a.vin,
                            a.kout, a.vout, w.wk, w.wv, a.offsets, uni_len, w.st, w.tiles);
@@ -604,7 +626,7 @@ int launch_segmented(const SegArgs& a) {
 
     {
         LaunchTimer timer("seg_init", 1, a.stream);
-        hipLaunchKernelGGL(k_seg_init, dim3(1), dim3(64), 0, a.stream, w.st);
+        hipLaunchKernelGGL(k_seg_init, dim3(1), dim3(256), 0, a.stream, w.st);
     }
     if (int rc = (int)hipGetLastError()) return rc;
     {
