@@ -540,13 +540,16 @@ __device__ __forceinline__ void m4_serial(const unsigned char* sm, uint32_t pa, 
 // Slice r sits at tile position p_r + r * kM4Gap (a multiple of 64 apart),
 // so a wavefront's 64 consecutive keys that lie in one slice are read from
 // one scalar base and written to LDS at one scalar offset.
-template <int DT, int THREADS, int KPT>
-__global__ __launch_bounds__(THREADS) void k_merge4(const uint32_t* __restrict__ in,
-                                                    uint32_t* __restrict__ out,
-                                                    const int32_t* __restrict__ bnd, M4Geom g4,
-                                                    uint32_t* __restrict__ samp_first,
-                                                    uint32_t* __restrict__ samp_last) {
-    const int skip = *g4.skip;  // tested once the boundary loads are in flight
+// gin: the group's first key (run r starts L keys after run r - 1); slice r
+// is gin[r * L + lo[r], + c[r]); the tile's outputs go to out[ostart, ostart
+// + sum c).  SAMPLES: also record the output's chunk samples for the next
+// pass.  lds: m4_lds_words(THREADS) words of static LDS.
+template <int DT, int THREADS, int KPT, bool SAMPLES>
+__device__ __forceinline__ void m4_merge_tile(const uint32_t* __restrict__ gin, int64_t L,
+                                              const int (&lo)[4], const int (&c)[4],
+                                              uint32_t* __restrict__ out, int64_t ostart,
+                                              uint32_t* __restrict__ samp_first,
+                                              uint32_t* __restrict__ samp_last, uint32_t* lds) {
     static_assert(DT == kU32 || DT == kI32, "integer keys only");
     static_assert(kM4MaxTile <= THREADS * KPT, "tile fits");
     static_assert(KPT == 16 || KPT == 32, "outputs of a thread stay in one padded 32-block");
@@ -554,30 +557,8 @@ __global__ __launch_bounds__(THREADS) void k_merge4(const uint32_t* __restrict__
     constexpr Key kMax = DT == kI32 ? (Key)0x7fffffff : (Key)0xffffffffu;
     constexpr int kBuf = m4_buf_keys();
     constexpr uint32_t kDummy = kBuf - 1;
-    // static LDS: its base is a compile-time constant the address math folds
-    __shared__ __align__(16) uint32_t lds[m4_lds_words(THREADS)];
     unsigned char* smem = reinterpret_cast<unsigned char*>(lds);
     Key* b = reinterpret_cast<Key*>(lds);
-
-    // tile -> (group, tile of the group); grids stay below 2^31 tiles
-    const uint32_t t = blockIdx.x;
-    int64_t g, j;
-    {
-        const uint32_t q = m4_udiv(t, g4.by_tiles);
-        g = q < (uint64_t)g4.full_groups ? q : g4.full_groups;
-        j = (int64_t)t - g * g4.tiles_full;
-    }
-    const int64_t row = m4_bound_row(g4, g, j);
-    const int64_t gb = g * 4 * g4.L;
-    int c[4], lo[4];
-    int64_t ostart = gb;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        lo[r] = bnd[row * 4 + r];
-        c[r] = bnd[(row + 1) * 4 + r] - lo[r];
-        ostart += lo[r];
-    }
-    if (skip) return;  // the input is already sorted
     const int p1 = c[0], p2 = p1 + c[1], p3 = p2 + c[2], cnt = p3 + c[3];
     const int tid = threadIdx.x;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -595,8 +576,6 @@ __global__ __launch_bounds__(THREADS) void k_merge4(const uint32_t* __restrict__
             return (x >= p1 ? 1 : 0) + (x >= p2 ? 1 : 0) + (x >= p3 ? 1 : 0);
         };
         // tile key x of slice r is group key x + sh_r
-        const uint32_t* gin = in + gb;
-        const int64_t L = g4.L;
         const int64_t sh0 = lo[0], sh1 = L + lo[1] - p1, sh2 = 2 * L + lo[2] - p2,
                       sh3 = 3 * L + lo[3] - p3;
         const int X0 = wv * 64 * KPT;
@@ -767,16 +746,52 @@ __global__ __launch_bounds__(THREADS) void k_merge4(const uint32_t* __restrict__
         if (q > 0 || tid >= al)
             __builtin_amdgcn_raw_buffer_store_b32(v[q], ro, (tid + q * THREADS) * 4, 0, kM4StoreNt);
     // chunk samples of the output for the next pass
-    constexpr int G = kSampleChunk;
-    const int f0 = (int)((G - (ostart % G)) % G);             // first chunk start in the tile
-    const int l0 = (int)((2 * G - 1 - (ostart % G)) % G);     // first chunk end in the tile
-    if (tid < 32) {
-        const int e = f0 + tid * G;
-        if (e < cnt) samp_first[(ostart + e) / G] = st[e + (e >> 5)];
-    } else if (tid < 64) {
-        const int e = l0 + (tid - 32) * G;
-        if (e < cnt) samp_last[(ostart + e) / G] = st[e + (e >> 5)];
+    if constexpr (SAMPLES) {
+        constexpr int G = kSampleChunk;
+        const int f0 = (int)((G - (ostart % G)) % G);          // first chunk start in the tile
+        const int l0 = (int)((2 * G - 1 - (ostart % G)) % G);  // first chunk end in the tile
+        if (tid < 32) {
+            const int e = f0 + tid * G;
+            if (e < cnt) samp_first[(ostart + e) / G] = st[e + (e >> 5)];
+        } else if (tid < 64) {
+            const int e = l0 + (tid - 32) * G;
+            if (e < cnt) samp_last[(ostart + e) / G] = st[e + (e >> 5)];
+        }
     }
+}
+
+// One tile of a four-way pass of the flat sort: tile -> (group, tile of the
+// group) -> its boundary rows, then the merge.
+template <int DT, int THREADS, int KPT>
+__global__ __launch_bounds__(THREADS) void k_merge4(const uint32_t* __restrict__ in,
+                                                    uint32_t* __restrict__ out,
+                                                    const int32_t* __restrict__ bnd, M4Geom g4,
+                                                    uint32_t* __restrict__ samp_first,
+                                                    uint32_t* __restrict__ samp_last) {
+    const int skip = *g4.skip;  // tested once the boundary loads are in flight
+    // static LDS: its base is a compile-time constant the address math folds
+    __shared__ __align__(16) uint32_t lds[m4_lds_words(THREADS)];
+    // grids stay below 2^31 tiles
+    const uint32_t t = blockIdx.x;
+    int64_t g, j;
+    {
+        const uint32_t q = m4_udiv(t, g4.by_tiles);
+        g = q < (uint64_t)g4.full_groups ? q : g4.full_groups;
+        j = (int64_t)t - g * g4.tiles_full;
+    }
+    const int64_t row = m4_bound_row(g4, g, j);
+    const int64_t gb = g * 4 * g4.L;
+    int c[4], lo[4];
+    int64_t ostart = gb;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        lo[r] = bnd[row * 4 + r];
+        c[r] = bnd[(row + 1) * 4 + r] - lo[r];
+        ostart += lo[r];
+    }
+    if (skip) return;  // the input is already sorted
+    m4_merge_tile<DT, THREADS, KPT, true>(in + gb, g4.L, lo, c, out, ostart, samp_first,
+                                          samp_last, lds);
 }
 
 

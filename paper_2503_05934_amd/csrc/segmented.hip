@@ -23,6 +23,7 @@
 // grid size terminates.
 #include <algorithm>
 
+#include "merge4.hpp"
 #include "seg_tasks.hpp"
 
 namespace msn {
@@ -35,6 +36,10 @@ enum SegClass : int {
     kCBig = 4,    // longer than kSegTiledMax tiles
     kNumClasses = 5
 };
+// The class lists, then the list of four-way segments (keys-only tiled
+// segments of three or four runs).
+constexpr int kList4 = kNumClasses;
+constexpr int kNumLists = kNumClasses + 1;
 
 // Work queues of the tile sort: one per XCD (workgroups are dispatched to
 // the eight XCDs in turn), each head on a 128-byte line of its own.
@@ -45,7 +50,9 @@ struct SegState {
     uint32_t head;
     uint32_t tiles;   // entries of the tile list
     uint32_t status;  // MSN_SEG_BAD_* bits found in this call (0 = offsets valid)
-    uint32_t pad[5];
+    uint32_t tiles4;  // entries of the four-way tile list
+    uint32_t mtiles;  // entries of the merge list (tiles of segments with binary passes)
+    uint32_t pad[3];
     uint32_t queue[kSegQueues][32];  // tile-sort queue heads (word 0 of each line)
 };
 
@@ -59,15 +66,36 @@ inline size_t seg_max_tiles(int64_t n_total, int64_t num_segments) {
     return (size_t)(n_total / 4096) + (size_t)num_segments + 1;
 }
 
+// Four-way tiles: a four-way segment has runs of at most kSeg4MaxChunks
+// chunks of kSampleChunk keys, so at most kSeg4MaxTiles tiles of
+// kM4SamplesPerTile samples; each tile is one self-contained record.
+constexpr int kSeg4MaxChunks = 64;
+constexpr int kSeg4MaxTiles =
+    (4 * kSeg4MaxChunks + kM4SamplesPerTile - 1) / kM4SamplesPerTile;
+struct Seg4Tile {
+    uint32_t off;    // the segment's first key
+    int32_t lo[4];   // first key of run r's slice, from the run's start
+    int32_t c[4];    // keys of run r's slice
+    uint32_t pad[7];
+};
+static_assert(sizeof(Seg4Tile) == 64, "one record per 64 bytes");
+// A four-way segment holds more than two runs of at least 8192 keys.
+inline size_t seg_max_tiles4(int64_t n_total, int64_t num_segments) {
+    const int64_t segs = std::min<int64_t>(num_segments, n_total / 16385 + 1);
+    return (size_t)segs * kSeg4MaxTiles;
+}
 
-// Workspace: ping-pong keys (and values), the class lists, the state block,
-// the tile list (segment, tile) and one merge-path split per tile.
+// Workspace: ping-pong keys (and values), the lists, the state block, the
+// tile list (segment, tile) of every tiled segment, the merge list (the
+// entries of the segments that take binary merge passes) with one
+// merge-path split per entry, and the four-way tile records.
 size_t seg_ws_bytes(int64_t n_total, int64_t num_segments, bool vals) {
     const size_t nk = align_up((size_t)n_total * 4, 256);
-    const size_t lists = align_up((size_t)num_segments * 4 * kNumClasses, 256);
+    const size_t lists = align_up((size_t)num_segments * 4 * kNumLists, 256);
     const size_t mt = seg_max_tiles(n_total, num_segments);
     return nk + (vals ? nk : 0) + lists + align_up(sizeof(SegState), 256) +
-           align_up(mt * 8, 256) + align_up(mt * 4, 256);
+           2 * align_up(mt * 8, 256) + align_up(mt * 4, 256) +
+           align_up(seg_max_tiles4(n_total, num_segments) * sizeof(Seg4Tile), 256);
 }
 
 // Merge passes of a segment of `tiles` block-sort tiles: ceil(log2(tiles)).
@@ -75,6 +103,15 @@ __host__ __device__ inline int seg_passes(uint32_t tiles) {
     int p = 0;
     while ((1u << p) < tiles) ++p;
     return p;
+}
+
+// Global passes a tiled segment of len keys takes after its runs of `run`
+// keys are sorted: binary merge passes, except that a keys-only (FOUR)
+// segment of three or four runs takes one four-way pass instead of two.
+template <bool FOUR>
+__host__ __device__ inline int seg_global_passes(uint32_t len, int run) {
+    const int p = seg_passes((len + run - 1) / run);
+    return (FOUR && p == 2) ? 1 : p;
 }
 
 // Runs the tile sort leaves in a tiled segment: keys-only tiles take the
@@ -122,18 +159,23 @@ __global__ void k_seg_init(SegState* st) {
 __global__ __launch_bounds__(256) void k_seg_bin(const uint32_t* __restrict__ offsets,
                                                  int64_t num_segments, int64_t n_total,
                                                  uint32_t uni_len, int lane_max, int wave_max,
-                                                 int block_max, uint32_t tile, SegState* st,
+                                                 int block_max, uint32_t tile, uint32_t merge_min,
+                                                 uint32_t four_min, SegState* st,
                                                  uint32_t* __restrict__ lists,
-                                                 uint2* __restrict__ tiles, uint32_t max_tiles) {
-    __shared__ uint32_t cnt[kNumClasses + 1], base[kNumClasses + 1];  // + the tile count
+                                                 uint2* __restrict__ tiles,
+                                                 uint2* __restrict__ mtiles, uint32_t max_tiles) {
+    // the class counts, the tile count, the four-way segment count, the
+    // merge-list count
+    __shared__ uint32_t cnt[kNumClasses + 3], base[kNumClasses + 3];
     __shared__ uint32_t bad;
     const int tid = threadIdx.x;
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + tid;
-    if (tid <= kNumClasses) cnt[tid] = 0u;
+    if (tid <= kNumClasses + 2) cnt[tid] = 0u;
     if (tid == 0) bad = 0u;
     __syncthreads();
     int cls = -1;
-    uint32_t pos = 0, nt = 0, tpos = 0;
+    uint32_t pos = 0, nt = 0, tpos = 0, fpos = 0, mpos = 0;
+    bool four = false, merged = false;
     if (s < num_segments) {
         uint32_t off, len;
         uint32_t err = 0u;
@@ -160,6 +202,10 @@ __global__ __launch_bounds__(256) void k_seg_bin(const uint32_t* __restrict__ of
             if (cls == kCTiled) {
                 nt = (len + tile - 1) / tile;
                 tpos = atomicAdd(&cnt[kNumClasses], nt);
+                four = four_min != 0u && len > four_min;
+                if (four) fpos = atomicAdd(&cnt[kNumClasses + 1], 1u);
+                merged = !four && len > merge_min;
+                if (merged) mpos = atomicAdd(&cnt[kNumClasses + 2], nt);
             } else {
                 pos = atomicAdd(&cnt[cls], 1u);
             }
@@ -169,13 +215,19 @@ __global__ __launch_bounds__(256) void k_seg_bin(const uint32_t* __restrict__ of
     __syncthreads();
     if (tid < kNumClasses && cnt[tid] != 0u) base[tid] = atomicAdd(&st->count[tid], cnt[tid]);
     if (tid == kNumClasses && cnt[tid] != 0u) base[tid] = atomicAdd(&st->tiles, cnt[tid]);
-    if (tid == kNumClasses + 1 && bad != 0u) atomicOr(&st->status, bad);
+    if (tid == kNumClasses + 1 && cnt[tid] != 0u)
+        base[tid] = atomicAdd(&st->count[kList4], cnt[tid]);
+    if (tid == kNumClasses + 2 && cnt[tid] != 0u) base[tid] = atomicAdd(&st->mtiles, cnt[tid]);
+    if (tid == kNumClasses + 3 && bad != 0u) atomicOr(&st->status, bad);
     __syncthreads();
     if (cls == kCTiled) {
         for (uint32_t c = 0; c < nt; ++c) {
             const uint32_t e = base[kNumClasses] + tpos + c;
             if (e < max_tiles) tiles[e] = make_uint2((uint32_t)s, c);
+            const uint32_t m = base[kNumClasses + 2] + mpos + c;
+            if (merged && m < max_tiles) mtiles[m] = make_uint2((uint32_t)s, c);
         }
+        if (four) lists[(int64_t)kList4 * num_segments + base[kNumClasses + 1] + fpos] = (uint32_t)s;
     } else if (cls >= 0) {
         lists[(int64_t)cls * num_segments + base[cls] + pos] = (uint32_t)s;
     }
@@ -344,7 +396,7 @@ void k_seg_tile_sort(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, u
             if (tc.y % kPer != 0) continue;  // uniform: not a run's first list tile
             uint32_t off, len;
             seg_bounds(offsets, tc.x, uni_len, off, len);
-            const int passes = seg_passes((len + kRun - 1) / kRun);
+            const int passes = seg_global_passes<!STABLE>(len, kRun);
             const uint32_t first = tc.y * (uint32_t)R::kListTile;
             const int nv = min(kRun, (int)(len - first));
             uint32_t* kd = ((passes & 1) ? wk : kout) + off + first;
@@ -383,15 +435,16 @@ struct SegTilePass {
 
 // Geometry of list entry (seg, c) in pass p (runs of `run` keys after the
 // tile sort, output tiles of `tile` keys); false when the segment has no
-// pass p.
-template <bool VALS>
+// binary pass p (FOUR: keys-only, whose segments of three or four runs take
+// the four-way pass instead).
+template <bool VALS, bool FOUR>
 __device__ __forceinline__ bool seg_tile_pass(uint2 tc, int p, int tile, int run,
                                               const uint32_t* offsets, uint32_t uni_len,
                                               uint32_t* kout, uint32_t* vout, uint32_t* wk,
                                               uint32_t* wv, SegTilePass& g) {
     seg_bounds(offsets, tc.x, uni_len, g.off, g.len);
     const int passes = seg_passes((g.len + run - 1) / run);
-    if (passes <= p) return false;
+    if (passes <= p || (FOUR && passes == 2)) return false;
     const bool src_ws = ((passes - p) & 1) != 0;  // before pass p the data sit in wk
     g.ks = (src_ws ? wk : kout) + g.off;
     g.kd = (src_ws ? kout : wk) + g.off;
@@ -415,9 +468,10 @@ __global__ __launch_bounds__(256) void k_seg_tile_part(
     const uint32_t* __restrict__ offsets, uint32_t uni_len, const SegState* st,
     const uint2* __restrict__ tiles, int32_t* __restrict__ part, int tile, int run, int p) {
     const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (st->status || e >= st->tiles) return;
+    if (st->status || e >= st->mtiles) return;
     SegTilePass g;
-    if (!seg_tile_pass<VALS>(tiles[e], p, tile, run, offsets, uni_len, kout, vout, wk, wv, g))
+    if (!seg_tile_pass<VALS, !VALS && DT != kF32>(tiles[e], p, tile, run, offsets, uni_len, kout,
+                                                   vout, wk, wv, g))
         return;
     part[e] = corank_global<DT>(g.ks + g.base, g.la, g.ks + g.base + g.la, g.lb, g.d0);
 }
@@ -435,16 +489,155 @@ __global__ __launch_bounds__(kBlockThreads, DT == kF32 ? 1 : 6) void k_seg_tile_
     uint32_t* sk = reinterpret_cast<uint32_t*>(smem);
     uint32_t* sv = sk + seg_merge_words(kTile);
     if (st->status) return;
-    const uint32_t n = st->tiles;
+    const uint32_t n = st->mtiles;
     for (uint32_t e = blockIdx.x; e < n; e += gridDim.x) {
         SegTilePass g;
-        if (!seg_tile_pass<VALS>(tiles[e], p, kTile, run, offsets, uni_len, kout, vout, wk, wv,
-                                 g))
+        if (!seg_tile_pass<VALS, !VALS && DT != kF32>(tiles[e], p, kTile, run, offsets, uni_len,
+                                                       kout, vout, wk, wv, g))
             continue;
         const int i0 = part[e];
         const int i1 = g.d1 == g.la + g.lb ? g.la : part[e + 1];
         seg_merge_tile<DT, VALS, KPT>(g.ks, g.vs, g.kd, g.vd, g.base, g.la, g.d0, g.d1, i0, i1,
                                       sk, sv);
+    }
+}
+
+// ------------------------------------------ four-way pass, tiled path ---
+// A keys-only tiled segment of three or four runs merges them in one pass,
+// with the tiles and the tile merge of the flat sort's four-way passes.  One
+// workgroup per segment of the four-way list: the first key of every
+// kSampleChunk-key chunk of every run is staged in LDS (run r at r * CL, CL
+// = run / kSampleChunk chunks) and ranked in the segment's order (key, run,
+// position) against the other runs' samples; every kM4SamplesPerTile-th
+// sample in that order is a tile boundary, whose splits in the other runs
+// are refined inside one chunk.  The segment then appends one record per
+// tile to the four-way tile list.
+template <int DT>
+__global__ __launch_bounds__(256) void k_seg_m4_bounds(const uint32_t* __restrict__ src,
+                                                       const uint32_t* __restrict__ offsets,
+                                                       uint32_t uni_len, int64_t num_segments,
+                                                       SegState* st,
+                                                       const uint32_t* __restrict__ lists,
+                                                       Seg4Tile* __restrict__ tiles4, int run,
+                                                       int lg_cl) {
+    __shared__ uint32_t smp_g[1 + 4 * kSeg4MaxChunks];  // a guard word, then the samples
+    __shared__ int32_t rows[(kSeg4MaxTiles + 1) * 4];
+    __shared__ M4Cut cuts[kSeg4MaxTiles];
+    __shared__ int ncut;
+    __shared__ uint32_t s_base;
+    uint32_t* smp = smp_g + 1;
+    const int tid = threadIdx.x;
+    const int CL = 1 << lg_cl;
+    if (st->status) return;
+    const uint32_t n4 = st->count[kList4];
+    const uint32_t* list4 = lists + (int64_t)kList4 * num_segments;
+    for (uint32_t g = blockIdx.x; g < n4; g += gridDim.x) {
+        uint32_t off, len;
+        seg_bounds(offsets, list4[g], uni_len, off, len);
+        const uint32_t* gin = src + off;
+        int64_t rl[4], rs[4];
+        int total = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int64_t rem = (int64_t)len - (int64_t)k * run;
+            rl[k] = rem <= 0 ? 0 : (rem < run ? rem : run);
+            rs[k] = m4_ceil_div(rl[k], kSampleChunk);
+            total += (int)rs[k];
+        }
+        const int tiles = (total + kM4SamplesPerTile - 1) / kM4SamplesPerTile;
+        if (tid == 0) ncut = 0;
+        if (tid < 4 * CL) {
+            const int r = tid >> lg_cl, i = tid & (CL - 1);
+            if (i < m4_sel(rs, r)) smp[tid] = ord_key<DT>(gin[(int64_t)r * run + (int64_t)i * kSampleChunk]);
+        }
+        __syncthreads();
+        if (tid < 4 * CL) {
+            const int r = tid >> lg_cl;
+            const int64_t ic = tid & (CL - 1);
+            if (ic < m4_sel(rs, r)) {
+                const uint32_t ov = smp[tid];
+                const int o[3] = {r == 0 ? 1 : 0, r <= 1 ? 2 : 1, r <= 2 ? 3 : 2};  // other runs
+                const uint32_t* sa[3] = {smp + o[0] * CL, smp + o[1] * CL, smp + o[2] * CL};
+                const int ma[3] = {(int)m4_sel(rs, o[0]), (int)m4_sel(rs, o[1]),
+                                   (int)m4_sel(rs, o[2])};
+                int cj[3];
+                m4_lds_count3(sa, ma, o, ov, r, lg_cl, cj);
+                const int64_t rank = ic + cj[0] + cj[1] + cj[2];
+                if (rank == 0) {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        rows[k] = 0;
+                        rows[tiles * 4 + k] = (int32_t)rl[k];
+                    }
+                } else if (rank % kM4SamplesPerTile == 0) {
+                    M4Cut c;
+                    c.g = 0;
+                    c.ic = ic;
+                    c.rank = rank;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        c.cnt[k] = k == r ? ic : k == o[0] ? cj[0] : k == o[1] ? cj[1] : cj[2];
+                    c.ov = ov;
+                    c.r = r;
+                    cuts[atomicAdd(&ncut, 1)] = c;  // at most tiles - 1 cuts
+                }
+            }
+        }
+        __syncthreads();
+        // each (cut, run) pair by one thread: keys of run k before the cut
+        {
+            const int e = tid >> 2, k = tid & 3;
+            if (e < ncut) {
+                const M4Cut& c = cuts[e];
+                const int64_t split =
+                    k == c.r ? c.ic * kSampleChunk
+                             : m4_key_count<DT>(gin + (int64_t)k * run, m4_sel(rl, k),
+                                                m4_sel(c.cnt, k), c.ov, k, c.r);
+                rows[(c.rank / kM4SamplesPerTile) * 4 + k] = (int32_t)split;
+            }
+        }
+        if (tid == 0) s_base = atomicAdd(&st->tiles4, (uint32_t)tiles);
+        __syncthreads();
+        if (tid < tiles) {
+            Seg4Tile t;
+            t.off = off;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                t.lo[k] = rows[tid * 4 + k];
+                t.c[k] = rows[(tid + 1) * 4 + k] - rows[tid * 4 + k];
+            }
+#pragma unroll
+            for (int k = 0; k < 7; ++k) t.pad[k] = 0u;
+            tiles4[s_base + tid] = t;
+        }
+        __syncthreads();  // the LDS is reused for the next segment
+    }
+}
+
+// The four-way tiles, workgroups taking records in turn: slices of the
+// runs in src (where the tile sort left them), merged into dst.
+template <int DT, int THREADS, int KPT>
+__global__ __launch_bounds__(THREADS, 8) void k_seg_merge4(const uint32_t* __restrict__ src,
+                                                        uint32_t* __restrict__ dst,
+                                                        const SegState* st,
+                                                        const Seg4Tile* __restrict__ tiles4,
+                                                        int run) {
+    __shared__ __align__(16) uint32_t lds[m4_lds_words(THREADS)];
+    if (st->status) return;
+    const uint32_t n = st->tiles4;
+    for (uint32_t e = blockIdx.x; e < n; e += gridDim.x) {
+        const Seg4Tile t = tiles4[e];
+        int lo[4], c[4];
+        int64_t ostart = t.off;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            lo[k] = t.lo[k];
+            c[k] = t.c[k];
+            ostart += lo[k];
+        }
+        m4_merge_tile<DT, THREADS, KPT, false>(src + t.off, run, lo, c, dst, ostart, nullptr,
+                                               nullptr, lds);
+        __syncthreads();  // the LDS is reused for the next tile
     }
 }
 
@@ -497,8 +690,11 @@ struct SegWs {
     uint32_t *wk, *wv, *lists;
     SegState* st;
     uint2* tiles;
+    uint2* mtiles;
     int32_t* part;
+    Seg4Tile* tiles4;
     size_t max_tiles;
+    size_t max_segs4;  // bound on the four-way segments
 };
 
 template <int DT, int K, bool STABLE, int VM, int NET>
@@ -515,12 +711,18 @@ int launch_seg_kernel(const SegArgs& a, const SegWs& w, uint32_t uni_len) {
         if (int rc = fill_grid(kern, kBlockThreads, Tr::kLds, &grid)) return rc;
     }
     // equal-length segments: the host knows their class and pass count
+    // binary passes, and whether any segment takes the four-way pass
+    // (keys-only segments of three or four runs: seg_global_passes)
     bool any_tiled = true;
     int npass = seg_passes((uint32_t)(kSegTiledMax * kTile / kRun));
+    if (!STABLE) npass = std::min(npass, 1);
+    bool any4 = !STABLE;
     if (!a.offsets) {
         const int64_t len = uni_len;
         any_tiled = len > a.block_max && len <= (int64_t)kSegTiledMax * kTile;
-        npass = any_tiled ? seg_passes((uint32_t)((len + kRun - 1) / kRun)) : 0;
+        const int p = any_tiled ? seg_passes((uint32_t)((len + kRun - 1) / kRun)) : 0;
+        any4 = !STABLE && p == 2;
+        npass = any4 ? 0 : p;
     }
     // equal stable rows of one workgroup-sized tile: the row kernel
     if constexpr (STABLE) {
@@ -570,17 +772,41 @@ int launch_seg_kernel(const SegArgs& a, const SegWs& w, uint32_t uni_len) {
         {
             LaunchTimer timer("seg_tile_part", a.n_total, a.stream);
             hipLaunchKernelGGL((k_seg_tile_part<DT, kVals>), dim3(pgrid), dim3(256), 0, a.stream,
-                               a.kout, a.vout, w.wk, w.wv, a.offsets, uni_len, w.st, w.tiles,
+                               a.kout, a.vout, w.wk, w.wv, a.offsets, uni_len, w.st, w.mtiles,
                                w.part, kTile, kRun, p);
         }
         if (int rc = (int)hipGetLastError()) return rc;
         {
             LaunchTimer timer("seg_tile_merge", a.n_total, a.stream);
             hipLaunchKernelGGL(mkern, dim3(mgrid), dim3(kBlockThreads), mlds, a.stream, a.kout,
-                               a.vout, w.wk, w.wv, a.offsets, uni_len, w.st, w.tiles, w.part,
+                               a.vout, w.wk, w.wv, a.offsets, uni_len, w.st, w.mtiles, w.part,
                                kRun, p);
         }
         if (int rc = (int)hipGetLastError()) return rc;
+    }
+    if constexpr (!STABLE) {
+        if (any4) {
+            static_assert(kRun / kSampleChunk <= kSeg4MaxChunks, "four-way runs fit the samples");
+            const int lg_cl = ilog2(kRun / kSampleChunk);
+            const unsigned bgrid = (unsigned)std::max<size_t>(
+                1, std::min<size_t>(w.max_segs4, 4096));
+            {
+                LaunchTimer timer("seg_m4_bounds", a.n_total, a.stream);
+                hipLaunchKernelGGL(k_seg_m4_bounds<DT>, dim3(bgrid), dim3(256), 0, a.stream, w.wk,
+                                   a.offsets, uni_len, a.num_segments, w.st, w.lists, w.tiles4,
+                                   kRun, lg_cl);
+            }
+            if (int rc = (int)hipGetLastError()) return rc;
+            auto m4kern = &k_seg_merge4<DT, 512, 16>;
+            int m4grid = 0;
+            if (int rc = fill_grid(m4kern, 512, 0, &m4grid)) return rc;
+            {
+                LaunchTimer timer("seg_merge4", a.n_total, a.stream);
+                hipLaunchKernelGGL(m4kern, dim3(m4grid), dim3(512), 0, a.stream, w.wk, a.kout,
+                                   w.st, w.tiles4, kRun);
+            }
+            if (int rc = (int)hipGetLastError()) return rc;
+        }
     }
     return 0;
 }
@@ -608,9 +834,10 @@ int launch_segmented(const SegArgs& a) {
     const bool vals = a.vmode != kNoVals;
     uint8_t* ws = static_cast<uint8_t*>(a.ws);
     const size_t nk = align_up((size_t)a.n_total * 4, 256);
-    const size_t nl = align_up((size_t)a.num_segments * 4 * kNumClasses, 256);
+    const size_t nl = align_up((size_t)a.num_segments * 4 * kNumLists, 256);
     SegWs w;
     w.max_tiles = seg_max_tiles(a.n_total, a.num_segments);
+    w.max_segs4 = seg_max_tiles4(a.n_total, a.num_segments) / kSeg4MaxTiles;
     w.wk = reinterpret_cast<uint32_t*>(ws);
     w.wv = vals ? reinterpret_cast<uint32_t*>(ws + nk) : nullptr;
     uint8_t* q = ws + nk + (vals ? nk : 0);
@@ -620,9 +847,18 @@ int launch_segmented(const SegArgs& a) {
     q += align_up(sizeof(SegState), 256);
     w.tiles = reinterpret_cast<uint2*>(q);
     q += align_up(w.max_tiles * 8, 256);
+    w.mtiles = reinterpret_cast<uint2*>(q);
+    q += align_up(w.max_tiles * 8, 256);
     w.part = reinterpret_cast<int32_t*>(q);
+    q += align_up(w.max_tiles * 4, 256);
+    w.tiles4 = reinterpret_cast<Seg4Tile*>(q);
     const uint32_t uni_len = a.offsets ? 0u : (uint32_t)(a.n_total / a.num_segments);
     const uint32_t tile = 1024u * (uint32_t)a.leaf_k;  // the block-sort tile of every segmented kernel
+    // keys-only sorts (integer keys, no payload) sort runs of two tiles and
+    // merge segments of more than two runs four ways
+    const bool stable = a.vmode != kNoVals || a.dtype == kF32;
+    const uint32_t merge_min = stable ? tile : 2u * tile;  // one run of the tile sort
+    const uint32_t four_min = stable ? 0u : 4u * tile;
 
     {
         LaunchTimer timer("seg_init", 1, a.stream);
@@ -633,8 +869,8 @@ int launch_segmented(const SegArgs& a) {
         LaunchTimer timer("seg_bin", a.num_segments, a.stream);
         hipLaunchKernelGGL(k_seg_bin, dim3((unsigned)((a.num_segments + 255) / 256)), dim3(256),
                            0, a.stream, a.offsets, a.num_segments, a.n_total, uni_len,
-                           a.lane_max, a.wave_max, a.block_max, tile, w.st, w.lists, w.tiles,
-                           (uint32_t)w.max_tiles);
+                           a.lane_max, a.wave_max, a.block_max, tile, merge_min, four_min, w.st,
+                           w.lists, w.tiles, w.mtiles, (uint32_t)w.max_tiles);
     }
     if (int rc = (int)hipGetLastError()) return rc;
     int rc = 0;
@@ -676,7 +912,7 @@ int launch_segmented(const SegArgs& a) {
 
 size_t seg_status_offset(int64_t n_total, int64_t num_segments, bool vals) {
     const size_t nk = align_up((size_t)n_total * 4, 256);
-    const size_t nl = align_up((size_t)num_segments * 4 * kNumClasses, 256);
+    const size_t nl = align_up((size_t)num_segments * 4 * kNumLists, 256);
     return nk + (vals ? nk : 0) + nl + offsetof(SegState, status);
 }
 

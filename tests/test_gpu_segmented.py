@@ -70,6 +70,54 @@ def test_segmented_all_classes(orc, dtype, leaf):
     assert np.array_equal(host(po).view(np.uint32), rp)
 
 
+# Keys-only segments of three or four runs (runs of 2 x 1024 K keys after the
+# tile sort) merge in one four-way pass; two-run segments in one binary pass.
+FOUR_WAY_LENGTHS = {"6To8": [16385, 32768, 32769, 32770, 40000, 49151, 49152, 49153, 65535, 65536],
+                    "3To5": [8193, 16384, 16385, 20000, 24576, 24577, 32767, 32768]}
+
+
+def _four_way_keys(total, dist, dtype, seed):
+    rng = np.random.default_rng(seed)
+    hi = 2**31 if dtype == "i32" else 2**32
+    if dist == "random":
+        x = rng.integers(0, hi, total, dtype=np.int64)
+    elif dist == "few":
+        x = rng.integers(0, 3, total, dtype=np.int64) * (hi // 4)
+    elif dist == "equal":
+        x = np.full(total, hi // 2 + 1, dtype=np.int64)
+    elif dist == "ascending":
+        x = np.arange(total, dtype=np.int64) % hi
+    else:  # descending, with the extremes
+        x = (hi - 1 - np.arange(total, dtype=np.int64)) % hi
+        x[:: 97] = 0
+        x[1:: 89] = hi - 1
+    return x.astype(np.int32 if dtype == "i32" else np.uint32)
+
+
+@pytest.mark.parametrize("leaf", ["6To8", "3To5"])
+@pytest.mark.parametrize("dtype", ["i32", "u32"])
+def test_four_way_segments(orc, dtype, leaf):
+    base = FOUR_WAY_LENGTHS[leaf]
+    rng = np.random.default_rng(17)
+    top = base[-1]
+    lengths = np.concatenate([base, rng.integers(top // 2 + 1, top + 1, 40), [5, 0, 3000], base[::-1]])
+    off = offsets_of(lengths)
+    for i, dist in enumerate(("random", "few", "equal", "ascending", "descending")):
+        x = _four_way_keys(int(off[-1]), dist, dtype, seed=30 + i)
+        say(f"four-way segments {dtype} {leaf} {dist} S={len(lengths)} n={int(off[-1])}")
+        y = msn.segmented_sort(gpu(x), gpu(off), leaf=leaf)
+        ref = orc.segmented_sort(x, off, dtype=dtype, config=leaf)
+        assert np.array_equal(host(y), ref), dist
+    # equal-length rows of three and of four runs (no offsets array: the
+    # host knows the pass plan)
+    for rl in (base[3], base[-1]):
+        x = _four_way_keys(rl * 7, "few", dtype, seed=rl)
+        off_r = offsets_of(np.full(7, rl))
+        say(f"four-way rows (offsets=None) {dtype} {leaf} 7 x {rl}")
+        y = msn.segmented_sort(gpu(x), None, num_segments=7, leaf=leaf)
+        assert np.array_equal(host(y), orc.segmented_sort(x, off_r, dtype=dtype, config=leaf)), rl
+
+
 def test_segmented_batched_recipe(orc):
     # the batched workload's recipe (log-uniform 3..65536, 30 % presorted) at
     # 1,500 segments so the oracle finishes in seconds
