@@ -10,14 +10,18 @@
 //   tiled  (up to kSegTiledMax block-sort tiles): every run is a work item
 //          of its own (k_seg_tile_sort: keys-only runs are two tiles long,
 //          sorted by the flat sort's 1024-thread block sort; stable runs are
-//          one tile), then up to two (keys-only) or three merge passes over
-//          all such segments at once, one workgroup per output tile
-//          (k_seg_tile_part, then k_seg_tile_merge); tiles already in order
-//          are copied rather than sorted or merged;
+//          one tile), then merge passes over all such segments at once, one
+//          workgroup per output tile: keys-only segments of two runs take one
+//          binary pass (k_seg_tile_part, then k_seg_tile_merge) and those of
+//          three or four runs one four-way pass (k_seg_m4_bounds, then
+//          k_seg_merge4); stable segments take up to three binary passes;
+//          tiles already in order are copied rather than sorted or merged;
 //   big    (longer): one workgroup sorts the segment's tiles in turn and then
 //          merges them pass by pass through global memory.
-// k_seg_bin sorts segment ids into per-class lists and the tiles of tiled
-// segments into a tile list; the persistent k_segmented pulls the lane, wave,
+// k_seg_bin sorts segment ids into per-class lists, the tiles of tiled
+// segments into a tile list (and those of segments that take binary passes
+// into a merge list), and the four-way segments into a list of their own;
+// the persistent k_segmented pulls the lane, wave,
 // block and big work items (big segments first) from one atomic counter
 // until the lists are exhausted.  No workgroup ever waits for another, so any
 // grid size terminates.
