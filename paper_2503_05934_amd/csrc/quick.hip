@@ -216,8 +216,11 @@ __device__ __forceinline__ void q_child(const QPartRound& r, uint32_t start, uin
     else q_append(r.lout_p, r.cap, start, len, kQPart, 0u, r.claim_keys);
 }
 
-// One super-tile of partition item `it` (index sub of its super-tiles).
-template <int DT>
+// One claim tile of partition item `it` (index sub of its claim tiles of CK
+// keys: kQChunk, read once, or kQSuper, counted and then read again).  The
+// claim size is a template parameter so that each kernel holds the registers
+// of its own path only.
+template <int DT, int CK>
 __device__ void q_partition(const QPartRound& r, QItem* itp, const QItem& it, uint32_t sub,
                             uint32_t* smem) {
     const int tid = threadIdx.x;
@@ -228,14 +231,14 @@ __device__ void q_partition(const QPartRound& r, QItem* itp, const QItem& it, ui
     const uint32_t kc = ord_key<DT>(src[it.len - 1]);
     const uint32_t p = max(min(ka, kb), min(max(ka, kb), kc));
 
-    const int ck = (int)r.claim_keys;
+    constexpr int ck = CK;
     const int s0 = (int)sub * ck;
     const int ns = min(ck, (int)it.len - s0);
     const int first = tid * kQKeysPerThread;
     uint32_t* sw = smem + kQChunk;
     __shared__ unsigned long long s_base;
 
-    if (ck == kQChunk) {
+    if constexpr (ck == kQChunk) {
         // one chunk per claim: read once, count, claim, compact, write
         uint32_t x[kQKeysPerThread];
         q_load(src + s0, first, ns, x);
@@ -337,7 +340,7 @@ __device__ void q_partition(const QPartRound& r, QItem* itp, const QItem& it, ui
         // No fence: the children are read by later launches only, and a
         // device-scope release here would write back the L2 for every
         // claim tile.  This tile's claim returned before this increment.
-        if (atomicAdd(&itp->done, 1u) + 1u == q_tiles(kQPart, it.len, r.claim_keys)) {
+        if (atomicAdd(&itp->done, 1u) + 1u == q_tiles(kQPart, it.len, (uint32_t)CK)) {
             // every tile has claimed its room: the totals are final
             const unsigned long long c = atomicAdd(&itp->claimed, 0ull);
             const uint32_t nl = (uint32_t)c, ng = (uint32_t)(c >> 32);
@@ -354,7 +357,7 @@ __device__ void q_partition(const QPartRound& r, QItem* itp, const QItem& it, ui
 // Partition and fill items.  Workgroup b takes a contiguous range of the
 // round's super-tiles, so it looks its first item up once and then steps
 // through the list.
-template <int DT>
+template <int DT, int CK>
 __global__ __launch_bounds__(kBlockThreads, 6) void k_qs_part(QPartRound r) {
     __shared__ __align__(16) uint32_t smem[kQChunk + 2 * kBlockThreads / kWave];
     __shared__ uint32_t s_item;
@@ -383,7 +386,7 @@ __global__ __launch_bounds__(kBlockThreads, 6) void k_qs_part(QPartRound r) {
         const QItem it = items[i];
         const uint32_t sub = t - it.tile0;
         if (it.kind == kQPart) {
-            q_partition<DT>(r, items + i, it, sub, smem);
+            q_partition<DT, CK>(r, items + i, it, sub, smem);
         } else {  // fill
             const uint32_t f0 = sub * kQSuper;
             const uint32_t nf = min((uint32_t)kQSuper, it.len - f0);
@@ -492,7 +495,8 @@ int q_grid(Kern kern, size_t lds, int* out) {
 template <int DT, int K, int NETS>
 int q_run(const QuickArgs& a) {
     constexpr uint32_t kLeafMax = TileTraits<DT, K, false>::kTile;
-    auto pkern = &k_qs_part<DT>;
+    const bool one_pass = a.n <= kQOnePassMax;
+    auto pkern = one_pass ? &k_qs_part<DT, kQChunk> : &k_qs_part<DT, kQSuper>;
     auto lkern = &k_qs_leaf<DT, K, NETS>;
     const size_t llds = q_leaf_lds<DT, K, NETS>();
     if (int rc = set_dynamic_lds(reinterpret_cast<const void*>(lkern), llds)) return rc;
@@ -506,7 +510,7 @@ int q_run(const QuickArgs& a) {
     uint32_t* wk = reinterpret_cast<uint32_t*>(ws);
     uint8_t* lb = ws + align_up((size_t)a.n * 4, 256);
     const size_t lbytes = q_list_bytes(a.n);
-    const uint32_t claim_keys = a.n <= kQOnePassMax ? (uint32_t)kQChunk : (uint32_t)kQSuper;
+    const uint32_t claim_keys = one_pass ? (uint32_t)kQChunk : (uint32_t)kQSuper;
     QList* P[3];
     QList* L[3];
     for (int i = 0; i < 3; ++i) {
