@@ -354,15 +354,18 @@ __device__ void q_partition(const QPartRound& r, QItem* itp, const QItem& it, ui
     }
 }
 
-// Partition and fill items.  Workgroup b takes a contiguous range of the
-// round's super-tiles, so it looks its first item up once and then steps
+// LDS words of the partition work: one chunk and the scan's per-wave words.
+constexpr int kQPartWords = kQChunk + 2 * kBlockThreads / kWave;
+
+// Partition and fill items.  Workgroup b of nb takes a contiguous range of
+// the round's claim tiles, so it looks its first item up once and then steps
 // through the list.
 template <int DT, int CK>
-__global__ __launch_bounds__(kBlockThreads, 6) void k_qs_part(QPartRound r) {
-    __shared__ __align__(16) uint32_t smem[kQChunk + 2 * kBlockThreads / kWave];
+__device__ __forceinline__ void q_part_work(const QPartRound& r, uint32_t b, uint32_t nb,
+                                            uint32_t* smem) {
     __shared__ uint32_t s_item;
     const int tid = threadIdx.x;
-    if (blockIdx.x == 0 && tid == 0) {
+    if (b == 0 && tid == 0) {
         r.clr_p->packed = 0ull;
         r.clr_l->packed = 0ull;
     }
@@ -370,8 +373,8 @@ __global__ __launch_bounds__(kBlockThreads, 6) void k_qs_part(QPartRound r) {
     const uint32_t count = (uint32_t)(pk >> 32);
     const uint32_t tiles = (uint32_t)pk;
     if (count > r.cap) return;  // an append was dropped (status set); never index past the list
-    const uint32_t per = (tiles + gridDim.x - 1) / gridDim.x;
-    const uint32_t t0 = blockIdx.x * per;
+    const uint32_t per = (tiles + nb - 1) / nb;
+    const uint32_t t0 = b * per;
     const uint32_t t1 = min(tiles, t0 + per);
     if (t0 >= t1) return;
     QItem* items = q_items(r.lin);
@@ -402,6 +405,12 @@ __global__ __launch_bounds__(kBlockThreads, 6) void k_qs_part(QPartRound r) {
     }
 }
 
+template <int DT, int CK>
+__global__ __launch_bounds__(kBlockThreads, 6) void k_qs_part(QPartRound r) {
+    __shared__ __align__(16) uint32_t smem[kQPartWords];
+    q_part_work<DT, CK>(r, blockIdx.x, gridDim.x, smem);
+}
+
 struct QLeafRound {
     const uint32_t* cur;  // where this round's items are
     uint32_t* out;        // the output array
@@ -411,14 +420,14 @@ struct QLeafRound {
     uint32_t set_mask;    // network sizes of the leaf set
 };
 
-// Leaf and big items, one workgroup each.
+// Leaf and big items, one workgroup each (workgroup b of nb).
 template <int DT, int K, int NETS>
-__global__ __launch_bounds__(kBlockThreads, 4) void k_qs_leaf(QLeafRound r) {
-    extern __shared__ __align__(16) unsigned char smem[];
+__device__ __forceinline__ void q_leaf_work(const QLeafRound& r, uint32_t b, uint32_t nb,
+                                            unsigned char* smem) {
     const int tid = threadIdx.x;
     const uint32_t count = min((uint32_t)(r.lin->packed >> 32), r.cap);
     const QItem* items = q_items(r.lin);
-    for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {
+    for (uint32_t i = b; i < count; i += nb) {
         const QItem it = items[i];
         if (it.kind == kQLeaf) {
             constexpr int KPL = TileTraits<DT, K, false>::kKPL;
@@ -440,6 +449,28 @@ __global__ __launch_bounds__(kBlockThreads, 4) void k_qs_leaf(QLeafRound r) {
         }
         __syncthreads();  // the LDS is reused
     }
+}
+
+template <int DT, int K, int NETS>
+__global__ __launch_bounds__(kBlockThreads, 4) void k_qs_leaf(QLeafRound r) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    q_leaf_work<DT, K, NETS>(r, blockIdx.x, gridDim.x, smem);
+}
+
+// One whole round of a sort of at most kQOnePassMax keys: the first pb
+// workgroups partition, the others sort the round's leaves.  The two are
+// independent (the round's leaves came from the previous round's
+// partitions, and the partitions write other positions and other lists), so
+// one launch serves both: half the launches of the two-kernel round, which
+// dominate a sort whose rounds are short.
+template <int DT, int K, int NETS>
+__global__ __launch_bounds__(kBlockThreads, 4) void k_qs_round(QPartRound rp, QLeafRound rl,
+                                                               uint32_t pb) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    if (blockIdx.x < pb)
+        q_part_work<DT, kQChunk>(rp, blockIdx.x, pb, reinterpret_cast<uint32_t*>(smem));
+    else
+        q_leaf_work<DT, K, NETS>(rl, blockIdx.x - pb, gridDim.x - pb, smem);
 }
 
 // Round 0's lists: the whole array as one item (a partition item, or a leaf
@@ -498,11 +529,20 @@ int q_run(const QuickArgs& a) {
     const bool one_pass = a.n <= kQOnePassMax;
     auto pkern = one_pass ? &k_qs_part<DT, kQChunk> : &k_qs_part<DT, kQSuper>;
     auto lkern = &k_qs_leaf<DT, K, NETS>;
+    auto rkern = &k_qs_round<DT, K, NETS>;
     const size_t llds = q_leaf_lds<DT, K, NETS>();
+    const size_t rlds = std::max(llds, (size_t)kQPartWords * 4);
     if (int rc = set_dynamic_lds(reinterpret_cast<const void*>(lkern), llds)) return rc;
-    int pgrid = 0, lgrid = 0;
+    if (int rc = set_dynamic_lds(reinterpret_cast<const void*>(rkern), rlds)) return rc;
+    int pgrid = 0, lgrid = 0, rgrid = 0;
     if (int rc = q_grid(pkern, 0, &pgrid)) return rc;
     if (int rc = q_grid(lkern, llds, &lgrid)) return rc;
+    if (int rc = q_grid(rkern, rlds, &rgrid)) return rc;
+    // one-launch rounds: partition workgroups for the most claim tiles a
+    // round can hold (its items are longer than a leaf, so fewer than
+    // 2 n / kQChunk tiles), then a resident grid's worth for the leaves
+    const uint32_t rpart = (uint32_t)std::min<int64_t>(
+        std::max<int64_t>(1, (2 * a.n + kQChunk - 1) / kQChunk), rgrid);
 
     const int rounds =
         a.n <= kLeafMax ? 1 : a.rounds > 0 ? a.rounds : quick_rounds(a.n, kLeafMax);
@@ -542,17 +582,20 @@ int q_run(const QuickArgs& a) {
             q.leaf_max = kLeafMax;
             q.final_next = r + 2 == rounds ? 1 : 0;
             q.claim_keys = claim_keys;
+            if (one_pass) {
+                // the round's partitions and leaves in one launch
+                QLeafRound ql{cur, a.kout, wk, L[r % 3], cap, a.set_mask};
+                LaunchTimer timer(kinds.part[r], a.n, a.stream);
+                hipLaunchKernelGGL(rkern, dim3(rpart + (uint32_t)rgrid), dim3(kBlockThreads),
+                                   rlds, a.stream, q, ql, rpart);
+                if (int rc = (int)hipGetLastError()) return rc;
+                continue;
+            }
             LaunchTimer timer(kinds.part[r], a.n, a.stream);
             hipLaunchKernelGGL(pkern, dim3(pgrid), dim3(kBlockThreads), 0, a.stream, q);
             if (int rc = (int)hipGetLastError()) return rc;
         }
-        QLeafRound ql;
-        ql.cur = cur;
-        ql.out = a.kout;
-        ql.wk = wk;
-        ql.lin = L[r % 3];
-        ql.cap = cap;
-        ql.set_mask = a.set_mask;
+        QLeafRound ql{cur, a.kout, wk, L[r % 3], cap, a.set_mask};
         LaunchTimer timer(kinds.leaf[r], a.n, a.stream);
         hipLaunchKernelGGL(lkern, dim3(lgrid), dim3(kBlockThreads), llds, a.stream, ql);
         if (int rc = (int)hipGetLastError()) return rc;
