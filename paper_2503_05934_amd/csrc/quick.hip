@@ -4,9 +4,10 @@
 // partitioned around it and both sides are sorted the same way.
 //
 // On the GPU the recursion runs level by level.  Round r works through two
-// lists of subarrays ("items") of the whole array, one launch each, and
-// builds the lists of round r + 1:
-//   partition launch:
+// lists of subarrays ("items") of the whole array in one launch (the first
+// workgroups take the partition list, the others the leaf list) and builds
+// the lists of round r + 1:
+//   partition list:
 //     partition item (longer than one block-sort tile): cut into claim
 //       tiles, one workgroup each: 8192-key chunks in sorts of at most
 //       kQOnePassMax keys, 65,536-key super-tiles in larger ones.  A tile
@@ -21,7 +22,7 @@
 //       three-way split; the paper splits in two, which for equal keys only
 //       moves them to one side or the other);
 //     fill item: the keys equal to a pivot, written to the output;
-//   leaf launch:
+//   leaf list:
 //     leaf item (at most one block-sort tile): sorted by one workgroup into
 //       the output -- a subarray of at most K keys by one lane with one
 //       K-key network, a longer one by the block sort (K-key networks in
@@ -405,12 +406,6 @@ __device__ __forceinline__ void q_part_work(const QPartRound& r, uint32_t b, uin
     }
 }
 
-template <int DT, int CK>
-__global__ __launch_bounds__(kBlockThreads, 6) void k_qs_part(QPartRound r) {
-    __shared__ __align__(16) uint32_t smem[kQPartWords];
-    q_part_work<DT, CK>(r, blockIdx.x, gridDim.x, smem);
-}
-
 struct QLeafRound {
     const uint32_t* cur;  // where this round's items are
     uint32_t* out;        // the output array
@@ -457,18 +452,19 @@ __global__ __launch_bounds__(kBlockThreads, 4) void k_qs_leaf(QLeafRound r) {
     q_leaf_work<DT, K, NETS>(r, blockIdx.x, gridDim.x, smem);
 }
 
-// One whole round of a sort of at most kQOnePassMax keys: the first pb
-// workgroups partition, the others sort the round's leaves.  The two are
-// independent (the round's leaves came from the previous round's
-// partitions, and the partitions write other positions and other lists), so
-// one launch serves both: half the launches of the two-kernel round, which
-// dominate a sort whose rounds are short.
-template <int DT, int K, int NETS>
+// One whole round: the first pb workgroups partition (claim tiles of CK
+// keys), the others sort the round's leaves.  The two are independent (the
+// round's leaves came from the previous round's partitions, and the
+// partitions write other positions and other lists), so one launch serves
+// both: the leaves overlap the partitions, and a sort of short rounds makes
+// half the launches.  (Two launches per round: 10,000 keys 79.5 against
+// 56.9 us, 2^28 keys 17.3 against 16.1 ms.)
+template <int DT, int K, int NETS, int CK>
 __global__ __launch_bounds__(kBlockThreads, 4) void k_qs_round(QPartRound rp, QLeafRound rl,
                                                                uint32_t pb) {
     extern __shared__ __align__(16) unsigned char smem[];
     if (blockIdx.x < pb)
-        q_part_work<DT, kQChunk>(rp, blockIdx.x, pb, reinterpret_cast<uint32_t*>(smem));
+        q_part_work<DT, CK>(rp, blockIdx.x, pb, reinterpret_cast<uint32_t*>(smem));
     else
         q_leaf_work<DT, K, NETS>(rl, blockIdx.x - pb, gridDim.x - pb, smem);
 }
@@ -502,13 +498,14 @@ constexpr size_t q_leaf_lds() {
     return SegTraits<DT, K, false, kNoVals>::kLds;
 }
 
-// Timing kinds "qs_part_00" .. and "qs_leaf_00" ..: one per round index.
+// Timing kinds "qs_round_00" ..: one per round index ("qs_leaf_00" for a
+// sort of one round).
 struct QRoundKinds {
-    char part[kQuickMaxRounds][16];
+    char round[kQuickMaxRounds][16];
     char leaf[kQuickMaxRounds][16];
     QRoundKinds() {
         for (int i = 0; i < kQuickMaxRounds; ++i) {
-            snprintf(part[i], sizeof part[i], "qs_part_%02d", i);
+            snprintf(round[i], sizeof round[i], "qs_round_%02d", i);
             snprintf(leaf[i], sizeof leaf[i], "qs_leaf_%02d", i);
         }
     }
@@ -527,22 +524,22 @@ template <int DT, int K, int NETS>
 int q_run(const QuickArgs& a) {
     constexpr uint32_t kLeafMax = TileTraits<DT, K, false>::kTile;
     const bool one_pass = a.n <= kQOnePassMax;
-    auto pkern = one_pass ? &k_qs_part<DT, kQChunk> : &k_qs_part<DT, kQSuper>;
+    const int ck = one_pass ? kQChunk : kQSuper;
     auto lkern = &k_qs_leaf<DT, K, NETS>;
-    auto rkern = &k_qs_round<DT, K, NETS>;
+    auto rkern = one_pass ? &k_qs_round<DT, K, NETS, kQChunk> : &k_qs_round<DT, K, NETS, kQSuper>;
     const size_t llds = q_leaf_lds<DT, K, NETS>();
     const size_t rlds = std::max(llds, (size_t)kQPartWords * 4);
     if (int rc = set_dynamic_lds(reinterpret_cast<const void*>(lkern), llds)) return rc;
     if (int rc = set_dynamic_lds(reinterpret_cast<const void*>(rkern), rlds)) return rc;
-    int pgrid = 0, lgrid = 0, rgrid = 0;
-    if (int rc = q_grid(pkern, 0, &pgrid)) return rc;
+    int lgrid = 0, rgrid = 0;
     if (int rc = q_grid(lkern, llds, &lgrid)) return rc;
     if (int rc = q_grid(rkern, rlds, &rgrid)) return rc;
-    // one-launch rounds: partition workgroups for the most claim tiles a
+    // a round's launch: partition workgroups for the most claim tiles a
     // round can hold (its items are longer than a leaf, so fewer than
-    // 2 n / kQChunk tiles), then a resident grid's worth for the leaves
-    const uint32_t rpart = (uint32_t)std::min<int64_t>(
-        std::max<int64_t>(1, (2 * a.n + kQChunk - 1) / kQChunk), rgrid);
+    // 2 n / ck tiles), capped at a resident grid, then a resident grid's
+    // worth for the leaves
+    const uint32_t rpart =
+        (uint32_t)std::min<int64_t>(std::max<int64_t>(1, (2 * a.n + ck - 1) / ck), rgrid);
 
     const int rounds =
         a.n <= kLeafMax ? 1 : a.rounds > 0 ? a.rounds : quick_rounds(a.n, kLeafMax);
@@ -550,7 +547,7 @@ int q_run(const QuickArgs& a) {
     uint32_t* wk = reinterpret_cast<uint32_t*>(ws);
     uint8_t* lb = ws + align_up((size_t)a.n * 4, 256);
     const size_t lbytes = q_list_bytes(a.n);
-    const uint32_t claim_keys = one_pass ? (uint32_t)kQChunk : (uint32_t)kQSuper;
+    const uint32_t claim_keys = (uint32_t)ck;
     QList* P[3];
     QList* L[3];
     for (int i = 0; i < 3; ++i) {
@@ -582,19 +579,15 @@ int q_run(const QuickArgs& a) {
             q.leaf_max = kLeafMax;
             q.final_next = r + 2 == rounds ? 1 : 0;
             q.claim_keys = claim_keys;
-            if (one_pass) {
-                // the round's partitions and leaves in one launch
-                QLeafRound ql{cur, a.kout, wk, L[r % 3], cap, a.set_mask};
-                LaunchTimer timer(kinds.part[r], a.n, a.stream);
-                hipLaunchKernelGGL(rkern, dim3(rpart + (uint32_t)rgrid), dim3(kBlockThreads),
-                                   rlds, a.stream, q, ql, rpart);
-                if (int rc = (int)hipGetLastError()) return rc;
-                continue;
-            }
-            LaunchTimer timer(kinds.part[r], a.n, a.stream);
-            hipLaunchKernelGGL(pkern, dim3(pgrid), dim3(kBlockThreads), 0, a.stream, q);
+            // the round's partitions and leaves in one launch
+            QLeafRound ql{cur, a.kout, wk, L[r % 3], cap, a.set_mask};
+            LaunchTimer timer(kinds.round[r], a.n, a.stream);
+            hipLaunchKernelGGL(rkern, dim3(rpart + (uint32_t)rgrid), dim3(kBlockThreads), rlds,
+                               a.stream, q, ql, rpart);
             if (int rc = (int)hipGetLastError()) return rc;
+            continue;
         }
+        // a sort of one round: its one leaf or big item
         QLeafRound ql{cur, a.kout, wk, L[r % 3], cap, a.set_mask};
         LaunchTimer timer(kinds.leaf[r], a.n, a.stream);
         hipLaunchKernelGGL(lkern, dim3(lgrid), dim3(kBlockThreads), llds, a.stream, ql);
