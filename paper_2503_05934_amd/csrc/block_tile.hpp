@@ -75,16 +75,23 @@ __device__ __forceinline__ void write_samples(const Samples& samp, int first, in
 // per thread; fewer co-rank searches for more live registers.
 // PACK (stable integer tiles of 16 keys per lane): tiles whose keys all fit
 // 32 - kPackPosBits bits sort 32-bit (key, position) composites instead of
-// 64-bit ones (a run-time choice per tile).
+// 64-bit ones (a run-time choice per tile); kPackOnly leaves any other tile
+// untouched and returns false (its caller then needs only the LDS of the
+// packed path, packed_lds_bytes).  Returns true when the tile was sorted.
+constexpr int kPackNone = 0, kPackAuto = 1, kPackOnly = 2;
+
 template <int DT, int K, bool STABLE, int VM, int SHAPE = 0, bool WIDE = false,
-          bool PACK = false, int NETS = kNetPlain>
-__device__ __forceinline__ void block_sort_tile(const uint32_t* kin, const uint32_t* vin,
+          int PACK = kPackNone, int NETS = kNetPlain>
+__device__ __forceinline__ bool block_sort_tile(const uint32_t* kin, const uint32_t* vin,
                                                 uint32_t* kout, uint32_t* vout, int nv,
                                                 uint32_t val_base, void* smem,
                                                 Samples samp = Samples{nullptr, nullptr, 0}) {
     using Tr = TileTraits<DT, K, STABLE, SHAPE>;
     using T = typename Tr::T;
     static_assert(STABLE || (DT != kF32 && VM == kNoVals), "float keys and pairs sort stably");
+    static_assert(PACK != kPackOnly || (STABLE && DT != kF32 && Tr::kKPL == 16 &&
+                                        Tr::kTile <= (1 << kPackPosBits)),
+                  "pack-only tiles are stable integer tiles of 16 keys per lane");
     static_assert(NETS != kNetNone || (!WIDE && !PACK),
                   "the network-free tile takes the plain paths");
     T* s = reinterpret_cast<T*>(smem);
@@ -161,7 +168,7 @@ __device__ __forceinline__ void block_sort_tile(const uint32_t* kin, const uint3
         constexpr bool kNeedBits = DT == kF32;
         constexpr bool kNeedVals = VM == kVals;
         uint32_t* sbits = reinterpret_cast<uint32_t*>(smem);
-        uint32_t* svals = sbits + Tr::kTile;
+        uint32_t* svals = kNeedBits ? sbits + Tr::kTile : sbits;
         if constexpr (PACK && DT != kF32 && KPL == 16 && Tr::kTile <= (1 << kPackPosBits)) {
             // Every key of the tile below 2^(32 - kPackPosBits): the composite
             // (key, position) fits 32 bits, and the tile takes the keys-only
@@ -218,8 +225,9 @@ __device__ __forceinline__ void block_sort_tile(const uint32_t* kin, const uint3
                             }
                     }
                 }
-                return;
+                return true;
             }
+            if constexpr (PACK == kPackOnly) return false;
         }
         if constexpr (NETS != kNetNone)
             block_sort_regs<T, K, KPL, NETS>(v, s, span);
@@ -264,6 +272,19 @@ __device__ __forceinline__ void block_sort_tile(const uint32_t* kin, const uint3
                 }
         }
     }
+    return true;
+}
+
+// LDS bytes of a stable tile of shape 0 that takes only the packed path:
+// the 32-bit composite layout of the wide merge levels, or the staged float
+// bits and payloads, whichever is larger.
+template <int DT, int K>
+constexpr size_t packed_lds_bytes() {
+    constexpr int kTile = TileTraits<DT, K, true, 0>::kTile;
+    constexpr int KPL = TileTraits<DT, K, true, 0>::kKPL;
+    constexpr size_t sort = (size_t)block_lds_words2<uint32_t, KPL, 2 * KPL>(kTile) * 4;
+    constexpr size_t stage = (size_t)kTile * 4 * (DT == kF32 ? 2 : 1);
+    return sort > stage ? sort : stage;
 }
 
 }  // namespace msn

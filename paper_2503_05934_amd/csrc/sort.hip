@@ -32,6 +32,60 @@ __global__ __launch_bounds__((TileTraits<DT, K, STABLE, SHAPE>::kThreads),
                                              Samples{samp_first, samp_last, base});
 }
 
+// Stable integer first sweep in two launches.  Most tiles pack (every key
+// below 2^(32 - kPackPosBits), 32-bit composites): k_block_sort_packed sorts
+// those with the LDS of the packed path only, so that three workgroups share
+// a compute unit instead of the two that the 64-bit path's LDS allows, and
+// flags every other tile; k_block_sort_wide then sorts the flagged tiles
+// with 64-bit composites, each workgroup scanning 64 flags at a time (when
+// every tile packed, it reads the flags and returns).
+template <int DT, int K, int VM, int NETS>
+__global__ __launch_bounds__(kBlockThreads, 6) void k_block_sort_packed(
+    const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, int64_t n,
+    uint32_t* samp_first, uint32_t* samp_last, int* sorted_flag, int* wide_flag) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *sorted_flag = 1;
+    __shared__ __align__(16) unsigned char smem[packed_lds_bytes<DT, K>()];
+    constexpr int kTile = TileTraits<DT, K, true, 0>::kTile;
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    const int nv = (int)((n - base) < kTile ? (n - base) : kTile);
+    const bool sorted = block_sort_tile<DT, K, true, VM, 0, false, kPackOnly, NETS>(
+        kin + base, VM == kVals ? vin + base : nullptr, kout + base,
+        VM != kNoVals ? vout + base : nullptr, nv, (uint32_t)base, smem,
+        Samples{samp_first, samp_last, base});
+    if (threadIdx.x == 0) wide_flag[blockIdx.x] = sorted ? 0 : 1;
+}
+
+template <int DT, int K, int VM, int NETS>
+__global__ __launch_bounds__(kBlockThreads, (TileTraits<DT, K, true, 0>::kWavesPerSimd)) void
+k_block_sort_wide(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
+                  int64_t n, uint32_t* samp_first, uint32_t* samp_last,
+                  const int* __restrict__ wide_flag, int64_t tiles) {
+    __shared__ __align__(16) unsigned char smem[TileTraits<DT, K, true, 0>::kLdsBytes];
+    __shared__ unsigned long long s_mask;
+    constexpr int kTile = TileTraits<DT, K, true, 0>::kTile;
+    for (int64_t b0 = (int64_t)blockIdx.x * kWave; b0 < tiles; b0 += (int64_t)gridDim.x * kWave) {
+        if (threadIdx.x < kWave) {
+            const int64_t t = b0 + threadIdx.x;
+            const unsigned long long m = __ballot(t < tiles && wide_flag[t] != 0);
+            if (threadIdx.x == 0) s_mask = m;
+        }
+        __syncthreads();
+        unsigned long long m = s_mask;
+        __syncthreads();  // s_mask is written again for the next 64 flags
+        while (m != 0ull) {
+            const int j = __builtin_ctzll(m);
+            m &= m - 1ull;
+            const int64_t base = (b0 + j) * kTile;
+            const int nv = (int)((n - base) < kTile ? (n - base) : kTile);
+            block_sort_tile<DT, K, true, VM, 0, false, kPackNone, NETS>(
+                kin + base, VM == kVals ? vin + base : nullptr, kout + base,
+                VM != kNoVals ? vout + base : nullptr, nv, (uint32_t)base, smem,
+                Samples{samp_first, samp_last, base});
+            __syncthreads();  // the LDS is reused for the next flagged tile
+        }
+    }
+}
+
 // ------------------------------------------------------- merge-path split ---
 // For merge tile t of a pass that merges runs of length L: the number of
 // elements of the pair's left run among the tile's first output position.
@@ -324,13 +378,48 @@ inline int block_shape(const SortArgs& a) {
     return ratio >= 4 ? 2 : ratio == 2 ? 1 : 0;
 }
 
+// The two-launch stable first sweep (k_block_sort_packed, k_block_sort_wide);
+// wide: one flag per tile.
+template <int DT, int K, int VM, int NETS>
+int launch_block_sort_packed(const SortArgs& a, uint32_t* kdst, uint32_t* vdst,
+                             const Samples& sm, int* sorted_flag, int* wide) {
+    using Tr = TileTraits<DT, K, true, 0>;
+    const int64_t tiles = (a.n + Tr::kTile - 1) / Tr::kTile;
+    {
+        LaunchTimer timer("block_sort", a.n, a.stream);
+        hipLaunchKernelGGL((k_block_sort_packed<DT, K, VM, NETS>), dim3((unsigned)tiles),
+                           dim3(kBlockThreads), 0, a.stream, a.kin, a.vin, kdst, vdst, a.n,
+                           sm.first, sm.last, sorted_flag, wide);
+    }
+    if (int rc = (int)hipGetLastError()) return rc;
+    auto wkern = &k_block_sort_wide<DT, K, VM, NETS>;
+    int grid = 0;
+    if (int rc = resident_grid(reinterpret_cast<const void*>(wkern), kBlockThreads, 0, &grid))
+        return rc;
+    grid = (int)std::max<int64_t>(1, std::min<int64_t>(grid, (tiles + kWave - 1) / kWave));
+    {
+        LaunchTimer timer("block_sort_wide", a.n, a.stream);
+        hipLaunchKernelGGL(wkern, dim3((unsigned)grid), dim3(kBlockThreads), 0, a.stream, a.kin,
+                           a.vin, kdst, vdst, a.n, sm.first, sm.last, wide, tiles);
+    }
+    return (int)hipGetLastError();
+}
+
 template <int DT, int K, int NETS>
 int dispatch_block_sort(const SortArgs& a, uint32_t* kdst, uint32_t* vdst,
-                        const Samples& sm, int* fl) {
-    if (a.vmode == kVals)
+                        const Samples& sm, int* fl, int* wide) {
+    // stable integer sorts with 8-key groups pack their tiles when they can
+    constexpr bool kPacks = DT != kF32 && K == 8 && NETS != kNetNone;
+    if (a.vmode == kVals) {
+        if constexpr (kPacks)
+            return launch_block_sort_packed<DT, K, kVals, NETS>(a, kdst, vdst, sm, fl, wide);
         return launch_block_sort<DT, K, true, kVals, 0, NETS>(a, kdst, vdst, sm, fl);
-    if (a.vmode == kArg)
+    }
+    if (a.vmode == kArg) {
+        if constexpr (kPacks)
+            return launch_block_sort_packed<DT, K, kArg, NETS>(a, kdst, vdst, sm, fl, wide);
         return launch_block_sort<DT, K, true, kArg, 0, NETS>(a, kdst, vdst, sm, fl);
+    }
     if constexpr (DT == kF32) {
         return launch_block_sort<DT, K, true, kNoVals, 0, NETS>(a, kdst, vdst, sm, fl);
     } else {
@@ -485,14 +574,19 @@ int run_sort(const SortArgs& a) {
 
     int cur = passes & 1;
     int rc = 0;
+    // the merge-path split table (one word per 2048 keys) is free during the
+    // first sweep: it holds the per-tile flags of the stable packed sweep
+    int* wide = part;
     if (a.nets == kNetNone)
-        rc = dispatch_block_sort<DT, 8, kNetNone>(a, kb[cur], vb[cur], sm, sorted_flag);
+        rc = dispatch_block_sort<DT, 8, kNetNone>(a, kb[cur], vb[cur], sm, sorted_flag, wide);
     else if (a.nets == kNetSplit)
-        rc = a.leaf_k == 8 ? dispatch_block_sort<DT, 8, kNetSplit>(a, kb[cur], vb[cur], sm, sorted_flag)
-                           : dispatch_block_sort<DT, 4, kNetSplit>(a, kb[cur], vb[cur], sm, sorted_flag);
+        rc = a.leaf_k == 8
+                 ? dispatch_block_sort<DT, 8, kNetSplit>(a, kb[cur], vb[cur], sm, sorted_flag, wide)
+                 : dispatch_block_sort<DT, 4, kNetSplit>(a, kb[cur], vb[cur], sm, sorted_flag, wide);
     else
-        rc = a.leaf_k == 8 ? dispatch_block_sort<DT, 8, kNetPlain>(a, kb[cur], vb[cur], sm, sorted_flag)
-                           : dispatch_block_sort<DT, 4, kNetPlain>(a, kb[cur], vb[cur], sm, sorted_flag);
+        rc = a.leaf_k == 8
+                 ? dispatch_block_sort<DT, 8, kNetPlain>(a, kb[cur], vb[cur], sm, sorted_flag, wide)
+                 : dispatch_block_sort<DT, 4, kNetPlain>(a, kb[cur], vb[cur], sm, sorted_flag, wide);
     if (rc) return rc;
     if (passes > 0) {
         const int64_t runs = (a.n + tile - 1) / tile;

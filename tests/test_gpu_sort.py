@@ -430,6 +430,34 @@ def test_packed_composite_edges(orc):
         assert np.array_equal(host(po).view(np.uint32), rp), dtype
 
 
+def test_packed_and_wide_tiles_across_flag_windows(orc):
+    # The stable first sweep sorts packable tiles in one launch and flags the
+    # others for a second, which scans the flags 64 tiles at a time: wide
+    # tiles at both ends of a window, in later windows, and the ragged last
+    # tile; argsort (positions as payload) takes the same two launches.
+    tile = 8192
+    rng = np.random.default_rng(91)
+    ntiles = 150
+    n = (ntiles - 1) * tile + 77
+    k = rng.integers(0, 1 << 16, n, dtype=np.uint32)
+    for t in (0, 63, 64, 100, 127, 128, ntiles - 1):
+        lo = t * tile
+        k[lo + (rng.integers(0, min(tile, n - lo)))] = np.uint32(rng.integers(1 << 19, 2**32))
+    v = rng.integers(0, 2**32, n, dtype=np.uint32)
+    say(f"packed and wide tiles: n={n}")
+    rk, rv = orc.sort(k, vals=v, dtype="u32", stable=True)
+    ko, vo = msn.sort_pairs(gpu(k), gpu(v))
+    assert np.array_equal(host(ko), rk) and np.array_equal(host(vo), rv)
+    _, po = msn.sort_pairs(gpu(k))
+    _, rp = orc.sort(k, dtype="u32", stable=True, want_perm=True)
+    assert np.array_equal(host(po).view(np.uint32), rp)
+    # every tile wide, and every tile packed
+    for kk in (rng.integers(0, 2**32, n, dtype=np.uint32), k & np.uint32(0xffff)):
+        rk, rv = orc.sort(kk, vals=v, dtype="u32", stable=True)
+        ko, vo = msn.sort_pairs(gpu(kk), gpu(v))
+        assert np.array_equal(host(ko), rk) and np.array_equal(host(vo), rv)
+
+
 def _cpu_corank(a, b, d):
     """Elements of a among the first d outputs of the stable merge of a and b
     (a first on equal keys): the merge itself, step by step."""
