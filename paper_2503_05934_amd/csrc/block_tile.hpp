@@ -30,9 +30,12 @@ struct TileTraits {
     // keys-only tiles of 16 keys per lane can merge in LDS at 32 outputs per
     // thread (block_sort_regs2); LDS is sized for either layout
     static constexpr bool kWideOk = !STABLE && kKPL == 16;
+    // stable tiles of shape 3 always merge in LDS at 2K outputs per thread:
+    // half the co-rank searches of the 64-bit composites
+    static constexpr bool kMerge2 = STABLE && SHAPE == 3;
     static constexpr size_t kLdsBytes =
-        (size_t)(kWideOk && block_lds_words2<T, kKPL, 2 * kKPL>(kTile) >
-                                block_lds_words<T, kKPL>(kTile)
+        (size_t)((kWideOk || kMerge2) && block_lds_words2<T, kKPL, 2 * kKPL>(kTile) >
+                                              block_lds_words<T, kKPL>(kTile)
                      ? block_lds_words2<T, kKPL, 2 * kKPL>(kTile)
                      : block_lds_words<T, kKPL>(kTile)) * sizeof(T);
     static_assert(!STABLE || kLdsBytes >= (size_t)2 * kTile * 4, "staging must fit");
@@ -69,6 +72,57 @@ __device__ __forceinline__ void write_samples(const Samples& samp, int first, in
     if ((p & (kSampleChunk - 1)) == 0 && first < nv) samp.first[p / kSampleChunk] = x[0];
     if (((p + N - 1) & (kSampleChunk - 1)) == kSampleChunk - 1 && first + N - 1 < nv)
         samp.last[(p + N - 1) / kSampleChunk] = x[N - 1];
+}
+
+// Stable tiles: copies what the outputs gather by tile position into LDS
+// (the float bits of the keys, the payloads).  Call between barriers.
+template <int DT, int VM, int THREADS>
+__device__ __forceinline__ void stage_stable(const uint32_t* kin, const uint32_t* vin, int nv,
+                                             uint32_t* sbits, uint32_t* svals) {
+    if constexpr (DT == kF32 || VM == kVals) {
+        for (int i = threadIdx.x; i < nv; i += THREADS) {
+            if constexpr (DT == kF32) sbits[i] = kin[i];
+            if constexpr (VM == kVals) svals[i] = vin[i];
+        }
+    }
+}
+
+// Stable tiles: writes N sorted outputs at tile positions first.., output j
+// holding ordered key ok[j] from tile position t[j].  Float keys are copied
+// bit for bit from the staged input, payloads gathered from the staged values
+// (kVals) or generated (kArg: val_base + position).
+template <int DT, int VM, int N>
+__device__ __forceinline__ void emit_stable(const uint32_t (&t)[N], const uint32_t (&ok)[N],
+                                            int first, int nv, const uint32_t* sbits,
+                                            const uint32_t* svals, uint32_t* kout,
+                                            uint32_t* vout, uint32_t val_base,
+                                            const Samples& samp) {
+    uint32_t kx[N], vy[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        const uint32_t tj = first + j < nv ? t[j] : 0u;
+        if constexpr (DT == kF32) kx[j] = sbits[tj];
+        else kx[j] = unord_key<DT>(ok[j]);
+        if constexpr (VM == kVals) vy[j] = svals[tj];
+        else vy[j] = val_base + tj;
+    }
+    write_samples(samp, first, nv, kx);
+    if (first + N <= nv) {
+#pragma unroll
+        for (int q = 0; q < N / 4; ++q) {
+            st4(kout + first + 4 * q, kx[4 * q], kx[4 * q + 1], kx[4 * q + 2], kx[4 * q + 3]);
+            if constexpr (VM != kNoVals)
+                st4(vout + first + 4 * q, vy[4 * q], vy[4 * q + 1], vy[4 * q + 2],
+                    vy[4 * q + 3]);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < N; ++j)
+            if (first + j < nv) {
+                kout[first + j] = kx[j];
+                if constexpr (VM != kNoVals) vout[first + j] = vy[j];
+            }
+    }
 }
 
 // WIDE (keys-only tiles of 16 keys per lane): LDS merge levels at 32 outputs
@@ -166,7 +220,6 @@ __device__ __forceinline__ bool block_sort_tile(const uint32_t* kin, const uint3
         }
     } else {
         constexpr bool kNeedBits = DT == kF32;
-        constexpr bool kNeedVals = VM == kVals;
         uint32_t* sbits = reinterpret_cast<uint32_t*>(smem);
         uint32_t* svals = kNeedBits ? sbits + Tr::kTile : sbits;
         if constexpr (PACK && DT != kF32 && KPL == 16 && Tr::kTile <= (1 << kPackPosBits)) {
@@ -187,47 +240,43 @@ __device__ __forceinline__ bool block_sort_tile(const uint32_t* kin, const uint3
                                : 0xffffffffu;
                 block_sort_regs2<uint32_t, K, KPL, MK, NETS>(w, o, reinterpret_cast<uint32_t*>(smem),
                                                        span);
-                if constexpr (kNeedBits || kNeedVals) {
-                    for (int i = tid; i < nv; i += Tr::kThreads) {
-                        if constexpr (kNeedBits) sbits[i] = kin[i];
-                        if constexpr (kNeedVals) svals[i] = vin[i];
-                    }
-                }
+                stage_stable<DT, VM, Tr::kThreads>(kin, vin, nv, sbits, svals);
                 __syncthreads();
                 const int first2 = tid * MK;
                 if (first2 < span) {
-                    uint32_t kx[MK], vy[MK];
+                    uint32_t t[MK], ok[MK];
 #pragma unroll
                     for (int j = 0; j < MK; ++j) {
-                        const uint32_t t =
-                            first2 + j < nv ? (o[j] & ((1u << kPackPosBits) - 1u)) : 0u;
-                        if constexpr (kNeedBits) kx[j] = sbits[t];
-                        else kx[j] = unord_key<DT>(o[j] >> kPackPosBits);
-                        if constexpr (VM == kVals) vy[j] = svals[t];
-                        else vy[j] = val_base + t;
+                        t[j] = o[j] & ((1u << kPackPosBits) - 1u);
+                        ok[j] = o[j] >> kPackPosBits;
                     }
-                    write_samples(samp, first2, nv, kx);
-                    if (first2 + MK <= nv) {
-#pragma unroll
-                        for (int q = 0; q < MK / 4; ++q) {
-                            st4(kout + first2 + 4 * q, kx[4 * q], kx[4 * q + 1], kx[4 * q + 2],
-                                kx[4 * q + 3]);
-                            if constexpr (VM != kNoVals)
-                                st4(vout + first2 + 4 * q, vy[4 * q], vy[4 * q + 1],
-                                    vy[4 * q + 2], vy[4 * q + 3]);
-                        }
-                    } else {
-#pragma unroll
-                        for (int j = 0; j < MK; ++j)
-                            if (first2 + j < nv) {
-                                kout[first2 + j] = kx[j];
-                                if constexpr (VM != kNoVals) vout[first2 + j] = vy[j];
-                            }
-                    }
+                    emit_stable<DT, VM, MK>(t, ok, first2, nv, sbits, svals, kout, vout,
+                                            val_base, samp);
                 }
                 return true;
             }
             if constexpr (PACK == kPackOnly) return false;
+        }
+        if constexpr (Tr::kMerge2 && NETS != kNetNone) {
+            // LDS merge levels at MK = 2 KPL outputs per thread (the first
+            // half of the threads), which then write them
+            constexpr int MK = 2 * KPL;
+            T o[MK];
+            block_sort_regs2<T, K, KPL, MK, NETS>(v, o, s, span);
+            stage_stable<DT, VM, Tr::kThreads>(kin, vin, nv, sbits, svals);
+            __syncthreads();
+            const int first2 = tid * MK;
+            if (first2 < span) {
+                uint32_t t[MK], ok[MK];
+#pragma unroll
+                for (int j = 0; j < MK; ++j) {
+                    t[j] = comp_pos(o[j]);
+                    ok[j] = comp_ord(o[j]);
+                }
+                emit_stable<DT, VM, MK>(t, ok, first2, nv, sbits, svals, kout, vout, val_base,
+                                        samp);
+            }
+            return true;
         }
         if constexpr (NETS != kNetNone)
             block_sort_regs<T, K, KPL, NETS>(v, s, span);
@@ -235,42 +284,15 @@ __device__ __forceinline__ bool block_sort_tile(const uint32_t* kin, const uint3
             block_merge_only<T, KPL>(v, s, span);
         // Stage what must be gathered by position (float bits, payload).
         __syncthreads();
-        if constexpr (kNeedBits || kNeedVals) {
-            for (int i = tid; i < nv; i += Tr::kThreads) {
-                if constexpr (kNeedBits) sbits[i] = kin[i];
-                if constexpr (kNeedVals) svals[i] = vin[i];
-            }
-        }
+        stage_stable<DT, VM, Tr::kThreads>(kin, vin, nv, sbits, svals);
         __syncthreads();
-        uint32_t y[KPL];
+        uint32_t t[KPL], ok[KPL];
 #pragma unroll
         for (int j = 0; j < KPL; ++j) {
-            const uint32_t tag = comp_pos(v[j]);
-            const bool live = first + j < nv;
-            const uint32_t t = live ? tag : 0u;
-            if constexpr (kNeedBits) x[j] = sbits[t];
-            else x[j] = unord_key<DT>(comp_ord(v[j]));
-            if constexpr (VM == kVals) y[j] = svals[t];
-            else y[j] = val_base + t;
+            t[j] = comp_pos(v[j]);
+            ok[j] = comp_ord(v[j]);
         }
-        write_samples(samp, first, nv, x);
-        if (first + KPL <= nv) {
-#pragma unroll
-            for (int q = 0; q < KPL / 4; ++q) {
-                st4(kout + first + 4 * q, x[4 * q], x[4 * q + 1], x[4 * q + 2],
-                    x[4 * q + 3]);
-                if constexpr (VM != kNoVals)
-                    st4(vout + first + 4 * q, y[4 * q], y[4 * q + 1], y[4 * q + 2],
-                    y[4 * q + 3]);
-            }
-        } else {
-#pragma unroll
-            for (int j = 0; j < KPL; ++j)
-                if (first + j < nv) {
-                    kout[first + j] = x[j];
-                    if constexpr (VM != kNoVals) vout[first + j] = y[j];
-                }
-        }
+        emit_stable<DT, VM, KPL>(t, ok, first, nv, sbits, svals, kout, vout, val_base, samp);
     }
     return true;
 }

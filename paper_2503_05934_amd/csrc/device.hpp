@@ -408,6 +408,31 @@ __device__ __forceinline__ int corank_lds(const T* s, int a0, int la, int b0, in
     return lo;
 }
 
+// corank_lds with PlainLess for two runs of L keys each (L a power of two)
+// laid out so that LDS words [a0, b0 + L) all belong to the pair: A at a0, B
+// at b0 >= a0 + L.  Binary
+// lifting with the steps L, L/2, ..., 1, the same for every lane: m is the
+// last position of A known to go before B[d-1-m]; a step is taken when its
+// new last position is still inside A's share of the diagonal and goes
+// first.  A probe beyond that share stays inside the pair's words (at most L
+// past the share on either side) and its result is discarded.  Nine VALU
+// instructions per step and no exit test.
+template <typename T>
+__device__ __forceinline__ int corank_pow2(const T* s, int a0, int b0, int L, int d) {
+    const int lo = d > L ? d - L : 0;
+    const int hi = d < L ? d : L;
+    const uint32_t lim = (uint32_t)(a0 + hi);
+    const uint32_t c = (uint32_t)(b0 + d - 1 + a0);  // B[d-1-(t-a0)] sits at c - t
+    uint32_t m = (uint32_t)(a0 + lo) - 1u;
+    for (int step = L; step > 0; step >>= 1) {
+        const uint32_t t = m + (uint32_t)step;
+        const T av = lds_load(s, t);
+        const T bv = lds_load(s, c - t);
+        if (t < lim && !(bv < av)) m = t;
+    }
+    return (int)(m + 1u) - a0;
+}
+
 // Sequential stable merge of N outputs starting at A[i], B[j] (LDS runs
 // [a0, a0+la) and [b0, b0+lb)).  One LDS read per output; reads past a run's
 // end are clamped to `limit` and their values ignored.  src[k] receives the
@@ -581,7 +606,7 @@ __device__ __forceinline__ void block_sort_regs(T (&v)[KPL], T* s, int span) {
             const int a0 = ra * (L + KPL);
             const int b0 = a0 + L + KPL;
             const int d = e - ra * L;
-            const int i = corank_lds(s, a0, L, b0, L, d, PlainLess{});
+            const int i = corank_pow2(s, a0, b0, L, d);
             serial_merge_closed<T, KPL>(s, a0 + i, b0 + d - i, v);
         }
         __syncthreads();
@@ -632,7 +657,7 @@ __device__ __forceinline__ void block_merge_only(T (&v)[KPL], T* s, int span) {
         if (active) {
             const int a0 = e & ~(2 * L - 1);
             const int d = e - a0;
-            const int i = corank_lds(s, a0, L, a0 + L, L, d, PlainLess{});
+            const int i = corank_pow2(s, a0, a0 + L, L, d);
             int src[KPL];
             serial_merge<T, KPL, false>(s, a0, L, a0 + L, L, i, d - i, span - 1, v, src,
                                         PlainLess{});
@@ -689,7 +714,7 @@ __device__ __forceinline__ void block_sort_regs2(T (&v)[KPL], T (&o)[MK], T* s, 
             const int a0 = ra * (L + MK);
             const int b0 = a0 + L + MK;
             const int d = e - ra * L;
-            const int i = corank_lds(s, a0, L, b0, L, d, PlainLess{});
+            const int i = corank_pow2(s, a0, b0, L, d);
             serial_merge_closed<T, MK>(s, a0 + i, b0 + d - i, o);
         }
         L <<= 1;
