@@ -182,7 +182,7 @@ __device__ __forceinline__ bool block_sort_tile(const uint32_t* kin, const uint3
     if constexpr (WIDE && Tr::kWideOk) {
         constexpr int MK = 2 * KPL;
         T o[MK];
-        block_sort_regs2<T, K, KPL, MK, NETS>(v, o, s, span);
+        block_sort_regs2<T, K, KPL, MK, NETS>(v, o, s, span, nv);
         const int first2 = tid * MK;
         if (first2 < span) {
             uint32_t y[MK];
@@ -202,7 +202,7 @@ __device__ __forceinline__ bool block_sort_tile(const uint32_t* kin, const uint3
         }
     } else if constexpr (!STABLE) {
         if constexpr (NETS != kNetNone)
-            block_sort_regs<T, K, KPL, NETS>(v, s, span);
+            block_sort_regs<T, K, KPL, NETS>(v, s, span, nv);
         else
             block_merge_only<T, KPL>(v, s, span);
 #pragma unroll
@@ -239,7 +239,7 @@ __device__ __forceinline__ bool block_sort_tile(const uint32_t* kin, const uint3
                                ? (ord_key<DT>(x[j]) << kPackPosBits) | (uint32_t)(first + j)
                                : 0xffffffffu;
                 block_sort_regs2<uint32_t, K, KPL, MK, NETS>(w, o, reinterpret_cast<uint32_t*>(smem),
-                                                       span);
+                                                       span, nv);
                 stage_stable<DT, VM, Tr::kThreads>(kin, vin, nv, sbits, svals);
                 __syncthreads();
                 const int first2 = tid * MK;
@@ -262,7 +262,7 @@ __device__ __forceinline__ bool block_sort_tile(const uint32_t* kin, const uint3
             // half of the threads), which then write them
             constexpr int MK = 2 * KPL;
             T o[MK];
-            block_sort_regs2<T, K, KPL, MK, NETS>(v, o, s, span);
+            block_sort_regs2<T, K, KPL, MK, NETS>(v, o, s, span, nv);
             stage_stable<DT, VM, Tr::kThreads>(kin, vin, nv, sbits, svals);
             __syncthreads();
             const int first2 = tid * MK;
@@ -279,7 +279,7 @@ __device__ __forceinline__ bool block_sort_tile(const uint32_t* kin, const uint3
             return true;
         }
         if constexpr (NETS != kNetNone)
-            block_sort_regs<T, K, KPL, NETS>(v, s, span);
+            block_sort_regs<T, K, KPL, NETS>(v, s, span, nv);
         else
             block_merge_only<T, KPL>(v, s, span);
         // Stage what must be gathered by position (float bits, payload).

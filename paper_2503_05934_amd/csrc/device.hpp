@@ -576,14 +576,16 @@ __host__ __device__ constexpr int block_lds_words(int n) {
 // merges them; the wavefront merges its 64 lane runs by bitonic exchanges;
 // then LDS merge-path levels double the run length up to `span` (a power of
 // two, at least 64*KPL): lanes beyond it still take part in barriers but skip
-// the work.  On return thread t holds outputs t*KPL .. t*KPL+KPL-1 of the
-// sorted span.  s is LDS of block_lds_words<T, KPL>(tile keys) words.
+// the work.  Keys from position nv on are padding (the largest value): a
+// wavefront holding only padding is sorted already and skips the networks
+// and its merge.  On return thread t holds outputs t*KPL .. t*KPL+KPL-1 of
+// the sorted span.  s is LDS of block_lds_words<T, KPL>(tile keys) words.
 template <typename T, int K, int KPL, int NET = kNetPlain>
-__device__ __forceinline__ void block_sort_regs(T (&v)[KPL], T* s, int span) {
+__device__ __forceinline__ void block_sort_regs(T (&v)[KPL], T* s, int span, int nv) {
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const bool active = tid * KPL < span;
-    if (active) {
+    if (active && __builtin_amdgcn_readfirstlane((tid - lane) * KPL) < nv) {
         lane_sort<T, K, KPL, NET>(v);
         wave_merge<T, KPL>(v, lane);
     }
@@ -677,14 +679,17 @@ __host__ __device__ constexpr int block_lds_words2(int n) {
 // return thread t < threads/2 holds outputs t*MK .. t*MK+MK-1 of the sorted
 // span in o[].  s is LDS of block_lds_words2<T, KPL, MK>(tile keys) words.
 template <typename T, int K, int KPL, int MK, int NET = kNetPlain>
-__device__ __forceinline__ void block_sort_regs2(T (&v)[KPL], T (&o)[MK], T* s, int span) {
+__device__ __forceinline__ void block_sort_regs2(T (&v)[KPL], T (&o)[MK], T* s, int span,
+                                                 int nv) {
     static_assert(MK == 2 * KPL, "two lanes' keys per merger");
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     int L = kWave * KPL;  // wavefront runs
     if (tid * KPL < span) {
-        lane_sort<T, K, KPL, NET>(v);
-        wave_merge<T, KPL>(v, lane);
+        if (__builtin_amdgcn_readfirstlane((tid - lane) * KPL) < nv) {
+            lane_sort<T, K, KPL, NET>(v);
+            wave_merge<T, KPL>(v, lane);
+        }
         // run r occupies [r*(L+MK), r*(L+MK)+L), then MK sentinels
         const int e = tid * KPL;
         const int run = e / L;
