@@ -30,12 +30,9 @@ struct TileTraits {
     // keys-only tiles of 16 keys per lane can merge in LDS at 32 outputs per
     // thread (block_sort_regs2); LDS is sized for either layout
     static constexpr bool kWideOk = !STABLE && kKPL == 16;
-    // stable tiles of shape 3 always merge in LDS at 2K outputs per thread:
-    // half the co-rank searches of the 64-bit composites
-    static constexpr bool kMerge2 = STABLE && SHAPE == 3;
     static constexpr size_t kLdsBytes =
-        (size_t)((kWideOk || kMerge2) && block_lds_words2<T, kKPL, 2 * kKPL>(kTile) >
-                                              block_lds_words<T, kKPL>(kTile)
+        (size_t)(kWideOk && block_lds_words2<T, kKPL, 2 * kKPL>(kTile) >
+                                block_lds_words<T, kKPL>(kTile)
                      ? block_lds_words2<T, kKPL, 2 * kKPL>(kTile)
                      : block_lds_words<T, kKPL>(kTile)) * sizeof(T);
     static_assert(!STABLE || kLdsBytes >= (size_t)2 * kTile * 4, "staging must fit");
@@ -256,27 +253,6 @@ __device__ __forceinline__ bool block_sort_tile(const uint32_t* kin, const uint3
                 return true;
             }
             if constexpr (PACK == kPackOnly) return false;
-        }
-        if constexpr (Tr::kMerge2 && NETS != kNetNone) {
-            // LDS merge levels at MK = 2 KPL outputs per thread (the first
-            // half of the threads), which then write them
-            constexpr int MK = 2 * KPL;
-            T o[MK];
-            block_sort_regs2<T, K, KPL, MK, NETS>(v, o, s, span, nv);
-            stage_stable<DT, VM, Tr::kThreads>(kin, vin, nv, sbits, svals);
-            __syncthreads();
-            const int first2 = tid * MK;
-            if (first2 < span) {
-                uint32_t t[MK], ok[MK];
-#pragma unroll
-                for (int j = 0; j < MK; ++j) {
-                    t[j] = comp_pos(o[j]);
-                    ok[j] = comp_ord(o[j]);
-                }
-                emit_stable<DT, VM, MK>(t, ok, first2, nv, sbits, svals, kout, vout, val_base,
-                                        samp);
-            }
-            return true;
         }
         if constexpr (NETS != kNetNone)
             block_sort_regs<T, K, KPL, NETS>(v, s, span, nv);
