@@ -130,10 +130,69 @@ __device__ __forceinline__ uint64_t kmax(uint64_t a, uint64_t b) {
 __device__ __forceinline__ uint32_t keep(uint32_t mine, uint32_t theirs, uint32_t upper) {
     return kmax(kmin(mine, theirs), kmin(kmax(mine, theirs), upper));
 }
-__device__ __forceinline__ uint64_t keep(uint64_t mine, uint64_t theirs, uint32_t upper) {
-    // one 64-bit compare: the lower lane keeps mine when it is the smaller,
-    // the upper lane when it is not
-    return ((mine < theirs) != (upper != 0u)) ? mine : theirs;
+// Half of a compare-exchange between lanes for four 64-bit composites at
+// once, where lane bit BIT selects the upper lanes: the lower lanes take the
+// double minima and the upper lanes the double maxima, each under its own
+// execution mask (eight VALU and four scalar instructions for four keys;
+// keep() would take a compare and two selects per key).  The mask is
+// restored before the block ends, and the closing s_nop covers the two wait
+// states a DPP move that reads a result next needs.
+template <int BIT>
+__device__ __forceinline__ void keep_lanes4(uint64_t (&v)[4], const uint64_t (&o)[4]) {
+    static_assert(BIT >= 0 && BIT < 6, "lane bit");
+    constexpr uint64_t kUpper = BIT == 0   ? 0xAAAAAAAAAAAAAAAAull
+                                : BIT == 1 ? 0xCCCCCCCCCCCCCCCCull
+                                : BIT == 2 ? 0xF0F0F0F0F0F0F0F0ull
+                                : BIT == 3 ? 0xFF00FF00FF00FF00ull
+                                : BIT == 4 ? 0xFFFF0000FFFF0000ull
+                                           : 0xFFFFFFFF00000000ull;
+    double r0, r1, r2, r3;
+    uint64_t save;
+    asm("s_mov_b64 %4, exec\n\t"
+        "s_andn2_b64 exec, %4, %13\n\t"
+        "v_min_f64 %0, %5, %9\n\t"
+        "v_min_f64 %1, %6, %10\n\t"
+        "v_min_f64 %2, %7, %11\n\t"
+        "v_min_f64 %3, %8, %12\n\t"
+        "s_and_b64 exec, %4, %13\n\t"
+        "v_max_f64 %0, %5, %9\n\t"
+        "v_max_f64 %1, %6, %10\n\t"
+        "v_max_f64 %2, %7, %11\n\t"
+        "v_max_f64 %3, %8, %12\n\t"
+        "s_mov_b64 exec, %4\n\t"
+        "s_nop 1"
+        : "=&v"(r0), "=&v"(r1), "=&v"(r2), "=&v"(r3), "=&s"(save)
+        : "v"(__builtin_bit_cast(double, v[0])), "v"(__builtin_bit_cast(double, v[1])),
+          "v"(__builtin_bit_cast(double, v[2])), "v"(__builtin_bit_cast(double, v[3])),
+          "v"(__builtin_bit_cast(double, o[0])), "v"(__builtin_bit_cast(double, o[1])),
+          "v"(__builtin_bit_cast(double, o[2])), "v"(__builtin_bit_cast(double, o[3])),
+          "s"(kUpper)
+        : "scc");
+    v[0] = __builtin_bit_cast(uint64_t, r0);
+    v[1] = __builtin_bit_cast(uint64_t, r1);
+    v[2] = __builtin_bit_cast(uint64_t, r2);
+    v[3] = __builtin_bit_cast(uint64_t, r3);
+}
+
+// keep() on K keys against their partners o[] for the upper lanes of lane
+// bit BIT (upper: their all-ones mask).
+template <int BIT, int K>
+__device__ __forceinline__ void keep_all(uint32_t (&v)[K], const uint32_t (&o)[K],
+                                         uint32_t upper) {
+#pragma unroll
+    for (int j = 0; j < K; ++j) v[j] = keep(v[j], o[j], upper);
+}
+template <int BIT, int K>
+__device__ __forceinline__ void keep_all(uint64_t (&v)[K], const uint64_t (&o)[K], uint32_t) {
+    static_assert(K % 4 == 0, "groups of four keys");
+#pragma unroll
+    for (int g = 0; g < K; g += 4) {
+        uint64_t a[4] = {v[g], v[g + 1], v[g + 2], v[g + 3]};
+        const uint64_t b[4] = {o[g], o[g + 1], o[g + 2], o[g + 3]};
+        keep_lanes4<BIT>(a, b);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[g + j] = a[j];
+    }
 }
 
 // floor(log2(x)) for x >= 1.
@@ -310,35 +369,34 @@ __device__ __forceinline__ uint64_t xor_lane(uint64_t x) {
 //           l ^ (2G-1), slot j meets slot K-1-j; the lower key keeps the min.
 //   clean : distance d = GK/2, ..., 1: key e meets e + d; for d >= K that is
 //           lane l ^ (d/K) in the same slot, below K it is inside the lane.
+// Cross-lane half-cleaner at lane distance M, then the next one down.
+template <typename T, int K, int M>
+__device__ __forceinline__ void wave_cross_stages(T (&v)[K], int lane) {
+    if constexpr (M >= 1) {
+        const uint32_t upper = lane_bit_mask(lane, ilog2(M));
+        if constexpr (sizeof(T) == 4) {
+#pragma unroll
+            for (int j = 0; j < K; ++j) v[j] = keep(v[j], xor_lane<M>(v[j]), upper);
+        } else {
+            T o[K];
+#pragma unroll
+            for (int j = 0; j < K; ++j) o[j] = xor_lane<M>(v[j]);
+            keep_all<ilog2(M), K>(v, o, upper);
+        }
+        wave_cross_stages<T, K, M / 2>(v, lane);
+    }
+}
+
 template <typename T, int K, int G>
 __device__ __forceinline__ void wave_merge_level(T (&v)[K], int lane) {
     {
         T o[K];
 #pragma unroll
         for (int j = 0; j < K; ++j) o[j] = xor_lane<2 * G - 1>(v[K - 1 - j]);
-        const uint32_t upper = lane_bit_mask(lane, ilog2(G));
-#pragma unroll
-        for (int j = 0; j < K; ++j) v[j] = keep(v[j], o[j], upper);
+        keep_all<ilog2(G), K>(v, o, lane_bit_mask(lane, ilog2(G)));
     }
-    if constexpr (G >= 2) {
-        // cross-lane half-cleaners, lane distance G/2 ... 1
-#pragma unroll
-        for (int m = G / 2; m >= 1; m >>= 1) {
-            const uint32_t upper = lane_bit_mask(lane, ilog2(m));
-#pragma unroll
-            for (int j = 0; j < K; ++j) {
-                T o;
-                switch (m) {
-                    case 1: o = xor_lane<1>(v[j]); break;
-                    case 2: o = xor_lane<2>(v[j]); break;
-                    case 4: o = xor_lane<4>(v[j]); break;
-                    case 8: o = xor_lane<8>(v[j]); break;
-                    default: o = xor_lane<16>(v[j]); break;
-                }
-                v[j] = keep(v[j], o, upper);
-            }
-        }
-    }
+    // cross-lane half-cleaners, lane distance G/2 ... 1
+    wave_cross_stages<T, K, G / 2>(v, lane);
     // in-lane half-cleaners, distance K/2 ... 1
 #pragma unroll
     for (int d = K / 2; d >= 1; d >>= 1) {
