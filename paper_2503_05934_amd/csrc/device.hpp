@@ -363,12 +363,6 @@ __device__ __forceinline__ uint64_t xor_lane(uint64_t x) {
 }
 
 // ----------------------------------------------------- wavefront merging ---
-// Runs of G lanes (G*K keys, lane-major: key e sits in lane e / K, slot
-// e % K) are merged pairwise into runs of 2G lanes by a bitonic merge:
-//   flip  : key e of the pair meets key (2GK-1-e): lane l meets lane
-//           l ^ (2G-1), slot j meets slot K-1-j; the lower key keeps the min.
-//   clean : distance d = GK/2, ..., 1: key e meets e + d; for d >= K that is
-//           lane l ^ (d/K) in the same slot, below K it is inside the lane.
 // Cross-lane half-cleaner at lane distance M, then the next one down.
 template <typename T, int K, int M>
 __device__ __forceinline__ void wave_cross_stages(T (&v)[K], int lane) {
@@ -387,6 +381,12 @@ __device__ __forceinline__ void wave_cross_stages(T (&v)[K], int lane) {
     }
 }
 
+// Runs of G lanes (G*K keys, lane-major: key e sits in lane e / K, slot
+// e % K) are merged pairwise into runs of 2G lanes by a bitonic merge:
+//   flip  : key e of the pair meets key (2GK-1-e): lane l meets lane
+//           l ^ (2G-1), slot j meets slot K-1-j; the lower key keeps the min.
+//   clean : distance d = GK/2, ..., 1: key e meets e + d; for d >= K that is
+//           lane l ^ (d/K) in the same slot, below K it is inside the lane.
 template <typename T, int K, int G>
 __device__ __forceinline__ void wave_merge_level(T (&v)[K], int lane) {
     {
@@ -468,13 +468,12 @@ __device__ __forceinline__ int corank_lds(const T* s, int a0, int la, int b0, in
 
 // corank_lds with PlainLess for two runs of L keys each (L a power of two)
 // laid out so that LDS words [a0, b0 + L) all belong to the pair: A at a0, B
-// at b0 >= a0 + L.  Binary
-// lifting with the steps L, L/2, ..., 1, the same for every lane: m is the
-// last position of A known to go before B[d-1-m]; a step is taken when its
-// new last position is still inside A's share of the diagonal and goes
-// first.  A probe beyond that share stays inside the pair's words (at most L
-// past the share on either side) and its result is discarded.  Nine VALU
-// instructions per step and no exit test.
+// at b0 >= a0 + L.  Binary lifting with the steps L, L/2, ..., 1, the same
+// for every lane: m is the last position of A known to go before
+// B[d-1-m]; a step is taken when its new last position is still inside A's
+// share of the diagonal and goes first.  A probe beyond that share stays
+// inside the pair's words (at most L past the share on either side) and its
+// result is discarded.  Nine VALU instructions per step and no exit test.
 template <typename T>
 __device__ __forceinline__ int corank_pow2(const T* s, int a0, int b0, int L, int d) {
     const int lo = d > L ? d - L : 0;
