@@ -9,8 +9,9 @@
 // the lists of round r + 1:
 //   partition list:
 //     partition item (longer than one block-sort tile): cut into claim
-//       tiles, one workgroup each: 8192-key chunks in sorts of at most
-//       kQOnePassMax keys, 65,536-key super-tiles in larger ones.  A tile
+//       tiles, one workgroup each: 8192-key chunks once the round's items
+//       are down to about kQOnePassMax keys, 65,536-key super-tiles in the
+//       rounds before (the host picks the size per round).  A tile
 //       counts its keys below and above the item's pivot, claims room for
 //       them with one 64-bit atomic on the item (smaller keys fill the
 //       subarray from its left end, larger keys from its right end),
@@ -32,9 +33,11 @@
 //       merge-sorts it through global memory.
 // Partitions alternate between the workspace and the output array, both at
 // the item's own positions, so finished subarrays are never moved again.
-// Large sorts claim per super-tile rather than per chunk: the claims queue
-// behind each other, and the first round of a 2^28-key array would otherwise
-// make 65,536 of them on one address.  No launch reads
+// The early rounds of large sorts claim per super-tile rather than per
+// chunk: the claims queue behind each other on their item, and the first
+// round of a 2^28-key array would otherwise make 65,536 of them on one
+// address.  Once the items are short enough to be many, claims spread over
+// their addresses and each chunk is read once.  No launch reads
 // anything on the host.  Integer keys only: the partition is not stable, and
 // float keys that compare equal (-0 and +0, NaNs) must keep their input
 // order.
@@ -71,11 +74,13 @@ constexpr int kQKeysPerThread = 16;
 constexpr int kQChunk = kQKeysPerThread * kBlockThreads;  // 8192 keys per pass step
 constexpr int kQChunks = 8;
 constexpr int kQSuper = kQChunk * kQChunks;  // keys per claim of a large sort: 65,536
-// Sorts of at most this many keys claim room per 8192-key chunk and read
-// their keys once; larger ones per super-tile, counting and scattering in
-// two reads.  Claims are device-scope atomics that queue behind each other:
-// a round of a 2^28-key sort in chunks makes 65,536 of them (claims and
-// completions), about 3 ms, against about 0.6 ms of traffic.
+// Rounds whose items hold about this many keys or fewer (n / 2^round, for
+// median-of-three splits) claim room per 8192-key chunk and read their keys
+// once; earlier rounds claim per super-tile, counting and scattering in two
+// reads.  Claims are device-scope atomics that queue behind each other on
+// their item: the first round of a 2^28-key sort in chunks makes 65,536 of
+// them (claims and completions) on one item, about 3 ms, against about
+// 0.6 ms of traffic.
 constexpr int64_t kQOnePassMax = 1ll << 23;
 
 __device__ __forceinline__ QItem* q_items(QList* l) { return reinterpret_cast<QItem*>(l + 1); }
@@ -206,15 +211,15 @@ struct QPartRound {
     uint32_t cap;         // items per list
     uint32_t leaf_max;    // longest leaf item
     int final_next;       // the next round is the last: long children become big items
-    uint32_t claim_keys;  // keys per claim tile: kQChunk or kQSuper
+    uint32_t next_claim_keys;  // keys per claim tile of the next round: kQChunk or kQSuper
 };
 
 // Appends one side of a finished partition to the list its length calls for.
 __device__ __forceinline__ void q_child(const QPartRound& r, uint32_t start, uint32_t len) {
     if (len == 0) return;
-    if (len <= r.leaf_max) q_append(r.lout_l, r.cap, start, len, kQLeaf, 0u, r.claim_keys);
-    else if (r.final_next) q_append(r.lout_l, r.cap, start, len, kQBig, 0u, r.claim_keys);
-    else q_append(r.lout_p, r.cap, start, len, kQPart, 0u, r.claim_keys);
+    if (len <= r.leaf_max) q_append(r.lout_l, r.cap, start, len, kQLeaf, 0u, r.next_claim_keys);
+    else if (r.final_next) q_append(r.lout_l, r.cap, start, len, kQBig, 0u, r.next_claim_keys);
+    else q_append(r.lout_p, r.cap, start, len, kQPart, 0u, r.next_claim_keys);
 }
 
 // One claim tile of partition item `it` (index sub of its claim tiles of CK
@@ -350,7 +355,7 @@ __device__ void q_partition(const QPartRound& r, QItem* itp, const QItem& it, ui
             q_child(r, it.start + it.len - ng, ng);
             if (ne)
                 q_append(r.lout_p, r.cap, it.start + nl, ne, kQFill, unord_key<DT>(p),
-                         r.claim_keys);
+                         r.next_claim_keys);
         }
     }
 }
@@ -520,26 +525,33 @@ int q_grid(Kern kern, size_t lds, int* out) {
     return resident_grid(reinterpret_cast<const void*>(kern), kBlockThreads, lds, out);
 }
 
+// Claim size of round r: chunks throughout for sorts of at most kQOnePassMax
+// keys; in larger ones super-tiles while the round's items (about n / 2^r
+// keys each) are longer than that, and in the first two rounds, whose one or
+// two items would queue too many chunk claims each.
+int q_claim_keys(int64_t n, int r) {
+    if (n <= kQOnePassMax) return kQChunk;
+    return r < 2 || (r < 32 && (n >> r) > kQOnePassMax) ? kQSuper : kQChunk;
+}
+
 template <int DT, int K, int NETS>
 int q_run(const QuickArgs& a) {
     constexpr uint32_t kLeafMax = TileTraits<DT, K, false>::kTile;
-    const bool one_pass = a.n <= kQOnePassMax;
-    const int ck = one_pass ? kQChunk : kQSuper;
     auto lkern = &k_qs_leaf<DT, K, NETS>;
-    auto rkern = one_pass ? &k_qs_round<DT, K, NETS, kQChunk> : &k_qs_round<DT, K, NETS, kQSuper>;
+    auto rchunk = &k_qs_round<DT, K, NETS, kQChunk>;
+    auto rsuper = &k_qs_round<DT, K, NETS, kQSuper>;
+    const bool any_super = a.n > kQOnePassMax;
     const size_t llds = q_leaf_lds<DT, K, NETS>();
     const size_t rlds = std::max(llds, (size_t)kQPartWords * 4);
     if (int rc = set_dynamic_lds(reinterpret_cast<const void*>(lkern), llds)) return rc;
-    if (int rc = set_dynamic_lds(reinterpret_cast<const void*>(rkern), rlds)) return rc;
-    int lgrid = 0, rgrid = 0;
+    if (int rc = set_dynamic_lds(reinterpret_cast<const void*>(rchunk), rlds)) return rc;
+    if (any_super)
+        if (int rc = set_dynamic_lds(reinterpret_cast<const void*>(rsuper), rlds)) return rc;
+    int lgrid = 0, cgrid = 0, sgrid = 0;
     if (int rc = q_grid(lkern, llds, &lgrid)) return rc;
-    if (int rc = q_grid(rkern, rlds, &rgrid)) return rc;
-    // a round's launch: partition workgroups for the most claim tiles a
-    // round can hold (its items are longer than a leaf, so fewer than
-    // 2 n / ck tiles), capped at a resident grid, then a resident grid's
-    // worth for the leaves
-    const uint32_t rpart =
-        (uint32_t)std::min<int64_t>(std::max<int64_t>(1, (2 * a.n + ck - 1) / ck), rgrid);
+    if (int rc = q_grid(rchunk, rlds, &cgrid)) return rc;
+    if (any_super)
+        if (int rc = q_grid(rsuper, rlds, &sgrid)) return rc;
 
     const int rounds =
         a.n <= kLeafMax ? 1 : a.rounds > 0 ? a.rounds : quick_rounds(a.n, kLeafMax);
@@ -547,7 +559,6 @@ int q_run(const QuickArgs& a) {
     uint32_t* wk = reinterpret_cast<uint32_t*>(ws);
     uint8_t* lb = ws + align_up((size_t)a.n * 4, 256);
     const size_t lbytes = q_list_bytes(a.n);
-    const uint32_t claim_keys = (uint32_t)ck;
     QList* P[3];
     QList* L[3];
     for (int i = 0; i < 3; ++i) {
@@ -558,7 +569,7 @@ int q_run(const QuickArgs& a) {
         LaunchTimer timer("qs_init", 1, a.stream);
         hipLaunchKernelGGL(k_qs_init, dim3(1), dim3(64), 0, a.stream, P[0], P[1], P[2], L[0],
                            L[1], L[2], (uint32_t)a.n, kLeafMax, rounds == 1 ? 1 : 0,
-                           claim_keys);
+                           (uint32_t)q_claim_keys(a.n, 0));
     }
     if (int rc = (int)hipGetLastError()) return rc;
     const QRoundKinds& kinds = q_kinds();
@@ -566,6 +577,7 @@ int q_run(const QuickArgs& a) {
     for (int r = 0; r < rounds; ++r) {
         const uint32_t* cur = r == 0 ? a.kin : (r & 1) ? wk : a.kout;
         if (rounds > 1) {
+            const int ck = q_claim_keys(a.n, r);
             QPartRound q;
             q.cur = cur;
             q.other = (r & 1) ? a.kout : wk;
@@ -578,12 +590,23 @@ int q_run(const QuickArgs& a) {
             q.cap = cap;
             q.leaf_max = kLeafMax;
             q.final_next = r + 2 == rounds ? 1 : 0;
-            q.claim_keys = claim_keys;
-            // the round's partitions and leaves in one launch
+            q.next_claim_keys = (uint32_t)q_claim_keys(a.n, r + 1);
+            // the round's partitions and leaves in one launch: partition
+            // workgroups for the most claim tiles the round can hold (its
+            // items are longer than a leaf, so fewer than 2 n / ck tiles),
+            // capped at a resident grid, then a resident grid's worth for the
+            // leaves
+            const int rgrid = ck == kQChunk ? cgrid : sgrid;
+            const uint32_t rpart =
+                (uint32_t)std::min<int64_t>(std::max<int64_t>(1, (2 * a.n + ck - 1) / ck), rgrid);
             QLeafRound ql{cur, a.kout, wk, L[r % 3], cap, a.set_mask};
             LaunchTimer timer(kinds.round[r], a.n, a.stream);
-            hipLaunchKernelGGL(rkern, dim3(rpart + (uint32_t)rgrid), dim3(kBlockThreads), rlds,
-                               a.stream, q, ql, rpart);
+            if (ck == kQChunk)
+                hipLaunchKernelGGL(rchunk, dim3(rpart + (uint32_t)rgrid), dim3(kBlockThreads), rlds,
+                                   a.stream, q, ql, rpart);
+            else
+                hipLaunchKernelGGL(rsuper, dim3(rpart + (uint32_t)rgrid), dim3(kBlockThreads), rlds,
+                                   a.stream, q, ql, rpart);
             if (int rc = (int)hipGetLastError()) return rc;
             continue;
         }
