@@ -10,8 +10,9 @@
 //   partition list:
 //     partition item (longer than one block-sort tile): cut into claim
 //       tiles, one workgroup each: 8192-key chunks once the round's items
-//       are down to about kQOnePassMax keys, 65,536-key super-tiles in the
-//       rounds before (the host picks the size per round).  A tile
+//       are down to about a quarter of kQOnePassMax keys, 65,536-key
+//       super-tiles in the rounds before (the host picks the size per
+//       round).  A tile
 //       counts its keys below and above the item's pivot, claims room for
 //       them with one 64-bit atomic on the item (smaller keys fill the
 //       subarray from its left end, larger keys from its right end),
@@ -74,8 +75,9 @@ constexpr int kQKeysPerThread = 16;
 constexpr int kQChunk = kQKeysPerThread * kBlockThreads;  // 8192 keys per pass step
 constexpr int kQChunks = 8;
 constexpr int kQSuper = kQChunk * kQChunks;  // keys per claim of a large sort: 65,536
-// Rounds whose items hold about this many keys or fewer (n / 2^round, for
-// median-of-three splits) claim room per 8192-key chunk and read their keys
+// Sorts of at most this many keys, and the rounds of larger ones whose items
+// hold about a quarter as many keys or fewer (n / 2^round, for
+// median-of-three splits), claim room per 8192-key chunk and read their keys
 // once; earlier rounds claim per super-tile, counting and scattering in two
 // reads.  Claims are device-scope atomics that queue behind each other on
 // their item: the first round of a 2^28-key sort in chunks makes 65,536 of
@@ -527,11 +529,13 @@ int q_grid(Kern kern, size_t lds, int* out) {
 
 // Claim size of round r: chunks throughout for sorts of at most kQOnePassMax
 // keys; in larger ones super-tiles while the round's items (about n / 2^r
-// keys each) are longer than that, and in the first two rounds, whose one or
-// two items would queue too many chunk claims each.
+// keys each) are longer than a quarter of that, and in the first two rounds,
+// whose one or two items would queue too many chunk claims each.  (Chunks
+// from items of about kQOnePassMax or half of it: 2^28 keys 14.3-14.5 and
+// 13.8-14.2 ms against 13.6 ms.)
 int q_claim_keys(int64_t n, int r) {
     if (n <= kQOnePassMax) return kQChunk;
-    return r < 2 || (r < 32 && (n >> r) > kQOnePassMax) ? kQSuper : kQChunk;
+    return r < 2 || (r < 32 && (n >> r) > kQOnePassMax / 4) ? kQSuper : kQChunk;
 }
 
 template <int DT, int K, int NETS>
