@@ -282,19 +282,30 @@ __device__ void q_partition(const QPartRound& r, QItem* itp, const QItem& it, ui
         }
         __syncthreads();  // the LDS and the scan words are reused
     } else {
-        // a super-tile per claim: count, claim, then read again and scatter
+        // a super-tile per claim: count, claim, then read again and scatter;
+        // the first two chunks, the ones longest out of the caches by the
+        // scatter, stay in registers from the count to the scatter
+        const int nch = (ns + kQChunk - 1) / kQChunk;
         // pass 1: count
         uint32_t cl = 0, cg = 0;
-        for (int c0 = 0; c0 < ns; c0 += kQChunk) {
+        uint32_t x0[kQKeysPerThread], x1[kQKeysPerThread];  // chunks 0 and 1
+        for (int c = 0; c < nch; ++c) {
             uint32_t x[kQKeysPerThread];
-            const int nv = min(kQChunk, ns - c0);
-            q_load(src + s0 + c0, first, nv, x);
+            const int nv = min(kQChunk, ns - c * kQChunk);
+            q_load(src + s0 + c * kQChunk, first, nv, x);
 #pragma unroll
             for (int j = 0; j < kQKeysPerThread; ++j) {
                 const bool live = first + j < nv;
                 const uint32_t o = ord_key<DT>(x[j]);
                 cl += (live && o < p) ? 1u : 0u;
                 cg += (live && o > p) ? 1u : 0u;
+            }
+            if (c == 0) {
+#pragma unroll
+                for (int j = 0; j < kQKeysPerThread; ++j) x0[j] = x[j];
+            } else if (c == 1) {
+#pragma unroll
+                for (int j = 0; j < kQKeysPerThread; ++j) x1[j] = x[j];
             }
         }
         q_sum2(cl, cg, sw);
@@ -305,11 +316,9 @@ __device__ void q_partition(const QPartRound& r, QItem* itp, const QItem& it, ui
         uint32_t run_l = (uint32_t)s_base;           // smaller keys placed before this chunk
         uint32_t run_g = (uint32_t)(s_base >> 32);   // larger keys placed after it
 
-        // pass 2: the same keys again (mostly from the caches), compacted and written
-        for (int c0 = 0; c0 < ns; c0 += kQChunk) {
-            uint32_t x[kQKeysPerThread];
-            const int nv = min(kQChunk, ns - c0);
-            q_load(src + s0 + c0, first, nv, x);
+        // pass 2: compact and write each chunk; the two held chunks, then the
+        // others read again
+        auto scatter = [&](const uint32_t (&x)[kQKeysPerThread], int nv) {
             uint32_t l = 0, g = 0;
 #pragma unroll
             for (int j = 0; j < kQKeysPerThread; ++j) {
@@ -342,6 +351,14 @@ __device__ void q_partition(const QPartRound& r, QItem* itp, const QItem& it, ui
             run_l += TL;
             run_g += TG;
             __syncthreads();  // the LDS and the scan words are reused
+        };
+        scatter(x0, min(kQChunk, ns));
+        if (nch >= 2) scatter(x1, min(kQChunk, ns - kQChunk));
+        for (int c = 2; c < nch; ++c) {
+            uint32_t x[kQKeysPerThread];
+            const int nv = min(kQChunk, ns - c * kQChunk);
+            q_load(src + s0 + c * kQChunk, first, nv, x);
+            scatter(x, nv);
         }
     }
     if (tid == 0) {
