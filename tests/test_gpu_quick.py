@@ -58,9 +58,11 @@ def test_quick_tricky_inputs(orc, n):
 
 @pytest.mark.parametrize("n", [1 << 23, (1 << 23) + 4097])
 def test_quick_claim_sizes(orc, n):
-    # sorts of at most 2^23 keys claim room per 8192-key chunk, larger ones
-    # per 65,536-key super-tile: both sides of the switch, on random keys and
-    # on few distinct values (long runs of keys equal to the pivot)
+    # sorts of at most 2^23 keys claim room per 8192-key chunk throughout;
+    # larger ones per 65,536-key super-tile in their first rounds (the first
+    # two, and while subarrays are longer than 2^21 keys) and per chunk after,
+    # so the larger size here runs both kinds of round: on random keys and on
+    # few distinct values (long runs of keys equal to the pivot)
     for dist, x in (("random", workloads.keys(n, "random", "u32", seed=n)),
                     ("four values", _tricky(n, seed=3)["four values"]),
                     ("organ pipe", _tricky(n, seed=3)["organ pipe"])):
