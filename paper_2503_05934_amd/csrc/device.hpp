@@ -174,6 +174,62 @@ __device__ __forceinline__ void keep_lanes4(uint64_t (&v)[4], const uint64_t (&o
     v[3] = __builtin_bit_cast(uint64_t, r3);
 }
 
+// The same for eight composites under one pair of masks (groups of eight
+// keys per lane): half the scalar instructions and wait states per key.
+template <int BIT>
+__device__ __forceinline__ void keep_lanes8(uint64_t (&v)[8], const uint64_t (&o)[8]) {
+    static_assert(BIT >= 0 && BIT < 6, "lane bit");
+    constexpr uint64_t kUpper = BIT == 0   ? 0xAAAAAAAAAAAAAAAAull
+                                : BIT == 1 ? 0xCCCCCCCCCCCCCCCCull
+                                : BIT == 2 ? 0xF0F0F0F0F0F0F0F0ull
+                                : BIT == 3 ? 0xFF00FF00FF00FF00ull
+                                : BIT == 4 ? 0xFFFF0000FFFF0000ull
+                                           : 0xFFFFFFFF00000000ull;
+    double r0, r1, r2, r3, r4, r5, r6, r7;
+    uint64_t save;
+    asm("s_mov_b64 %8, exec\n\t"
+        "s_andn2_b64 exec, %8, %25\n\t"
+        "v_min_f64 %0, %9, %17\n\t"
+        "v_min_f64 %1, %10, %18\n\t"
+        "v_min_f64 %2, %11, %19\n\t"
+        "v_min_f64 %3, %12, %20\n\t"
+        "v_min_f64 %4, %13, %21\n\t"
+        "v_min_f64 %5, %14, %22\n\t"
+        "v_min_f64 %6, %15, %23\n\t"
+        "v_min_f64 %7, %16, %24\n\t"
+        "s_and_b64 exec, %8, %25\n\t"
+        "v_max_f64 %0, %9, %17\n\t"
+        "v_max_f64 %1, %10, %18\n\t"
+        "v_max_f64 %2, %11, %19\n\t"
+        "v_max_f64 %3, %12, %20\n\t"
+        "v_max_f64 %4, %13, %21\n\t"
+        "v_max_f64 %5, %14, %22\n\t"
+        "v_max_f64 %6, %15, %23\n\t"
+        "v_max_f64 %7, %16, %24\n\t"
+        "s_mov_b64 exec, %8\n\t"
+        "s_nop 1"
+        : "=&v"(r0), "=&v"(r1), "=&v"(r2), "=&v"(r3), "=&v"(r4), "=&v"(r5), "=&v"(r6),
+          "=&v"(r7), "=&s"(save)
+        : "v"(__builtin_bit_cast(double, v[0])), "v"(__builtin_bit_cast(double, v[1])),
+          "v"(__builtin_bit_cast(double, v[2])), "v"(__builtin_bit_cast(double, v[3])),
+          "v"(__builtin_bit_cast(double, v[4])), "v"(__builtin_bit_cast(double, v[5])),
+          "v"(__builtin_bit_cast(double, v[6])), "v"(__builtin_bit_cast(double, v[7])),
+          "v"(__builtin_bit_cast(double, o[0])), "v"(__builtin_bit_cast(double, o[1])),
+          "v"(__builtin_bit_cast(double, o[2])), "v"(__builtin_bit_cast(double, o[3])),
+          "v"(__builtin_bit_cast(double, o[4])), "v"(__builtin_bit_cast(double, o[5])),
+          "v"(__builtin_bit_cast(double, o[6])), "v"(__builtin_bit_cast(double, o[7])),
+          "s"(kUpper)
+        : "scc");
+    v[0] = __builtin_bit_cast(uint64_t, r0);
+    v[1] = __builtin_bit_cast(uint64_t, r1);
+    v[2] = __builtin_bit_cast(uint64_t, r2);
+    v[3] = __builtin_bit_cast(uint64_t, r3);
+    v[4] = __builtin_bit_cast(uint64_t, r4);
+    v[5] = __builtin_bit_cast(uint64_t, r5);
+    v[6] = __builtin_bit_cast(uint64_t, r6);
+    v[7] = __builtin_bit_cast(uint64_t, r7);
+}
+
 // keep() on K keys against their partners o[] for the upper lanes of lane
 // bit BIT (upper: their all-ones mask).
 template <int BIT, int K>
@@ -185,6 +241,21 @@ __device__ __forceinline__ void keep_all(uint32_t (&v)[K], const uint32_t (&o)[K
 template <int BIT, int K>
 __device__ __forceinline__ void keep_all(uint64_t (&v)[K], const uint64_t (&o)[K], uint32_t) {
     static_assert(K % 4 == 0, "groups of four keys");
+    if constexpr (K % 8 == 0) {  // groups of eight
+#pragma unroll
+        for (int g = 0; g < K; g += 8) {
+            uint64_t a[8], b[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                a[j] = v[g + j];
+                b[j] = o[g + j];
+            }
+            keep_lanes8<BIT>(a, b);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[g + j] = a[j];
+        }
+        return;
+    }
 #pragma unroll
     for (int g = 0; g < K; g += 4) {
         uint64_t a[4] = {v[g], v[g + 1], v[g + 2], v[g + 3]};
